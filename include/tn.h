@@ -1,0 +1,184 @@
+/*
+ * tn.h -- C ABI of the MI355X boundary-MPS contraction and sampling library.
+ *
+ * The operations follow Rudolph & Tindall, "Simulating and Sampling from
+ * Quantum Circuits with 2D Tensor Networks":
+ *
+ *   tn_boundary_contract  norm <psi|psi> of a planar tensor-network state by
+ *                         boundary MPSs passed through its rows in reverse
+ *                         order, each MPS-MPO product compressed to bond chi by
+ *                         one-site variational fitting (Methods, "The Boundary
+ *                         Matrix Product State Method"; Appendix, "Sampling
+ *                         from a Tensor Network State", Fig. 7c-d).  The stored
+ *                         boundary set is kept in the handle for sampling.
+ *   tn_environments       one-site density matrices and nearest-neighbour
+ *                         <ZZ> by direct boundary-MPS contraction (Results,
+ *                         Fig. 4, "direct contraction").
+ *   tn_sample             sequential bitstring sampling, row by row and qubit
+ *                         by qubit from one-site reduced density matrices
+ *                         conditioned on the amplitude boundary above and the
+ *                         stored norm boundary below; q(x) is the product of
+ *                         the conditionals and p(x) comes from the last
+ *                         amplitude boundary (Appendix, sampling; Fig. 7d).
+ *
+ * Conventions for every call:
+ *  - Device pointers are HIP device memory on the handle's device; host
+ *    pointers are ordinary host memory.  The caller owns every input and output
+ *    buffer; the library owns only its workspace and the cached boundary set.
+ *  - Work is enqueued on the handle's stream.  Calls that return host scalars
+ *    synchronise that stream; the others are asynchronous.
+ *  - Errors are returned as tn_status; no exception crosses the ABI.  On error
+ *    the outputs are unspecified and tn_last_error() describes the failure.
+ *  - One handle must not be used by two threads at once.
+ *
+ * Site tensor layout: complex, interleaved (re, im), row-major with index order
+ * [p][u][l][d][r] (physical, up, left, down, right).  A bond that is absent or
+ * leaves the grid has dimension 1; a grid position without a qubit is a dummy
+ * site with p = 1.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_handle tn_handle;
+
+typedef enum {
+    TN_OK = 0,
+    TN_ERR_INVALID = 1,     /* null pointer, bad enum, bad option value          */
+    TN_ERR_SHAPE = 2,       /* inconsistent lattice dimensions                   */
+    TN_ERR_OOM = 3,         /* device allocation failed or workspace cap reached */
+    TN_ERR_HIP = 4,         /* a HIP runtime call failed (incl. no device)       */
+    TN_ERR_NUMERIC = 5,     /* non-finite or non-positive norm or marginal       */
+    TN_ERR_UNSUPPORTED = 6  /* valid request outside what this build implements  */
+} tn_status;
+
+typedef enum { TN_C128 = 0, TN_C64 = 1 } tn_dtype;
+
+/* Arithmetic of the bulk contractions.  QR, norms, renormalisation and the
+ * probability normalisation are FP64 in every mode. */
+typedef enum {
+    TN_PREC_FP64 = 0,    /* complex128 storage, FP64 MFMA                           */
+    TN_PREC_FP32 = 1,    /* complex64 storage, FP32 MFMA                            */
+    TN_PREC_BF16X3 = 2,  /* complex64 storage, each FP32 operand split into two BF16
+                            parts (hi + lo), three BF16 MFMA products, FP32 accumulate */
+    TN_PREC_BF16X6 = 3   /* as BF16X3 with three parts and six products             */
+} tn_prec;
+
+/* A planar tensor-network state embedded in a rows x cols grid; partitions are
+ * the rows (Methods: partitions forming a line). */
+typedef struct {
+    int32_t rows, cols;
+    const int32_t *phys;        /* host [rows*cols]: 2 for a qubit, 1 for a dummy        */
+    const int32_t *dim_h;       /* host [rows*(cols-1)]: bond (r,c)-(r,c+1), >= 1        */
+    const int32_t *dim_v;       /* host [(rows-1)*cols]: bond (r,c)-(r+1,c), >= 1        */
+    const int32_t *site_index;  /* host [rows*cols]: bit position of the qubit, -1 dummy */
+    tn_dtype dtype;             /* element type of every site tensor                     */
+    const void *const *site;    /* host array [rows*cols] of DEVICE pointers, layout above */
+} tn_peps;
+
+typedef struct {
+    int32_t chi;          /* max bond of the norm boundary MPS (paper: R_n)            */
+    int32_t chi_x;        /* max bond of the sampler's amplitude boundary (paper: R_x)  */
+    int32_t sweeps;       /* full one-site fit sweeps per MPS-MPO product (>= 1)        */
+    int32_t direction;    /* norm only: 0 bottom-up (rows last to first), 1 top-down,
+                             2 / 3 the same over columns.  Environments and sampling
+                             use rows, bottom-up boundaries (paper's order).           */
+    int32_t init;         /* 0: exact product + QR canonicalisation when chi reaches the
+                             exact bound, else fit from a random guess; 1: always fit    */
+    tn_prec prec;
+    uint64_t init_seed;   /* Philox key of the random initial guesses                  */
+    size_t workspace_cap; /* bytes of device workspace the library may hold; 0 = no cap */
+} tn_opts;
+
+/* Fills opts with defaults: chi = chi_x = 16, sweeps = 2, direction 0, init 0,
+ * FP64, seed 0, no cap. */
+void tn_default_opts(tn_opts *opts);
+
+/* Creates a handle bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t, NULL = the null stream).  TN_ERR_HIP if the device is absent. */
+tn_status tn_create(tn_handle **h, int device, void *hip_stream);
+
+/* Frees the handle, its workspace and cached boundary set (synchronises). */
+tn_status tn_destroy(tn_handle *h);
+
+/* Norm Z = <psi|psi> by boundary MPS (see top of file).  Writes log|Z| and
+ * arg Z to host doubles.  Caches the bottom-up boundary set when direction is 0.
+ * Synchronises the stream. */
+tn_status tn_boundary_contract(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
+                               double *log_abs_Z, double *arg_Z);
+
+/* One-site density matrices and nearest-neighbour <ZZ> from the boundary MPSs
+ * above and below every row (two-row environments for vertical pairs).
+ *   rho1 : device [rows*cols][2][2] complex128 (8 doubles per site), rho / Tr rho,
+ *          NaN for dummy sites;
+ *   zz_h : optional (NULL) device [rows*(cols-1)] doubles, <Z Z> of (r,c),(r,c+1),
+ *          NaN if either site is a dummy;
+ *   zz_v : optional (NULL) device [(rows-1)*cols] doubles, same for (r,c),(r+1,c);
+ *   p2_h, p2_v : optional (NULL) device [bonds][4]: diagonal of the normalised
+ *          two-site marginal in the order 00, 01, 10, 11.
+ * Horizontal (vertical) pairs are contracted only if zz_h or p2_h (zz_v or p2_v)
+ * is given.  Synchronises the stream. */
+tn_status tn_environments(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
+                          double *rho1, double *zz_h, double *zz_v,
+                          double *p2_h, double *p2_v);
+
+/* Draws samples first_sample .. first_sample+n-1 (paper's sampler).
+ *   uniforms : optional device [n][N] doubles in [0,1) (N = number of qubits):
+ *              the uniform that draws qubit q of sample i; NULL = Philox4x64-10
+ *              with key (seed, 3) and counter (q, first_sample+i, 0, 0), the
+ *              uniform being (word0 >> 11) * 2^-53;
+ *   bits     : device [n][N] uint8, bit of qubit q at position site_index;
+ *   log_q    : device [n] doubles, log of the product of drawn conditionals;
+ *   log_p    : optional device [n] doubles, 2 log|<x|psi>| from the last
+ *              amplitude boundary (accurate only when chi_x is large).
+ * Computes (and caches) the norm boundary set if the cached one does not match
+ * the state and options.  A sample is a function of (state, options, seed,
+ * sample index) only, so split runs reproduce one run.
+ * Synchronises the stream (marginal checks). */
+tn_status tn_sample(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
+                    uint64_t seed, uint64_t first_sample, int64_t n,
+                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
+
+/* Text of the last error on this handle ("" if none).  Valid until the next call. */
+const char *tn_last_error(const tn_handle *h);
+
+/* Work counters of the last call: the algorithmic flops of every contraction
+ * issued (8 real flops per complex multiply-add, summed over the actual index
+ * dimensions), their count, and -- when timing is enabled -- the summed device
+ * time of the contraction and of the QR kernels in milliseconds (HIP events on
+ * the handle's stream).  Any pointer may be NULL. */
+tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
+                          double *gemm_ms, double *qr_ms, int64_t *qr_launches);
+
+/* Enables (1) or disables (0) per-kernel HIP-event timing (adds host syncs). */
+tn_status tn_set_timing(tn_handle *h, int enable);
+
+/* ---------------------------------------------------------------------------
+ * Kernel test hooks: run one engine primitive on caller buffers so that its
+ * numerics can be checked in isolation.  Not needed by applications.
+ *
+ * tn_test_contract: C[ic] (+)= sum A[ia] * B[ib] (einsum letters, one char per
+ *   index, row-major dense DEVICE tensors of the precision's storage type:
+ *   complex128 for FP64, complex64 otherwise); dims are host arrays of
+ *   strlen(letters) entries; conjA/conjB conjugate an operand; accumulate adds.
+ *   Enqueued on the handle's stream.
+ * tn_test_qr: reduced Householder QR (FP64 arithmetic) of `batch` row-major
+ *   m x n DEVICE matrices of element size esz (16 or 8 bytes): Q is m x k,
+ *   R is k x n, k = min(m, n).  Enqueued on the handle's stream.
+ */
+tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims,
+                           int conjA, const char *ib, const void *B, const int32_t *bdims, int conjB,
+                           const char *ic, void *C, const int32_t *cdims, int accumulate);
+tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

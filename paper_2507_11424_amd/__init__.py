@@ -1,0 +1,247 @@
+"""MI355X-native boundary-MPS contraction and sampling of 2D tensor-network states.
+
+Thin Python binding of the C ABI in ``include/tn.h`` (``libtnbmps.so``, built
+in this directory by ``build_lib.py``).  This module only marshals arguments:
+PyTorch supplies device memory and the HIP stream, and every step of the
+computation runs in the library's HIP kernels.  There is no CPU fallback: if
+the library or a GPU is missing, the calls raise.
+
+Operations (Rudolph & Tindall, "Simulating and Sampling from Quantum Circuits
+with 2D Tensor Networks"):
+
+* ``boundary_contract`` -- norm <psi|psi> by boundary MPSs and the one-site fit;
+* ``environments``      -- one-site density matrices and nearest-neighbour <ZZ>;
+* ``sample``            -- sequential bitstring sampling with q(x) and p(x).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnbmps.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4: "TN_ERR_HIP",
+          5: "TN_ERR_NUMERIC", 6: "TN_ERR_UNSUPPORTED"}
+
+# every symbol declared in include/tn.h
+EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
+           "tn_sample", "tn_last_error", "tn_get_counters", "tn_set_timing", "tn_test_contract", "tn_test_qr"]
+
+
+class TnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class c_peps(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("phys", ctypes.POINTER(ctypes.c_int32)), ("dim_h", ctypes.POINTER(ctypes.c_int32)),
+                ("dim_v", ctypes.POINTER(ctypes.c_int32)), ("site_index", ctypes.POINTER(ctypes.c_int32)),
+                ("dtype", ctypes.c_int), ("site", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("chi", ctypes.c_int32), ("chi_x", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("init", ctypes.c_int32), ("prec", ctypes.c_int),
+                ("init_seed", ctypes.c_uint64), ("workspace_cap", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def lib(path: Optional[str] = None):
+    """Loads the C-ABI library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} not found: build it with `python -m paper_2507_11424_amd.build_lib`")
+    L = ctypes.CDLL(p)
+    vp, i32, i64, u64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)
+    L.tn_default_opts.argtypes = [ctypes.POINTER(c_opts)]
+    L.tn_default_opts.restype = None
+    L.tn_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    L.tn_destroy.argtypes = [vp]
+    L.tn_boundary_contract.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), dp, dp]
+    L.tn_environments.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), vp, vp, vp, vp, vp]
+    L.tn_sample.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, u64, i64, vp, vp, vp, vp]
+    L.tn_last_error.argtypes = [vp]
+    L.tn_last_error.restype = ctypes.c_char_p
+    L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64)]
+    L.tn_set_timing.argtypes = [vp, ctypes.c_int]
+    L.tn_test_contract.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
+                                   ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
+                                   ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int]
+    L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
+              "tn_get_counters", "tn_set_timing", "tn_test_contract", "tn_test_qr"):
+        getattr(L, f).restype = ctypes.c_int
+    if path is None:
+        _lib = L
+    return L
+
+
+def _i32(a) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+    return (ctypes.c_int32 * max(len(a), 1))(*a.tolist())
+
+
+def make_opts(chi=16, chi_x=None, sweeps=2, direction=0, force_fit=False, prec="fp64", init_seed=0,
+              workspace_cap=0) -> c_opts:
+    o = c_opts()
+    lib().tn_default_opts(ctypes.byref(o))
+    o.chi = int(chi)
+    o.chi_x = int(chi if chi_x is None else chi_x)
+    o.sweeps = int(sweeps)
+    o.direction = int(direction)
+    o.init = 1 if force_fit else 0
+    o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    o.init_seed = int(init_seed)
+    o.workspace_cap = int(workspace_cap)
+    return o
+
+
+class Peps:
+    """A PEPS on the device: lattice arrays (host) + one device tensor per site,
+    index order [p][u][l][d][r], complex128 or complex64 torch tensors."""
+
+    def __init__(self, lattice, site_tensors: Sequence):
+        import torch
+        self.lattice = lattice
+        self.tensors = list(site_tensors)  # keeps the device memory alive
+        dt = self.tensors[0].dtype
+        if dt not in (torch.complex128, torch.complex64):
+            raise TypeError("site tensors must be complex128 or complex64")
+        if any(t.dtype != dt for t in self.tensors):
+            raise TypeError("all site tensors must share one dtype")
+        self.dtype = dt
+        self._phys = _i32(lattice.phys)
+        self._dh = _i32(lattice.dim_h)
+        self._dv = _i32(lattice.dim_v)
+        self._si = _i32(lattice.site_index)
+        n = lattice.rows * lattice.cols
+        if len(self.tensors) != n:
+            raise ValueError("one tensor per grid position expected")
+        self._ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.tensors])
+        self.c = c_peps(lattice.rows, lattice.cols, self._phys, self._dh, self._dv, self._si,
+                        0 if dt == torch.complex128 else 1, self._ptrs)
+
+    @property
+    def n_qubits(self) -> int:
+        return int(self.lattice.n_qubits)
+
+    @staticmethod
+    def from_numpy(lattice, tensors, dtype="c128", device="cuda"):
+        """Copies host arrays ([rows][cols] nested list or flat list) to the device."""
+        import torch
+        flat = [t for row in tensors for t in row] if isinstance(tensors[0], (list, tuple)) else list(tensors)
+        td = torch.complex128 if dtype == "c128" else torch.complex64
+        dev = [torch.from_numpy(np.ascontiguousarray(t)).to(device=device, dtype=td) for t in flat]
+        return Peps(lattice, dev)
+
+
+class Handle:
+    """Library handle bound to a device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library needs an MI355X")
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib().tn_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise TnError(st, "tn_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise TnError(st, lib().tn_last_error(self.h).decode())
+
+    # ---------------------------------------------------------------- operations
+    def boundary_contract(self, peps: Peps, opts: c_opts):
+        la, ar = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().tn_boundary_contract(self.h, ctypes.byref(peps.c), ctypes.byref(opts),
+                                               ctypes.byref(la), ctypes.byref(ar)))
+        return la.value, ar.value
+
+    def environments(self, peps: Peps, opts: c_opts, want_zz: bool = True, want_p2: bool = True):
+        import torch
+        L = peps.lattice
+        dev = peps.tensors[0].device
+        f64 = dict(dtype=torch.float64, device=dev)
+        rho = torch.empty((L.rows * L.cols, 2, 2, 2), **f64)
+        zzh = torch.empty((L.rows, max(L.cols - 1, 0)), **f64) if want_zz else None
+        zzv = torch.empty((max(L.rows - 1, 0), L.cols), **f64) if want_zz else None
+        p2h = torch.empty((L.rows, max(L.cols - 1, 0), 4), **f64) if want_p2 else None
+        p2v = torch.empty((max(L.rows - 1, 0), L.cols, 4), **f64) if want_p2 else None
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None  # noqa: E731
+        self._check(lib().tn_environments(self.h, ctypes.byref(peps.c), ctypes.byref(opts), ptr(rho), ptr(zzh),
+                                          ptr(zzv), ptr(p2h), ptr(p2v)))
+        rho1 = torch.view_as_complex(rho).reshape(L.rows, L.cols, 2, 2)
+        return dict(rho1=rho1, zz_h=zzh, zz_v=zzv, p2_h=p2h, p2_v=p2v)
+
+    def sample(self, peps: Peps, opts: c_opts, n: int, seed: int = 0, first: int = 0, uniforms=None,
+               want_logp: bool = True):
+        import torch
+        dev = peps.tensors[0].device
+        nq = peps.n_qubits
+        bits = torch.empty((n, nq), dtype=torch.uint8, device=dev)
+        lq = torch.empty((n,), dtype=torch.float64, device=dev)
+        lp = torch.empty((n,), dtype=torch.float64, device=dev) if want_logp else None
+        if uniforms is not None:
+            uniforms = uniforms.to(device=dev, dtype=torch.float64).contiguous()
+            if tuple(uniforms.shape) != (n, nq):
+                raise ValueError("uniforms must have shape [n][N]")
+        up = ctypes.c_void_p(uniforms.data_ptr()) if uniforms is not None else None
+        self._check(lib().tn_sample(self.h, ctypes.byref(peps.c), ctypes.byref(opts), seed, first, n, up,
+                                    ctypes.c_void_p(bits.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
+                                    ctypes.c_void_p(lp.data_ptr()) if lp is not None else None))
+        return bits, lq, lp
+
+    def counters(self):
+        f, ms, qms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n, qn = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().tn_get_counters(self.h, ctypes.byref(f), ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(qms), ctypes.byref(qn)))
+        return dict(gemm_flops=f.value, gemm_launches=n.value, gemm_ms=ms.value, qr_ms=qms.value,
+                    qr_launches=qn.value)
+
+    def set_timing(self, on: bool):
+        self._check(lib().tn_set_timing(self.h, 1 if on else 0))
+
+    # ---------------------------------------------------------------- test hooks
+    def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
+                      accumulate=False):
+        self._check(lib().tn_test_contract(self.h, PREC[prec], ia.encode(), ctypes.c_void_p(A.data_ptr()),
+                                           _i32(A.shape), int(conjA), ib.encode(), ctypes.c_void_p(B.data_ptr()),
+                                           _i32(B.shape), int(conjB), ic.encode(), ctypes.c_void_p(C.data_ptr()),
+                                           _i32(C.shape), int(accumulate)))
+
+    def test_qr(self, A, Q, R):
+        m, n = A.shape[-2], A.shape[-1]
+        batch = int(np.prod(A.shape[:-2])) if A.dim() > 2 else 1
+        esz = 16 if A.element_size() == 16 else 8
+        self._check(lib().tn_test_qr(self.h, m, n, batch, esz, ctypes.c_void_p(A.data_ptr()),
+                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(R.data_ptr())))

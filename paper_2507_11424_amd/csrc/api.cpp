@@ -1,0 +1,341 @@
+// C ABI of the library (declared in include/tn.h): validation, staging of the
+// site tensors into the compute precision, the cached norm boundary set, and
+// error reporting.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/tn.h"
+#include "tn_core.hpp"
+
+using namespace tnb;
+
+struct tn_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Engine> E;
+    std::string err;
+    size_t cap = 0;
+    // cached bottom-up boundary set of the last state
+    BoundarySet cache;
+    std::string cache_key;
+    PepsDev cache_peps;
+};
+
+namespace {
+
+std::string peps_key(const tn_peps *p, const tn_opts *o) {
+    std::string k;
+    auto add = [&](const void *d, size_t n) { k.append(reinterpret_cast<const char *>(d), n); };
+    add(&p->rows, 4); add(&p->cols, 4); add(&p->dtype, sizeof(p->dtype));
+    const int n = p->rows * p->cols;
+    add(p->phys, (size_t)n * 4);
+    if (p->cols > 1) add(p->dim_h, (size_t)p->rows * (p->cols - 1) * 4);
+    if (p->rows > 1) add(p->dim_v, (size_t)(p->rows - 1) * p->cols * 4);
+    add(p->site_index, (size_t)n * 4);
+    add(p->site, (size_t)n * sizeof(void *));
+    add(&o->chi, 4); add(&o->sweeps, 4); add(&o->init, 4); add(&o->prec, sizeof(o->prec));
+    add(&o->init_seed, 8);
+    return k;
+}
+
+void validate(const tn_peps *p, const tn_opts *o) {
+    if (!p || !o) throw TnError(ST_INVALID, "null peps or opts");
+    if (p->rows < 1 || p->cols < 1) throw TnError(ST_SHAPE, "rows and cols must be >= 1");
+    if (!p->phys || !p->site_index || !p->site) throw TnError(ST_INVALID, "null lattice array");
+    if (p->cols > 1 && !p->dim_h) throw TnError(ST_INVALID, "null dim_h");
+    if (p->rows > 1 && !p->dim_v) throw TnError(ST_INVALID, "null dim_v");
+    if (p->dtype != TN_C128 && p->dtype != TN_C64) throw TnError(ST_INVALID, "bad dtype");
+    if (o->chi < 1 || o->chi_x < 1 || o->sweeps < 1) throw TnError(ST_INVALID, "chi, chi_x and sweeps must be >= 1");
+    if (o->direction < 0 || o->direction > 3) throw TnError(ST_INVALID, "direction must be 0..3");
+    if (o->init != 0 && o->init != 1) throw TnError(ST_INVALID, "init must be 0 or 1");
+    if (o->prec < TN_PREC_FP64 || o->prec > TN_PREC_BF16X6) throw TnError(ST_INVALID, "bad precision");
+    const int n = p->rows * p->cols;
+    int nq = 0;
+    std::vector<int> seen(n, 0);
+    for (int i = 0; i < n; ++i) {
+        if (p->phys[i] != 1 && p->phys[i] != 2) throw TnError(ST_SHAPE, "phys must be 1 or 2");
+        if (!p->site[i]) throw TnError(ST_INVALID, "null site tensor pointer");
+        if (p->phys[i] == 2) {
+            const int q = p->site_index[i];
+            if (q < 0 || q >= n || seen[q]) throw TnError(ST_SHAPE, "site_index must be a permutation of the qubits");
+            seen[q] = 1;
+            ++nq;
+        } else if (p->site_index[i] != -1) {
+            throw TnError(ST_SHAPE, "dummy sites must have site_index -1");
+        }
+    }
+    for (int q = 0; q < nq; ++q)
+        if (!seen[q]) throw TnError(ST_SHAPE, "site_index must cover 0..N-1");
+    for (int i = 0; i < p->rows * (p->cols - 1); ++i)
+        if (p->dim_h[i] < 1) throw TnError(ST_SHAPE, "bond dimensions must be >= 1");
+    for (int i = 0; i < (p->rows - 1) * p->cols; ++i)
+        if (p->dim_v[i] < 1) throw TnError(ST_SHAPE, "bond dimensions must be >= 1");
+}
+
+PepsDev stage(Engine &E, const tn_peps *p) {
+    PepsDev P;
+    P.rows = p->rows;
+    P.cols = p->cols;
+    const int n = p->rows * p->cols;
+    P.phys.assign(p->phys, p->phys + n);
+    P.site_index.assign(p->site_index, p->site_index + n);
+    P.nq = 0;
+    for (int i = 0; i < n; ++i) P.nq += p->phys[i] == 2;
+    const int src_esz = p->dtype == TN_C128 ? 16 : 8;
+    for (int r = 0; r < p->rows; ++r)
+        for (int c = 0; c < p->cols; ++c) {
+            const int i = r * p->cols + c;
+            const int u = r > 0 ? p->dim_v[(r - 1) * p->cols + c] : 1;
+            const int d = r + 1 < p->rows ? p->dim_v[r * p->cols + c] : 1;
+            const int l = c > 0 ? p->dim_h[r * (p->cols - 1) + c - 1] : 1;
+            const int rr = c + 1 < p->cols ? p->dim_h[r * (p->cols - 1) + c] : 1;
+            if (p->phys[i] == 1 && (u != 1 || d != 1 || l != 1 || rr != 1))
+                throw TnError(ST_SHAPE, "a dummy site must have only dimension-1 bonds");
+            Ten t = E.make({p->phys[i], u, l, d, rr});
+            TN_HIP(tnk::launch_convert(p->site[i], src_esz, t.p, t.esz, t.numel(), E.s));
+            P.site.push_back(t);
+        }
+    return P;
+}
+
+void unstage(Engine &E, PepsDev &P) {
+    for (auto &t : P.site)
+        if (t.p) E.drop(t);
+    P.site.clear();
+}
+
+tn_status fail(tn_handle *h, const TnError &e) {
+    if (h) h->err = e.what();
+    return (tn_status)e.code;
+}
+
+void begin(tn_handle *h, const tn_opts *o) {
+    if (!h) throw TnError(ST_INVALID, "null handle");
+    h->err.clear();
+    TN_HIP(hipSetDevice(h->device));
+    if (o) h->E->set_prec((int)o->prec);
+    h->E->ctr.reset();
+}
+
+FitOpts fit_opts(const tn_opts *o) {
+    FitOpts f;
+    f.chi = o->chi;
+    f.sweeps = o->sweeps;
+    f.force_fit = o->init == 1;
+    f.seed = o->init_seed;
+    return f;
+}
+
+// Bottom-up boundary set of the state, cached in the handle.
+const BoundarySet &cached_set(tn_handle *h, const tn_peps *p, const tn_opts *o, bool recompute) {
+    const std::string key = peps_key(p, o);
+    if (!recompute && key == h->cache_key && !h->cache.below.empty()) return h->cache;
+    free_set(*h->E, h->cache);
+    unstage(*h->E, h->cache_peps);
+    h->cache_key.clear();
+    h->cache_peps = stage(*h->E, p);
+    LView V = make_view(h->cache_peps, 0);
+    h->cache = boundary_set(*h->E, V, fit_opts(o), 0);
+    h->cache_key = key;
+    return h->cache;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tn_default_opts(tn_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->chi = 16;
+    o->chi_x = 16;
+    o->sweeps = 2;
+    o->direction = 0;
+    o->init = 0;
+    o->prec = TN_PREC_FP64;
+    o->init_seed = 0;
+    o->workspace_cap = 0;
+}
+
+tn_status tn_create(tn_handle **out, int device, void *stream) {
+    if (!out) return TN_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return TN_ERR_HIP;
+    }
+    if (device < 0 || device >= n) return TN_ERR_INVALID;
+    try {
+        auto h = std::make_unique<tn_handle>();
+        h->device = device;
+        h->stream = reinterpret_cast<hipStream_t>(stream);
+        TN_HIP(hipSetDevice(device));
+        h->E = std::make_unique<Engine>(device, h->stream, 0);
+        *out = h.release();
+        return TN_OK;
+    } catch (const TnError &e) {
+        return (tn_status)e.code;
+    } catch (...) {
+        return TN_ERR_HIP;
+    }
+}
+
+tn_status tn_destroy(tn_handle *h) {
+    if (!h) return TN_ERR_INVALID;
+    try {
+        (void)hipSetDevice(h->device);
+        if (h->E) {
+            free_set(*h->E, h->cache);
+            unstage(*h->E, h->cache_peps);
+        }
+        h->E.reset();
+    } catch (...) {
+    }
+    delete h;
+    return TN_OK;
+}
+
+tn_status tn_boundary_contract(tn_handle *h, const tn_peps *p, const tn_opts *o, double *logabs, double *arg) {
+    try {
+        begin(h, o);
+        validate(p, o);
+        if (!logabs || !arg) throw TnError(ST_INVALID, "null output");
+        if (o->direction == 0) {
+            const BoundarySet &S = cached_set(h, p, o, true);
+            LView V = make_view(h->cache_peps, 0);
+            norm_close(*h->E, V, S, logabs, arg);
+        } else {
+            PepsDev P = stage(*h->E, p);
+            LView V = make_view(P, o->direction);
+            BoundarySet S = boundary_set(*h->E, V, fit_opts(o), (o->direction == 1 || o->direction == 3) ? 1 : 0);
+            try {
+                norm_close(*h->E, V, S, logabs, arg);
+            } catch (...) {
+                free_set(*h->E, S);
+                unstage(*h->E, P);
+                throw;
+            }
+            free_set(*h->E, S);
+            unstage(*h->E, P);
+        }
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+tn_status tn_environments(tn_handle *h, const tn_peps *p, const tn_opts *o, double *rho1, double *zz_h,
+                          double *zz_v, double *p2_h, double *p2_v) {
+    try {
+        begin(h, o);
+        validate(p, o);
+        if (!rho1) throw TnError(ST_INVALID, "null rho1");
+        PepsDev P = stage(*h->E, p);
+        try {
+            environments(*h->E, P, fit_opts(o), rho1, zz_h, zz_v, p2_h, p2_v);
+        } catch (...) {
+            unstage(*h->E, P);
+            throw;
+        }
+        unstage(*h->E, P);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t seed, uint64_t first, int64_t n,
+                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p) {
+    try {
+        begin(h, o);
+        validate(p, o);
+        if (n < 0) throw TnError(ST_INVALID, "n must be >= 0");
+        if (n == 0) return TN_OK;
+        if (!bits || !log_q) throw TnError(ST_INVALID, "null output");
+        const BoundarySet &S = cached_set(h, p, o, false);
+        SampleOpts so;
+        so.chi_x = o->chi_x;
+        so.sweeps = o->sweeps;
+        so.force_fit = o->init == 1;
+        so.init_seed = o->init_seed;
+        so.seed = seed;
+        sample(*h->E, h->cache_peps, S, so, first, n, uniforms, bits, log_q, log_p);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
+                          double *qr_ms, int64_t *qr_launches) {
+    if (!h || !h->E) return TN_ERR_INVALID;
+    const Counters &c = h->E->ctr;
+    if (gemm_flops) *gemm_flops = c.gemm_flops;
+    if (gemm_launches) *gemm_launches = c.gemm_launches;
+    if (gemm_ms) *gemm_ms = c.gemm_ms;
+    if (qr_ms) *qr_ms = c.qr_ms;
+    if (qr_launches) *qr_launches = c.qr_launches;
+    return TN_OK;
+}
+
+tn_status tn_set_timing(tn_handle *h, int enable) {
+    if (!h || !h->E) return TN_ERR_INVALID;
+    h->E->timing = enable != 0;
+    return TN_OK;
+}
+
+// ---------------------------------------------------------------- test hooks
+
+tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims, int conjA,
+                           const char *ib, const void *B, const int32_t *bdims, int conjB, const char *ic,
+                           void *C, const int32_t *cdims, int accumulate) {
+    try {
+        if (!h) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        h->E->set_prec(prec);
+        auto mk = [&](const void *p, const int32_t *d, const char *idx) {
+            Ten t;
+            t.p = const_cast<void *>(p);
+            t.esz = h->E->esz;
+            t.d.assign(d, d + std::strlen(idx));
+            return t;
+        };
+        Ten a = mk(A, adims, ia), b = mk(B, bdims, ib), c = mk(C, cdims, ic);
+        h->E->contract(op(a, ia, conjA != 0), op(b, ib, conjB != 0), op(c, ic), accumulate != 0);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    }
+}
+
+tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R) {
+    try {
+        if (!h) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        const int k = m < n ? m : n;
+        tnk::QrArgs a{};
+        a.m = m; a.n = n; a.batch = batch;
+        a.A = A; a.a_esz = esz; a.a_bs = (int64_t)m * n; a.a_rs = n; a.a_cs = 1;
+        a.Q = Q; a.q_esz = esz; a.q_bs = (int64_t)m * k; a.q_rs = k; a.q_cs = 1;
+        a.R = R; a.r_esz = esz; a.r_bs = (int64_t)k * n; a.r_rs = n; a.r_cs = 1;
+        h->E->qr(a);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    }
+}
+
+}  // extern "C"

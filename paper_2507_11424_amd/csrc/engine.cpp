@@ -1,0 +1,372 @@
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <set>
+#include <sstream>
+
+namespace tnb {
+
+// ---------------------------------------------------------------- operands
+
+Op op(const Ten &t, const std::string &idx, bool conj) {
+    if (idx.size() != t.d.size())
+        throw TnError(ST_SHAPE, "operand letters '" + idx + "' do not match tensor rank");
+    Op o;
+    o.p = t.p;
+    o.esz = t.esz;
+    o.idx = idx;
+    o.dims = t.d;
+    o.str.assign(t.d.size(), 1);
+    for (int i = (int)t.d.size() - 2; i >= 0; --i) o.str[i] = o.str[i + 1] * t.d[i + 1];
+    o.conj = conj;
+    return o;
+}
+
+Op op_bcast(const Ten &t, char letter, int size, const std::string &idx, bool conj) {
+    Op o = op(t, idx, conj);
+    o.idx = std::string(1, letter) + o.idx;
+    o.dims.insert(o.dims.begin(), size);
+    o.str.insert(o.str.begin(), 0);
+    return o;
+}
+
+// ---------------------------------------------------------------- pool
+
+Pool::~Pool() {
+    for (auto &kv : size_) (void)hipFree(kv.first);
+}
+
+void *Pool::get(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = free_.lower_bound(bytes);
+    if (it != free_.end() && it->first <= 2 * bytes + (1 << 20)) {
+        void *p = it->second;
+        free_.erase(it);
+        return p;
+    }
+    size_t alloc = bytes;
+    if (alloc > (1 << 20)) alloc = (alloc + (1 << 20) - 1) & ~size_t((1 << 20) - 1);
+    if (cap_ && held_ + alloc > cap_) {
+        trim();
+        if (held_ + alloc > cap_)
+            throw TnError(ST_OOM, "workspace cap reached (" + std::to_string(held_ + alloc) + " > " +
+                                      std::to_string(cap_) + " bytes)");
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, alloc);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim();
+        e = hipMalloc(&p, alloc);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw TnError(ST_OOM, "hipMalloc of " + std::to_string(alloc) + " bytes failed");
+        }
+    }
+    held_ += alloc;
+    size_[p] = alloc;
+    return p;
+}
+
+void Pool::put(void *p) {
+    if (!p) return;
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_.emplace(it->second, p);
+}
+
+void Pool::trim() {
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : free_) {
+        held_ -= size_[kv.second];
+        size_.erase(kv.second);
+        (void)hipFree(kv.second);
+    }
+    free_.clear();
+}
+
+// ---------------------------------------------------------------- engine
+
+Engine::Engine(int dev, hipStream_t st, size_t cap) : s(st), device(dev), pool_(cap) {
+    TN_HIP(hipEventCreate(&ev0_));
+    TN_HIP(hipEventCreate(&ev1_));
+}
+
+Engine::~Engine() {
+    (void)hipStreamSynchronize(s);
+    for (auto &kv : plans_)
+        if (kv.second->dev) (void)hipFree(kv.second->dev);
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+}
+
+Ten Engine::make(const std::vector<int> &dims, int e) {
+    Ten t;
+    t.d = dims;
+    t.esz = e ? e : esz;
+    t.p = pool_.get(t.bytes());
+    return t;
+}
+
+void Engine::drop(Ten &t) {
+    pool_.put(t.p);
+    t.p = nullptr;
+}
+
+static Op squeeze(const Op &o) {
+    Op r = o;
+    r.idx.clear();
+    r.dims.clear();
+    r.str.clear();
+    for (size_t i = 0; i < o.idx.size(); ++i) {
+        if (o.dims[i] == 1) continue;
+        r.idx.push_back(o.idx[i]);
+        r.dims.push_back(o.dims[i]);
+        r.str.push_back(o.str[i]);
+    }
+    return r;
+}
+
+Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
+    const Op A = squeeze(A0), B = squeeze(B0), C = squeeze(C0);
+    std::ostringstream ks;
+    auto addk = [&](const Op &o) {
+        ks << o.idx << ':';
+        for (size_t i = 0; i < o.idx.size(); ++i) ks << o.dims[i] << '/' << o.str[i] << ',';
+        ks << '|';
+    };
+    addk(A); addk(B); addk(C);
+    const std::string key = ks.str();
+    auto it = plans_.find(key);
+    if (it != plans_.end()) return it->second.get();
+
+    std::map<char, int> dim;
+    auto note = [&](const Op &o) {
+        for (size_t i = 0; i < o.idx.size(); ++i) {
+            auto f = dim.find(o.idx[i]);
+            if (f != dim.end() && f->second != o.dims[i])
+                throw TnError(ST_SHAPE, std::string("dimension mismatch on letter ") + o.idx[i] + " in " + key);
+            dim[o.idx[i]] = o.dims[i];
+        }
+    };
+    note(A); note(B); note(C);
+    auto has = [](const Op &o, char c) { return o.idx.find(c) != std::string::npos; };
+    auto stride = [](const Op &o, char c) -> int64_t {
+        const size_t i = o.idx.find(c);
+        return i == std::string::npos ? 0 : o.str[i];
+    };
+    std::string bl, ml, nl, kl;
+    for (char c : C.idx) {
+        const bool a = has(A, c), b = has(B, c);
+        if (a && b) bl.push_back(c);
+        else if (a) ml.push_back(c);
+        else if (b) nl.push_back(c);
+        else throw TnError(ST_SHAPE, std::string("output letter ") + c + " not in inputs: " + key);
+    }
+    for (char c : A.idx) {
+        if (has(C, c)) continue;
+        if (!has(B, c)) throw TnError(ST_SHAPE, std::string("letter ") + c + " summed on one operand only: " + key);
+        kl.push_back(c);
+    }
+    for (char c : B.idx)
+        if (!has(C, c) && !has(A, c))
+            throw TnError(ST_SHAPE, std::string("letter ") + c + " summed on one operand only: " + key);
+    // order K letters to follow whichever operand is contiguous along K
+    if (!kl.empty()) {
+        const char lastA = A.idx.empty() ? 0 : A.idx.back();
+        const char lastB = B.idx.empty() ? 0 : B.idx.back();
+        std::string order;
+        if (lastB && kl.find(lastB) != std::string::npos && stride(B, lastB) == 1 &&
+            !(lastA && kl.find(lastA) != std::string::npos && stride(A, lastA) == 1)) {
+            for (char c : B.idx) if (kl.find(c) != std::string::npos) order.push_back(c);
+        } else {
+            for (char c : A.idx) if (kl.find(c) != std::string::npos) order.push_back(c);
+        }
+        kl = order;
+    }
+    auto total = [&](const std::string &l) {
+        int64_t t = 1;
+        for (char c : l) t *= dim[c];
+        return t;
+    };
+    const int64_t M = total(ml), N = total(nl), K = total(kl), Z = total(bl);
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX || Z > INT32_MAX)
+        throw TnError(ST_UNSUPPORTED, "contraction extent too large: " + key);
+    // offset tables
+    auto table = [&](const std::string &l, const Op &o, std::vector<int64_t> &out) {
+        const int64_t n = total(l);
+        out.assign((size_t)n, 0);
+        std::vector<int> idx(l.size(), 0);
+        std::vector<int64_t> st(l.size());
+        for (size_t i = 0; i < l.size(); ++i) st[i] = stride(o, l[i]);
+        int64_t off = 0;
+        for (int64_t e = 0; e < n; ++e) {
+            out[(size_t)e] = off;
+            for (int i = (int)l.size() - 1; i >= 0; --i) {
+                idx[i]++;
+                off += st[i];
+                if (idx[i] < dim[l[i]]) break;
+                off -= st[i] * idx[i];
+                idx[i] = 0;
+            }
+        }
+    };
+    std::vector<int64_t> am, ak, bk, bn, cm, cn, ab, bb, cb;
+    table(ml, A, am); table(kl, A, ak); table(bl, A, ab);
+    table(kl, B, bk); table(nl, B, bn); table(bl, B, bb);
+    table(ml, C, cm); table(nl, C, cn); table(bl, C, cb);
+    auto fits = [](const std::vector<int64_t> &v) {
+        for (int64_t x : v)
+            if (x < 0 || x > INT32_MAX) return false;
+        return true;
+    };
+    if (!fits(am) || !fits(ak) || !fits(bk) || !fits(bn) || !fits(cm) || !fits(cn))
+        throw TnError(ST_UNSUPPORTED, "tensor offsets exceed 2^31 elements: " + key);
+
+    auto P = std::make_unique<Plan>();
+    // kernel N dimension should be C's contiguous letter for coalesced stores
+    const char cfast = C.idx.empty() ? 0 : C.idx.back();
+    const bool swap = cfast && ml.find(cfast) != std::string::npos;
+    P->swapped = swap;
+    const std::vector<int64_t> &kam = swap ? bn : am, &kak = swap ? bk : ak, &kbk = swap ? ak : bk,
+                               &kbn = swap ? am : bn, &kcm = swap ? cn : cm, &kcn = swap ? cm : cn,
+                               &kab = swap ? bb : ab, &kbb = swap ? ab : bb;
+    const Op &opA = swap ? B : A;
+    const Op &opB = swap ? A : B;
+    const std::string &kml = swap ? nl : ml, &knl = swap ? ml : nl;
+    const int64_t kM = swap ? N : M, kN = swap ? M : N;
+    // upload: int32 tables then int64 batch tables
+    const size_t n32 = kam.size() + kak.size() + kbk.size() + kbn.size() + kcm.size() + kcn.size();
+    const size_t bytes = n32 * 4 + 3 * (size_t)Z * 8 + 64;
+    std::vector<char> host(bytes, 0);
+    size_t off = 0;
+    int32_t *t32[6];
+    const std::vector<int64_t> *src32[6] = {&kam, &kak, &kbk, &kbn, &kcm, &kcn};
+    for (int i = 0; i < 6; ++i) {
+        t32[i] = reinterpret_cast<int32_t *>(host.data() + off);
+        for (size_t j = 0; j < src32[i]->size(); ++j) t32[i][j] = (int32_t)(*src32[i])[j];
+        off += src32[i]->size() * 4;
+    }
+    off = (off + 7) & ~size_t(7);
+    const size_t off64 = off;
+    const std::vector<int64_t> *src64[3] = {&kab, &kbb, &cb};
+    for (int i = 0; i < 3; ++i) {
+        std::memcpy(host.data() + off, src64[i]->data(), src64[i]->size() * 8);
+        off += src64[i]->size() * 8;
+    }
+    TN_HIP(hipMalloc(&P->dev, bytes));
+    TN_HIP(hipMemcpy(P->dev, host.data(), bytes, hipMemcpyHostToDevice));
+    char *d = reinterpret_cast<char *>(P->dev);
+    size_t o2 = 0;
+    const int32_t *dt[6];
+    for (int i = 0; i < 6; ++i) {
+        dt[i] = reinterpret_cast<const int32_t *>(d + o2);
+        o2 += src32[i]->size() * 4;
+    }
+    const int64_t *db[3];
+    o2 = off64;
+    for (int i = 0; i < 3; ++i) {
+        db[i] = reinterpret_cast<const int64_t *>(d + o2);
+        o2 += src64[i]->size() * 8;
+    }
+    tnk::GettArgs &g = P->base;
+    std::memset(&g, 0, sizeof(g));
+    g.M = (int)kM; g.N = (int)kN; g.K = (int)K; g.batch = (int)Z;
+    g.a_moff = dt[0]; g.a_koff = dt[1]; g.b_koff = dt[2]; g.b_noff = dt[3]; g.c_moff = dt[4]; g.c_noff = dt[5];
+    g.a_boff = db[0]; g.b_boff = db[1]; g.c_boff = db[2];
+    // load direction: along k when the operand's fastest letter is a K letter with stride 1
+    const char la = opA.idx.empty() ? 0 : opA.idx.back();
+    const char lb = opB.idx.empty() ? 0 : opB.idx.back();
+    g.a_kfast = (la && kl.find(la) != std::string::npos && stride(opA, la) == 1) ? 1 : 0;
+    g.b_kfast = (lb && kl.find(lb) != std::string::npos && stride(opB, lb) == 1) ? 1 : 0;
+    (void)kml; (void)knl;
+    if (kN <= 16) P->cfg = tnk::CFG_64x16;
+    else if (kM >= 8192 && kN >= 128 && K >= 16) P->cfg = tnk::CFG_128x64;
+    else P->cfg = tnk::CFG_64x64;
+    P->flops = 8.0 * (double)M * (double)N * (double)K * (double)Z;
+    Plan *raw = P.get();
+    plans_[key] = std::move(P);
+    return raw;
+}
+
+void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
+    if (A.esz != esz || B.esz != esz || C.esz != esz)
+        throw TnError(ST_INVALID, "operand element size does not match the compute precision");
+    Plan *P = plan(A, B, C);
+    tnk::GettArgs g = P->base;
+    g.A = P->swapped ? B.p : A.p;
+    g.B = P->swapped ? A.p : B.p;
+    g.C = const_cast<void *>(C.p);
+    g.conjA = (P->swapped ? B.conj : A.conj) ? 1 : 0;
+    g.conjB = (P->swapped ? A.conj : B.conj) ? 1 : 0;
+    g.accumulate = accumulate ? 1 : 0;
+    if (timing) TN_HIP(hipEventRecord(ev0_, s));
+    TN_HIP(tnk::launch_gett(g, prec, P->cfg, s));
+    if (timing) {
+        TN_HIP(hipEventRecord(ev1_, s));
+        TN_HIP(hipEventSynchronize(ev1_));
+        float ms = 0.f;
+        TN_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+        ctr.gemm_ms += ms;
+    }
+    ctr.gemm_flops += P->flops;
+    ctr.gemm_launches += 1;
+}
+
+Ten Engine::contract_new(const Op &A, const Op &B, const std::string &ic) {
+    std::vector<int> dims;
+    for (char c : ic) {
+        size_t i = A.idx.find(c);
+        if (i != std::string::npos) { dims.push_back(A.dims[i]); continue; }
+        i = B.idx.find(c);
+        if (i != std::string::npos) { dims.push_back(B.dims[i]); continue; }
+        throw TnError(ST_SHAPE, std::string("output letter ") + c + " not found");
+    }
+    Ten C = make(dims);
+    contract(A, B, op(C, ic));
+    return C;
+}
+
+void Engine::qr(const tnk::QrArgs &a) {
+    const size_t ws = tnk::qr_workspace_bytes(a.m, a.n, a.batch);
+    void *w = pool_.get(ws);
+    if (timing) TN_HIP(hipEventRecord(ev0_, s));
+    TN_HIP(tnk::launch_qr(a, w, s));
+    if (timing) {
+        TN_HIP(hipEventRecord(ev1_, s));
+        TN_HIP(hipEventSynchronize(ev1_));
+        float ms = 0.f;
+        TN_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+        ctr.qr_ms += ms;
+    }
+    ctr.qr_launches += 1;
+    pool_.put(w);
+}
+
+void Engine::norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out) {
+    const int P = tnk::reduce_partial_count(n);
+    void *w = pool_.get((size_t)P * batch * 8);
+    TN_HIP(tnk::launch_norm2(x, e, n, batch, bs, reinterpret_cast<double *>(w), out, s));
+    pool_.put(w);
+}
+
+void Engine::normalise(void *x, int e, int64_t n, int batch, int64_t bs, double *logscale, bool acc,
+                       int *flags) {
+    void *q = pool_.get((size_t)batch * 8);
+    norm2(x, e, n, batch, bs, reinterpret_cast<double *>(q));
+    TN_HIP(tnk::launch_normalise(x, e, n, batch, bs, reinterpret_cast<double *>(q), logscale, acc ? 1 : 0,
+                                 flags, s));
+    pool_.put(q);
+}
+
+void Engine::dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out) {
+    const int P = tnk::reduce_partial_count(n);
+    void *w = pool_.get((size_t)P * batch * 16);
+    TN_HIP(tnk::launch_dot(x, y, e, n, batch, bs, reinterpret_cast<double *>(w), out, s));
+    pool_.put(w);
+}
+
+}  // namespace tnb

@@ -1,0 +1,140 @@
+// Host-side execution engine: device memory pool, tensor views, the
+// einsum-style contraction planner on top of the GETT kernel, QR and norm
+// wrappers.  All work is enqueued on one HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace tnb {
+
+enum : int { ST_INVALID = 1, ST_SHAPE = 2, ST_OOM = 3, ST_HIP = 4, ST_NUMERIC = 5, ST_UNSUPPORTED = 6 };
+
+struct TnError : std::runtime_error {
+    int code;
+    TnError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define TN_HIP(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw ::tnb::TnError(::tnb::ST_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Dense row-major complex tensor in device memory.
+struct Ten {
+    void *p = nullptr;
+    std::vector<int> d;
+    int esz = 16;
+    int64_t numel() const {
+        int64_t n = 1;
+        for (int x : d) n *= x;
+        return n;
+    }
+    size_t bytes() const { return (size_t)numel() * esz; }
+    int dim(int i) const { return d[i < 0 ? (int)d.size() + i : i]; }
+};
+
+// One operand of a contraction: letters, dims and element strides.  A letter
+// may have stride 0 (broadcast over that index).
+struct Op {
+    const void *p = nullptr;
+    int esz = 16;
+    std::string idx;
+    std::vector<int> dims;
+    std::vector<int64_t> str;
+    bool conj = false;
+};
+
+Op op(const Ten &t, const std::string &idx, bool conj = false);
+// The same tensor seen with an extra broadcast letter in front (stride 0).
+Op op_bcast(const Ten &t, char letter, int size, const std::string &idx, bool conj = false);
+
+class Pool {
+  public:
+    explicit Pool(size_t cap) : cap_(cap) {}
+    ~Pool();
+    void *get(size_t bytes);
+    void put(void *p);
+    size_t held() const { return held_; }
+    void trim();
+
+  private:
+    size_t cap_;
+    size_t held_ = 0;
+    std::multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> size_;
+};
+
+struct Plan {
+    tnk::GettArgs base;  // pointers to tables filled in; data pointers per call
+    int cfg = 0;
+    bool swapped = false;
+    void *dev = nullptr;  // table storage
+    double flops = 0;     // 8 * M * N * K * batch
+};
+
+struct Counters {
+    double gemm_flops = 0;
+    int64_t gemm_launches = 0;
+    double gemm_ms = 0;
+    double qr_ms = 0;
+    int64_t qr_launches = 0;
+    void reset() { *this = Counters(); }
+};
+
+class Engine {
+  public:
+    Engine(int device, hipStream_t s, size_t cap);
+    ~Engine();
+
+    hipStream_t s;
+    int device;
+    int prec = tnk::P_FP64;
+    int esz = 16;  // element size of compute tensors
+    Counters ctr;
+    bool timing = false;
+
+    void set_prec(int p) { prec = p; esz = (p == tnk::P_FP64) ? 16 : 8; }
+
+    Ten make(const std::vector<int> &dims, int esz_override = 0);
+    void drop(Ten &t);
+
+    // C[ic] (+)= sum A[ia] * B[ib]; C must be allocated with the dims of ic.
+    void contract(const Op &A, const Op &B, const Op &C, bool accumulate = false);
+    // Allocates C with the letters of ic (dims taken from A and B).
+    Ten contract_new(const Op &A, const Op &B, const std::string &ic);
+
+    // Reduced QR (FP64) of `batch` matrices; see tnk::QrArgs.
+    void qr(const tnk::QrArgs &a);
+    // norm2 per batch item into dev[batch]; normalise in place; logscale +=.
+    void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
+    void normalise(void *x, int e, int64_t n, int batch, int64_t bs, double *logscale, bool acc,
+                   int *flags);
+    void dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out);
+
+    // Raw device memory from the pool (stream-ordered reuse after unraw).
+    void *raw(size_t bytes) { return pool_.get(bytes); }
+    void unraw(void *p) { pool_.put(p); }
+    size_t held() const { return pool_.held(); }
+
+    void sync() { TN_HIP(hipStreamSynchronize(s)); }
+
+  private:
+    Pool pool_;
+    std::unordered_map<std::string, std::unique_ptr<Plan>> plans_;
+    Plan *plan(const Op &A, const Op &B, const Op &C);
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+};
+
+}  // namespace tnb

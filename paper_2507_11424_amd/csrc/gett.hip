@@ -1,0 +1,434 @@
+// Complex tensor contraction engine on CDNA4 matrix cores.
+//
+// Every contraction of the boundary-MPS fit and of the sampler (products of
+// boundary MPS, row tensors, their conjugates and environments) is a batched
+// complex GEMM over gathered indices (see GettArgs).  Complex products use the
+// 4M form on real MFMA:
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
+// with A and B tiles staged through LDS as planar (re, im) slabs.
+//
+// Precisions:
+//   FP64   : complex128 storage, v_mfma_f64_16x16x4_f64;
+//   FP32   : complex64 storage, v_mfma_f32_16x16x4_f32;
+//   BF16X3 : complex64 storage; each FP32 value x is split at LDS-staging time
+//            into bf16 parts x = h + l (+ residual), and a product a*b is
+//            formed as ah*bh + ah*bl + al*bh with v_mfma_f32_16x16x32_bf16,
+//            accumulated in FP32;
+//   BF16X6 : three parts x = h + m + l, products hh + hm + mh + hl + lh + mm.
+#include "kernels.hpp"
+
+namespace tnk {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Tr;
+template <> struct Tr<double> {
+    using C2 = double2;
+    using Acc = v4d;
+    __device__ static inline Acc mma(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Tr<float> {
+    using C2 = float2;
+    using Acc = v4f;
+    __device__ static inline Acc mma(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ inline int xcd_remap(int t, int ntiles) {
+    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of tiles so that tiles sharing an A panel share an L2
+    if ((ntiles & 7) != 0) return t;
+    return (t & 7) * (ntiles >> 3) + (t >> 3);
+}
+
+// --------------------------------------------------------------------------
+// FP64 / FP32: one MFMA 16x16x4 per real product, 4 per complex product.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+gett_mfma(GettArgs p) {
+    using C2 = typename Tr<T>::C2;
+    using Acc = typename Tr<T>::Acc;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int LA = (BM * BK) / NT;
+    constexpr int LB = (BK * BN) / NT;
+    constexpr int PA = BM + 2, PB = BN + 2;
+    static_assert(LA >= 1 && LB >= 1 && NT % BK == 0 && NT >= BM && NT >= BN, "tile");
+    __shared__ T sA[2][BK][PA];
+    __shared__ T sB[2][BK][PB];
+
+    const int tid = threadIdx.x;
+    const int tiles_n = (p.N + BN - 1) / BN;
+    const int tiles_m = (p.M + BM - 1) / BM;
+    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int m0 = (tile / tiles_n) * BM;
+    const int n0 = (tile % tiles_n) * BN;
+
+    // per-thread load coordinates inside the tile
+    int am[LA], ak[LA], bk[LB], bn[LB];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+        if (p.a_kfast) { ak[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
+        else           { am[i] = tid % BM; ak[i] = tid / BM + (NT / BM) * i; }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+        if (p.b_kfast) { bk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
+        else           { bn[i] = tid % BN; bk[i] = tid / BN + (NT / BN) * i; }
+    }
+    int amo[LA], bno[LB];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+        const int m = m0 + am[i];
+        amo[i] = (m < p.M) ? p.a_moff[m] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+        const int n = n0 + bn[i];
+        bno[i] = (n < p.N) ? p.b_noff[n] : -1;
+    }
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const T sgnA = p.conjA ? T(-1) : T(1);
+    const T sgnB = p.conjB ? T(-1) : T(1);
+
+    for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        const C2 *Ab = reinterpret_cast<const C2 *>(p.A) + p.a_boff[b];
+        const C2 *Bb = reinterpret_cast<const C2 *>(p.B) + p.b_boff[b];
+        C2 *Cb = reinterpret_cast<C2 *>(p.C) + p.c_boff[b];
+
+        Acc accR[FM][FN], accI[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { accR[i][j][r] = T(0); accI[i][j][r] = T(0); }
+
+        C2 ra[LA], rb[LB];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int k = k0 + ak[i];
+                C2 v; v.x = T(0); v.y = T(0);
+                if (amo[i] >= 0 && k < p.K) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
+                ra[i] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int k = k0 + bk[i];
+                C2 v; v.x = T(0); v.y = T(0);
+                if (bno[i] >= 0 && k < p.K) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
+                rb[i] = v;
+            }
+        };
+        gload(0);
+        for (int k0 = 0; k0 < p.K; k0 += BK) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                sA[0][ak[i]][am[i]] = ra[i].x;
+                sA[1][ak[i]][am[i]] = sgnA * ra[i].y;
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                sB[0][bk[i]][bn[i]] = rb[i].x;
+                sB[1][bk[i]][bn[i]] = sgnB * rb[i].y;
+            }
+            __syncthreads();
+            if (k0 + BK < p.K) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                const int kr = kk * 4 + (lane >> 4);
+                T arv[FM], aiv[FM], brv[FN], biv[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int mm = wm * WTM + i * 16 + (lane & 15);
+                    arv[i] = sA[0][kr][mm];
+                    aiv[i] = sA[1][kr][mm];
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int nn = wn * WTN + j * 16 + (lane & 15);
+                    brv[j] = sB[0][kr][nn];
+                    biv[j] = sB[1][kr][nn];
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        accR[i][j] = Tr<T>::mma(arv[i], brv[j], accR[i][j]);
+                        accR[i][j] = Tr<T>::mma(-aiv[i], biv[j], accR[i][j]);
+                        accI[i][j] = Tr<T>::mma(arv[i], biv[j], accI[i][j]);
+                        accI[i][j] = Tr<T>::mma(aiv[i], brv[j], accI[i][j]);
+                    }
+            }
+        }
+        // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+            if (n >= p.N) continue;
+            const int64_t cn = p.c_noff[n];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + r;
+                    if (m >= p.M) continue;
+                    C2 *dst = Cb + p.c_moff[m] + cn;
+                    C2 v;
+                    v.x = accR[i][j][r];
+                    v.y = accI[i][j][r];
+                    if (p.accumulate) { const C2 o = *dst; v.x += o.x; v.y += o.y; }
+                    *dst = v;
+                }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Split-BF16: FP32 operands split into NP bf16 parts at staging time.
+// MFMA 16x16x32 bf16: lane l holds A[l%16][8*(l/16) .. +8) and
+// B[8*(l/16) .. +8)[l%16]; accumulator layout as the 16x16x4 forms.
+__device__ inline unsigned short bf16_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    // round to nearest even on the upper 16 bits (inputs are finite here)
+    unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(r >> 16);
+}
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+template <int NP>
+__device__ inline void split_bf16(float x, unsigned short *out) {
+    float r = x;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        unsigned short h = bf16_rne(r);
+        out[q] = h;
+        r = r - bf16_to_f(h);
+    }
+}
+
+template <int NP, int BM, int BN, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+gett_bf16(GettArgs p) {
+    constexpr int BK = 32;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int LA = (BM * BK) / NT;
+    constexpr int LB = (BK * BN) / NT;
+    constexpr int KP = BK + 8;  // padded k extent (bf16 elements), keeps 16-byte alignment
+    static_assert(LA >= 1 && LB >= 1 && NT % BK == 0 && NT >= BM && NT >= BN, "tile");
+    // planes: [re/im][part][row][k]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[2][NP][BM][KP];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[2][NP][BN][KP];
+
+    const int tid = threadIdx.x;
+    const int tiles_n = (p.N + BN - 1) / BN;
+    const int tiles_m = (p.M + BM - 1) / BM;
+    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int m0 = (tile / tiles_n) * BM;
+    const int n0 = (tile % tiles_n) * BN;
+
+    int am[LA], ak[LA], bk[LB], bn[LB];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+        if (p.a_kfast) { ak[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
+        else           { am[i] = tid % BM; ak[i] = tid / BM + (NT / BM) * i; }
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+        if (p.b_kfast) { bk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
+        else           { bn[i] = tid % BN; bk[i] = tid / BN + (NT / BN) * i; }
+    }
+    int amo[LA], bno[LB];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+        const int m = m0 + am[i];
+        amo[i] = (m < p.M) ? p.a_moff[m] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+        const int n = n0 + bn[i];
+        bno[i] = (n < p.N) ? p.b_noff[n] : -1;
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const float sgnA = p.conjA ? -1.f : 1.f;
+    const float sgnB = p.conjB ? -1.f : 1.f;
+
+    for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        const float2 *Ab = reinterpret_cast<const float2 *>(p.A) + p.a_boff[b];
+        const float2 *Bb = reinterpret_cast<const float2 *>(p.B) + p.b_boff[b];
+        float2 *Cb = reinterpret_cast<float2 *>(p.C) + p.c_boff[b];
+        v4f accR[FM][FN], accI[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
+        float2 ra[LA], rb[LB];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int k = k0 + ak[i];
+                float2 v = make_float2(0.f, 0.f);
+                if (amo[i] >= 0 && k < p.K) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
+                ra[i] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int k = k0 + bk[i];
+                float2 v = make_float2(0.f, 0.f);
+                if (bno[i] >= 0 && k < p.K) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
+                rb[i] = v;
+            }
+        };
+        gload(0);
+        for (int k0 = 0; k0 < p.K; k0 += BK) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                unsigned short hr[NP], hi[NP];
+                split_bf16<NP>(ra[i].x, hr);
+                split_bf16<NP>(sgnA * ra[i].y, hi);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) { sA[0][q][am[i]][ak[i]] = hr[q]; sA[1][q][am[i]][ak[i]] = hi[q]; }
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                unsigned short hr[NP], hi[NP];
+                split_bf16<NP>(rb[i].x, hr);
+                split_bf16<NP>(sgnB * rb[i].y, hi);
+#pragma unroll
+                for (int q = 0; q < NP; ++q) { sB[0][q][bn[i]][bk[i]] = hr[q]; sB[1][q][bn[i]][bk[i]] = hi[q]; }
+            }
+            __syncthreads();
+            if (k0 + BK < p.K) gload(k0 + BK);
+            const int kc = (lane >> 4) * 8;
+            v8s a[2][NP][FM], bfr[2][NP][FN];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+                        a[c][q][i] = *reinterpret_cast<const v8s *>(&sA[c][q][wm * WTM + i * 16 + (lane & 15)][kc]);
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        bfr[c][q][j] = *reinterpret_cast<const v8s *>(&sB[c][q][wn * WTN + j * 16 + (lane & 15)][kc]);
+                }
+            // negated imaginary parts of A for the Re C term (sign bit flip is exact)
+            v8s an[NP][FM];
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int i = 0; i < FM; ++i) an[q][i] = a[1][q][i] ^ (short)0x8000;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+#pragma unroll
+                    for (int qa = 0; qa < NP; ++qa)
+#pragma unroll
+                        for (int qb = 0; qb < NP; ++qb) {
+                            if (qa + qb >= NP) continue;  // keep products of total order < NP
+                            accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[0][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accR[i][j], 0, 0, 0);
+                            accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, an[qa][i]), __builtin_bit_cast(v8bf, bfr[1][qb][j]), accR[i][j], 0, 0, 0);
+                            accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[0][qa][i]), __builtin_bit_cast(v8bf, bfr[1][qb][j]), accI[i][j], 0, 0, 0);
+                            accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[1][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accI[i][j], 0, 0, 0);
+                        }
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+            if (n >= p.N) continue;
+            const int64_t cn = p.c_noff[n];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + r;
+                    if (m >= p.M) continue;
+                    float2 *dst = Cb + p.c_moff[m] + cn;
+                    float2 v = make_float2(accR[i][j][r], accI[i][j][r]);
+                    if (p.accumulate) { const float2 o = *dst; v.x += o.x; v.y += o.y; }
+                    *dst = v;
+                }
+        }
+    }
+}
+
+template <typename K>
+hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStream_t s) {
+    const int tiles = ((a.M + bm - 1) / bm) * ((a.N + bn - 1) / bn);
+    const int gy = a.batch < 65535 ? a.batch : 65535;
+    if (tiles <= 0 || a.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kernel, dim3(tiles, gy), dim3(nt), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void gett_tile(int cfg, int prec, int *bm, int *bn) {
+    switch (cfg) {
+        case CFG_64x64: *bm = 64; *bn = 64; break;
+        case CFG_128x64: *bm = 128; *bn = 64; break;
+        case CFG_64x16: *bm = 64; *bn = 16; break;
+        default: *bm = 128; *bn = 128; break;
+    }
+    (void)prec;
+}
+
+hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+    if (prec == P_FP64) {
+        switch (cfg) {
+            case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
+            case CFG_128x64: return launch_k(gett_mfma<double, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
+            case CFG_64x16: return launch_k(gett_mfma<double, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
+            default: return launch_k(gett_mfma<double, 128, 128, 8, 2, 2>, a, 128, 128, 256, s);
+        }
+    }
+    if (prec == P_FP32) {
+        switch (cfg) {
+            case CFG_64x64: return launch_k(gett_mfma<float, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
+            case CFG_128x64: return launch_k(gett_mfma<float, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
+            case CFG_64x16: return launch_k(gett_mfma<float, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
+            default: return launch_k(gett_mfma<float, 128, 128, 8, 2, 2>, a, 128, 128, 256, s);
+        }
+    }
+    if (prec == P_BF16X3) {
+        switch (cfg) {
+            case CFG_64x64: return launch_k(gett_bf16<2, 64, 64, 2, 2>, a, 64, 64, 256, s);
+            case CFG_128x64: return launch_k(gett_bf16<2, 128, 64, 2, 2>, a, 128, 64, 256, s);
+            case CFG_64x16: return launch_k(gett_bf16<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
+            default: return launch_k(gett_bf16<2, 128, 128, 2, 2>, a, 128, 128, 256, s);
+        }
+    }
+    switch (cfg) {
+        case CFG_64x64: return launch_k(gett_bf16<3, 64, 64, 2, 2>, a, 64, 64, 256, s);
+        case CFG_128x64: return launch_k(gett_bf16<3, 128, 64, 2, 2>, a, 128, 64, 256, s);
+        case CFG_64x16: return launch_k(gett_bf16<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
+        default: return launch_k(gett_bf16<3, 128, 128, 2, 2>, a, 128, 128, 256, s);
+    }
+}
+
+}  // namespace tnk

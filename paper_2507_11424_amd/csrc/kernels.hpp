@@ -1,0 +1,115 @@
+// Internal launch interface of the HIP kernels (host side).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tnk {
+
+// Compute modes of the contraction engine (mirrors tn_prec).
+enum Prec : int { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
+
+// A batched complex contraction written as a GEMM over gathered indices:
+//   C[b](m, n) (+)= sum_k opA(A[b](m, k)) * opB(B[b](k, n))
+// Element (m, k) of A lives at A + a_boff[b] + a_moff[m] + a_koff[k] (complex
+// elements); likewise B and C.  opX conjugates when conjX is set.  The offset
+// tables let one kernel contract tensors of any rank and index order without
+// explicit transposes.
+struct GettArgs {
+    int M, N, K, batch;
+    const void *A; const int32_t *a_moff; const int32_t *a_koff; const int64_t *a_boff;
+    const void *B; const int32_t *b_koff; const int32_t *b_noff; const int64_t *b_boff;
+    void *C; const int32_t *c_moff; const int32_t *c_noff; const int64_t *c_boff;
+    int conjA, conjB;
+    int accumulate;      // 1: C += product, 0: C = product
+    int a_kfast;         // 1: A is contiguous along k (load lanes along k), 0: along m
+    int b_kfast;         // 1: B is contiguous along k, 0: along n
+};
+
+// Tile configurations of the contraction kernel.
+enum GettCfg : int {
+    CFG_64x64 = 0,    // 4 waves, 32x32 per wave
+    CFG_128x64 = 1,   // 4 waves, 64x32 per wave
+    CFG_64x16 = 2,    // skinny N
+    CFG_128x128 = 3,  // 4 waves, 64x64 per wave
+    CFG_COUNT = 4
+};
+
+hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s);
+void gett_tile(int cfg, int prec, int *bm, int *bn);
+
+// ---------------------------------------------------------------- linear algebra
+// Householder QR of `batch` complex matrices (m x n), FP64 arithmetic.
+// Element (i, j) of matrix b of A: A + b*a_bs + i*a_rs + j*a_cs (complex
+// elements of size esz: 16 = complex128, 8 = complex64), conjugated if a_conj.
+// Outputs Q (m x k, k = min(m, n)) with the same addressing scheme, and R (k x n)
+// if R != nullptr.  Workspace: see qr_workspace_bytes.
+struct QrArgs {
+    int m, n, batch;
+    const void *A; int a_esz; int64_t a_bs, a_rs, a_cs; int a_conj;
+    void *Q; int q_esz; int64_t q_bs, q_rs, q_cs; int q_conj;
+    void *R; int r_esz; int64_t r_bs, r_rs, r_cs; int r_conj;
+};
+size_t qr_workspace_bytes(int m, int n, int batch);
+hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
+
+// ---------------------------------------------------------------- small kernels
+// out[b] = sum |x[b][i]|^2 over n complex elements (FP64 accumulation), batch
+// stride `bs`.  Deterministic two-level reduction; partial needs
+// reduce_partial_count(n) * batch doubles.
+int reduce_partial_count(int64_t n);
+hipError_t launch_norm2(const void *x, int esz, int64_t n, int batch, int64_t bs,
+                        double *partial, double *out, hipStream_t s);
+// x[b] *= 1/sqrt(norm2[b]); logscale[b] (+)= 0.5 log(norm2[b]); flags[b] |= 1 if
+// norm2 is not finite or not positive.
+hipError_t launch_normalise(void *x, int esz, int64_t n, int batch, int64_t bs,
+                            const double *norm2, double *logscale, int accumulate_log,
+                            int *flags, hipStream_t s);
+// Element-type conversion / copy (c128 <-> c64), n complex elements.
+hipError_t launch_convert(const void *src, int src_esz, void *dst, int dst_esz, int64_t n,
+                          hipStream_t s);
+// Philox-uniform complex initial guess: element e of tensor gets counter
+// (e, site, row, sample[b]) and key (seed, tag).
+hipError_t launch_init_tensor(void *out, int esz, int64_t n, int batch, int64_t bs,
+                              uint64_t seed, uint64_t tag, uint64_t row, uint64_t site,
+                              const uint64_t *sample, hipStream_t s);
+// Fill with a complex constant.
+hipError_t launch_fill(void *x, int esz, int64_t n, double re, double im, hipStream_t s);
+// out[b] = sum_i x[b][i] * y[b][i] (no conjugation), complex FP64 result (2 doubles).
+hipError_t launch_dot(const void *x, const void *y, int esz, int64_t n, int batch, int64_t bs,
+                      double *partial, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- sampler
+struct DrawArgs {
+    int batch;                 // samples in flight
+    const double *pt0, *pt1;   // [batch][2]: complex P~(s) for s = 0 and s = 1
+    const double *uniforms;    // [n_total][n_qubits] or nullptr
+    int64_t u_row0;            // row of `uniforms` for batch entry 0
+    int n_qubits, qubit;       // qubit drawn now
+    uint64_t seed; const uint64_t *sample_index;  // Philox stream (when uniforms == nullptr)
+    uint8_t *bits; int64_t bits_row0;              // bits [n_total][n_qubits]
+    double *log_q;             // [batch]
+    int *xsel;                 // [batch] out: drawn bit
+    int *flags;                // [batch] |= 2 on a bad marginal
+};
+hipError_t launch_draw(const DrawArgs &a, hipStream_t s);
+// Gathers per-sample pointers: dst[b] = base_off + xsel[b] * stride.
+hipError_t launch_select_offsets(const int *xsel, int batch, int64_t base_off, int64_t stride,
+                                 int64_t *dst, hipStream_t s);
+// out[b] = x[b][sel[b]] copy of a slab of n complex elements (slab stride ss).
+hipError_t launch_select_copy(const void *x, int esz, int64_t n, int64_t ss, int64_t bs,
+                              const int *sel, int batch, void *out, int64_t obs, hipStream_t s);
+// out[b] = (sel[b] ? x1 : x0)[b], slabs of n complex elements, batch stride bs.
+hipError_t launch_select2(const void *x0, const void *x1, int esz, int64_t n, int64_t bs, const int *sel,
+                          int batch, void *out, hipStream_t s);
+// Fill n doubles with v.
+hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t s);
+// dots [4][2] = complex rho~[s][t] (order 00, 01, 10, 11) -> out[8] = rho / Tr rho.
+hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s);
+// dots [4][2] = complex P~(s, t) -> p2[4] = Re P / sum Re P (if p2), zz = sum (-1)^(s+t) Re P / sum Re P.
+hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t s);
+// Final amplitude -> log p.
+hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p,
+                       hipStream_t s);
+
+}  // namespace tnk

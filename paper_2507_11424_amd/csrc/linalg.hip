@@ -1,0 +1,436 @@
+// FP64 linear algebra of the boundary-MPS fit: Householder QR of the tall
+// (chi * phys) x chi site matrices (the gauge moves of the one-site fit), norms,
+// renormalisation, Philox initial guesses.
+//
+// QR is a tall-skinny (TSQR) tree: the rows are split into balanced blocks of at
+// most QR_LDS / n rows, each block is factored by one workgroup entirely in LDS
+// (Householder, wavefront reductions), the stacked n x n R factors are factored
+// the same way level by level, and the explicit thin Q is formed top-down by
+// applying each block's reflectors to its chunk of the parent Q.  Matrices with
+// more than 64 columns that do not fit one block fall back to a one-workgroup
+// factorisation in global memory.
+#include "kernels.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace tnk {
+namespace {
+
+constexpr int QR_NT = 256;
+constexpr int QR_LDS = 8192;  // complex doubles held by one workgroup (128 KiB)
+constexpr int QR_G = QR_NT / 64;
+
+struct MatDesc {
+    const void *p; int esz; int64_t bs, rs, cs; int conj;
+};
+struct MatOut {
+    void *p; int esz; int64_t bs, rs, cs; int conj;
+};
+
+__device__ inline double2 ld_c(const void *base, int esz, int64_t off, int conj) {
+    double2 v;
+    if (esz == 16) {
+        v = reinterpret_cast<const double2 *>(base)[off];
+    } else {
+        const float2 f = reinterpret_cast<const float2 *>(base)[off];
+        v.x = f.x; v.y = f.y;
+    }
+    if (conj) v.y = -v.y;
+    return v;
+}
+__device__ inline void st_c(void *base, int esz, int64_t off, double2 v, int conj) {
+    if (conj) v.y = -v.y;
+    if (esz == 16) {
+        reinterpret_cast<double2 *>(base)[off] = v;
+    } else {
+        reinterpret_cast<float2 *>(base)[off] = make_float2((float)v.x, (float)v.y);
+    }
+}
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// Block sum over QR_NT threads; every thread receives the result.
+__device__ inline double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < QR_NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// In-place Householder factorisation of X (rows x n, leading dimension ld).
+// After return: X[i][j], i >= j, holds reflector j (v_j[0] on the diagonal);
+// X[i][j], i < j, holds R; beta[j] = R[j][j]; tau[j] = 2 / ||v_j||^2.
+// H_j = I - tau_j v_j v_j^H is Hermitian and unitary; A = H_0 ... H_{k-1} R.
+__device__ void hh_factor(double2 *X, int rows, int n, int ld, double2 *beta, double *tau,
+                          double *red, double2 *wpart) {
+    const int t = threadIdx.x;
+    const int kmax = rows < n ? rows : n;
+    for (int j = 0; j < kmax; ++j) {
+        double s = 0.0;
+        for (int i = j + t; i < rows; i += QR_NT) {
+            const double2 x = X[(int64_t)i * ld + j];
+            s += x.x * x.x + x.y * x.y;
+        }
+        s = block_sum(s, red);
+        const double2 alpha = X[(int64_t)j * ld + j];
+        const double sigma = sqrt(s);
+        const double aabs = hypot(alpha.x, alpha.y);
+        __syncthreads();
+        double tj = 0.0;
+        double2 bj = make_double2(0.0, 0.0);
+        if (sigma > 0.0) {
+            const double2 ph = aabs > 0.0 ? make_double2(alpha.x / aabs, alpha.y / aabs) : make_double2(1.0, 0.0);
+            bj = make_double2(-ph.x * sigma, -ph.y * sigma);
+            tj = 1.0 / (sigma * (sigma + aabs));
+            if (t == 0) X[(int64_t)j * ld + j] = make_double2(ph.x * (aabs + sigma), ph.y * (aabs + sigma));
+        }
+        if (t == 0) { beta[j] = bj; tau[j] = tj; }
+        __syncthreads();
+        if (tj == 0.0) continue;
+        const int g = t >> 6;
+        for (int cb = j + 1; cb < n; cb += 64) {
+            const int c = cb + (t & 63);
+            double2 w = make_double2(0.0, 0.0);
+            if (c < n) {
+                for (int i = j + g; i < rows; i += QR_G) {
+                    const double2 v = X[(int64_t)i * ld + j];
+                    const double2 x = X[(int64_t)i * ld + c];
+                    const double2 p = cmulc(v, x);
+                    w.x += p.x; w.y += p.y;
+                }
+            }
+            wpart[g * 64 + (t & 63)] = w;
+            __syncthreads();
+            if (c < n) {
+                double2 ws = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < QR_G; ++q) { ws.x += wpart[q * 64 + (t & 63)].x; ws.y += wpart[q * 64 + (t & 63)].y; }
+                ws.x *= tj; ws.y *= tj;
+                for (int i = j + g; i < rows; i += QR_G) {
+                    const double2 v = X[(int64_t)i * ld + j];
+                    const double2 p = cmul(v, ws);
+                    double2 &x = X[(int64_t)i * ld + c];
+                    x.x -= p.x; x.y -= p.y;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Y <- H_0 ... H_{k-1} Y for Y (rows x nq, leading dim ldy); reflectors in V
+// (rows x k part of a rows x ldv array), tau[k].
+__device__ void hh_apply(double2 *Y, int rows, int nq, int ldy, const double2 *V, int ldv, int k,
+                         const double *tau, double2 *wpart) {
+    const int t = threadIdx.x;
+    const int g = t >> 6;
+    for (int j = k - 1; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        for (int cb = 0; cb < nq; cb += 64) {
+            const int c = cb + (t & 63);
+            double2 w = make_double2(0.0, 0.0);
+            if (c < nq) {
+                for (int i = j + g; i < rows; i += QR_G) {
+                    const double2 v = V[(int64_t)i * ldv + j];
+                    const double2 y = Y[(int64_t)i * ldy + c];
+                    const double2 p = cmulc(v, y);
+                    w.x += p.x; w.y += p.y;
+                }
+            }
+            wpart[g * 64 + (t & 63)] = w;
+            __syncthreads();
+            if (c < nq) {
+                double2 ws = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < QR_G; ++q) { ws.x += wpart[q * 64 + (t & 63)].x; ws.y += wpart[q * 64 + (t & 63)].y; }
+                ws.x *= tj; ws.y *= tj;
+                for (int i = j + g; i < rows; i += QR_G) {
+                    const double2 v = V[(int64_t)i * ldv + j];
+                    const double2 p = cmul(v, ws);
+                    double2 &y = Y[(int64_t)i * ldy + c];
+                    y.x -= p.x; y.y -= p.y;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct LeafArgs {
+    MatDesc in;              // level input (row i, col j), rows x n
+    int rows, n, nb, top;
+    char *ws; int64_t ws_bs;  // workspace base and per-batch stride (bytes)
+    size_t v_off, t_off, b_off, rs_off;
+    MatOut R; int want_r;    // top only: k x n
+};
+
+__global__ void __launch_bounds__(QR_NT) k_qr_leaf(LeafArgs a) {
+    extern __shared__ double2 lds[];
+    __shared__ double red[QR_NT / 64];
+    __shared__ double2 wpart[QR_NT];
+    __shared__ double2 sbeta[128];  // k <= 90 whenever one block holds the matrix
+    __shared__ double stau[128];
+    const int blk = blockIdx.x;
+    const int bt = blockIdx.y;
+    const int r0 = (int)(((int64_t)blk * a.rows) / a.nb);
+    const int r1 = (int)(((int64_t)(blk + 1) * a.rows) / a.nb);
+    const int len = r1 - r0;
+    const int n = a.n;
+    double2 *X = lds;
+    char *wb = a.ws + (int64_t)bt * a.ws_bs;
+    const char *inb = reinterpret_cast<const char *>(a.in.p) + (int64_t)bt * a.in.bs * a.in.esz;
+    for (int e = threadIdx.x; e < len * n; e += QR_NT) {
+        const int i = e / n, j = e % n;
+        X[e] = ld_c(inb, a.in.esz, (int64_t)(r0 + i) * a.in.rs + (int64_t)j * a.in.cs, a.in.conj);
+    }
+    __syncthreads();
+    hh_factor(X, len, n, n, sbeta, stau, red, wpart);
+    __syncthreads();
+    const int k = len < n ? len : n;
+    double2 *Vb = reinterpret_cast<double2 *>(wb + a.v_off) + (int64_t)r0 * n;
+    for (int e = threadIdx.x; e < len * n; e += QR_NT) Vb[e] = X[e];
+    double *tb = reinterpret_cast<double *>(wb + a.t_off) + (int64_t)blk * n;
+    double2 *bb = reinterpret_cast<double2 *>(wb + a.b_off) + (int64_t)blk * n;
+    for (int j = threadIdx.x; j < n; j += QR_NT) {
+        tb[j] = j < k ? stau[j] : 0.0;
+        bb[j] = j < k ? sbeta[j] : make_double2(0.0, 0.0);
+    }
+    if (!a.top) {
+        double2 *Rb = reinterpret_cast<double2 *>(wb + a.rs_off) + (int64_t)blk * n * n;
+        for (int e = threadIdx.x; e < n * n; e += QR_NT) {
+            const int i = e / n, j = e % n;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < k) {
+                if (j == i) v = sbeta[i];
+                else if (j > i) v = X[i * n + j];
+            }
+            Rb[e] = v;
+        }
+    } else if (a.want_r) {
+        char *rb = reinterpret_cast<char *>(a.R.p) + (int64_t)bt * a.R.bs * a.R.esz;
+        for (int e = threadIdx.x; e < k * n; e += QR_NT) {
+            const int i = e / n, j = e % n;
+            double2 v = make_double2(0.0, 0.0);
+            if (j == i) v = sbeta[i];
+            else if (j > i) v = X[i * n + j];
+            st_c(rb, a.R.esz, (int64_t)i * a.R.rs + (int64_t)j * a.R.cs, v, a.R.conj);
+        }
+    }
+}
+
+struct FormArgs {
+    int rows, n, nb, k, top, level0;
+    char *ws; int64_t ws_bs;
+    size_t v_off, t_off, x_off, q_off;  // x_off: parent Q ((nb n) x k), q_off: this level's Q
+    MatOut out;                          // level 0 destination
+};
+
+__global__ void __launch_bounds__(QR_NT) k_qr_form(FormArgs a) {
+    extern __shared__ double2 lds[];
+    __shared__ double2 wpart[QR_NT];
+    const int blk = blockIdx.x;
+    const int bt = blockIdx.y;
+    const int r0 = (int)(((int64_t)blk * a.rows) / a.nb);
+    const int r1 = (int)(((int64_t)(blk + 1) * a.rows) / a.nb);
+    const int len = r1 - r0;
+    const int n = a.n, k = a.k;
+    const int kb = len < n ? len : n;
+    char *wb = a.ws + (int64_t)bt * a.ws_bs;
+    double2 *Y = lds;  // len x k
+    const double2 *X = a.top ? nullptr : reinterpret_cast<const double2 *>(wb + a.x_off);
+    for (int e = threadIdx.x; e < len * k; e += QR_NT) {
+        const int i = e / k, c = e % k;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < kb) {
+            if (a.top) v = make_double2(i == c ? 1.0 : 0.0, 0.0);
+            else v = X[((int64_t)blk * n + i) * k + c];
+        }
+        Y[e] = v;
+    }
+    __syncthreads();
+    const double2 *Vb = reinterpret_cast<const double2 *>(wb + a.v_off) + (int64_t)r0 * n;
+    const double *tb = reinterpret_cast<const double *>(wb + a.t_off) + (int64_t)blk * n;
+    hh_apply(Y, len, k, k, Vb, n, kb, tb, wpart);
+    if (a.level0) {
+        char *ob = reinterpret_cast<char *>(a.out.p) + (int64_t)bt * a.out.bs * a.out.esz;
+        for (int e = threadIdx.x; e < len * k; e += QR_NT) {
+            const int i = e / k, c = e % k;
+            st_c(ob, a.out.esz, (int64_t)(r0 + i) * a.out.rs + (int64_t)c * a.out.cs, Y[e], a.out.conj);
+        }
+    } else {
+        double2 *qb = reinterpret_cast<double2 *>(wb + a.q_off) + (int64_t)r0 * k;
+        for (int e = threadIdx.x; e < len * k; e += QR_NT) qb[e] = Y[e];
+    }
+}
+
+// Fallback: one workgroup per matrix, matrix in global workspace.
+struct GlobalQrArgs {
+    MatDesc in; int m, n;
+    char *ws; int64_t ws_bs;
+    size_t w_off, y_off, t_off, b_off;
+    MatOut Q; MatOut R; int want_r;
+};
+
+__global__ void __launch_bounds__(QR_NT) k_qr_global(GlobalQrArgs a) {
+    __shared__ double red[QR_NT / 64];
+    __shared__ double2 wpart[QR_NT];
+    const int bt = blockIdx.x;
+    const int m = a.m, n = a.n, k = m < n ? m : n;
+    char *wb = a.ws + (int64_t)bt * a.ws_bs;
+    double2 *X = reinterpret_cast<double2 *>(wb + a.w_off);
+    double2 *Y = reinterpret_cast<double2 *>(wb + a.y_off);
+    double *tau = reinterpret_cast<double *>(wb + a.t_off);
+    double2 *beta = reinterpret_cast<double2 *>(wb + a.b_off);
+    const char *inb = reinterpret_cast<const char *>(a.in.p) + (int64_t)bt * a.in.bs * a.in.esz;
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += QR_NT) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        X[e] = ld_c(inb, a.in.esz, (int64_t)i * a.in.rs + (int64_t)j * a.in.cs, a.in.conj);
+    }
+    __syncthreads();
+    hh_factor(X, m, n, n, beta, tau, red, wpart);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
+        const int i = (int)(e / k), c = (int)(e % k);
+        Y[e] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    hh_apply(Y, m, k, k, X, n, k, tau, wpart);
+    char *qb = reinterpret_cast<char *>(a.Q.p) + (int64_t)bt * a.Q.bs * a.Q.esz;
+    for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
+        const int i = (int)(e / k), c = (int)(e % k);
+        st_c(qb, a.Q.esz, (int64_t)i * a.Q.rs + (int64_t)c * a.Q.cs, Y[e], a.Q.conj);
+    }
+    if (a.want_r) {
+        char *rb = reinterpret_cast<char *>(a.R.p) + (int64_t)bt * a.R.bs * a.R.esz;
+        for (int64_t e = threadIdx.x; e < (int64_t)k * n; e += QR_NT) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            double2 v = make_double2(0.0, 0.0);
+            if (j == i) v = beta[i];
+            else if (j > i) v = X[(int64_t)i * n + j];
+            st_c(rb, a.R.esz, (int64_t)i * a.R.rs + (int64_t)j * a.R.cs, v, a.R.conj);
+        }
+    }
+}
+
+struct TsqrLevel {
+    int rows, nb;
+    size_t v_off, t_off, b_off, rs_off, q_off;  // byte offsets inside one batch item's workspace
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Plans the TSQR tree; returns per-batch workspace bytes.
+size_t plan_tsqr(int m, int n, std::vector<TsqrLevel> &lv) {
+    lv.clear();
+    const int rb = QR_LDS / n;
+    int rows = m;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    while (true) {
+        TsqrLevel L;
+        L.rows = rows;
+        L.nb = (rows + rb - 1) / rb;
+        if (L.nb < 1) L.nb = 1;
+        L.v_off = take((size_t)rows * n * 16);
+        L.t_off = take((size_t)L.nb * n * 8);
+        L.b_off = take((size_t)L.nb * n * 16);
+        L.rs_off = (L.nb > 1) ? take((size_t)L.nb * n * n * 16) : 0;
+        L.q_off = lv.empty() ? 0 : take((size_t)rows * n * 16);
+        lv.push_back(L);
+        if (L.nb == 1) break;
+        rows = L.nb * n;
+    }
+    return off;
+}
+
+bool use_tsqr(int m, int n) { return n <= 64 || (int64_t)m * n <= QR_LDS; }
+
+size_t global_qr_bytes(int m, int n, size_t *w, size_t *y, size_t *t, size_t *b) {
+    const int k = m < n ? m : n;
+    size_t off = 0;
+    *w = off; off += align256((size_t)m * n * 16);
+    *y = off; off += align256((size_t)m * k * 16);
+    *t = off; off += align256((size_t)k * 8);
+    *b = off; off += align256((size_t)k * 16);
+    return off;
+}
+
+}  // namespace
+
+size_t qr_workspace_bytes(int m, int n, int batch) {
+    if (m <= 0 || n <= 0) return 0;
+    std::vector<TsqrLevel> lv;
+    size_t w, y, t, b;
+    const size_t per = use_tsqr(m, n) ? plan_tsqr(m, n, lv) : global_qr_bytes(m, n, &w, &y, &t, &b);
+    return per * (size_t)batch;
+}
+
+hipError_t launch_qr(const QrArgs &q, void *workspace, hipStream_t s) {
+    const int m = q.m, n = q.n;
+    if (m <= 0 || n <= 0 || q.batch <= 0) return hipSuccess;
+    const int k = m < n ? m : n;
+    char *ws = reinterpret_cast<char *>(workspace);
+    MatDesc in{q.A, q.a_esz, q.a_bs, q.a_rs, q.a_cs, q.a_conj};
+    MatOut qo{q.Q, q.q_esz, q.q_bs, q.q_rs, q.q_cs, q.q_conj};
+    MatOut ro{q.R, q.r_esz, q.r_bs, q.r_rs, q.r_cs, q.r_conj};
+    if (!use_tsqr(m, n)) {
+        GlobalQrArgs g;
+        const size_t per = global_qr_bytes(m, n, &g.w_off, &g.y_off, &g.t_off, &g.b_off);
+        g.in = in; g.m = m; g.n = n; g.ws = ws; g.ws_bs = (int64_t)per;
+        g.Q = qo; g.R = ro; g.want_r = q.R != nullptr;
+        hipLaunchKernelGGL(k_qr_global, dim3(q.batch), dim3(QR_NT), 0, s, g);
+        return hipGetLastError();
+    }
+    std::vector<TsqrLevel> lv;
+    const size_t per = plan_tsqr(m, n, lv);
+    const size_t lds_bytes = (size_t)QR_LDS * 16;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_qr_leaf),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_qr_form),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        attr_set = true;
+    }
+    for (size_t L = 0; L < lv.size(); ++L) {
+        LeafArgs a;
+        if (L == 0) a.in = in;
+        else a.in = MatDesc{ws + lv[L - 1].rs_off, 16, (int64_t)(per / 16), n, 1, 0};
+        a.rows = lv[L].rows; a.n = n; a.nb = lv[L].nb; a.top = (L + 1 == lv.size());
+        a.ws = ws; a.ws_bs = (int64_t)per;
+        a.v_off = lv[L].v_off; a.t_off = lv[L].t_off; a.b_off = lv[L].b_off; a.rs_off = lv[L].rs_off;
+        a.R = ro; a.want_r = (q.R != nullptr);
+        hipLaunchKernelGGL(k_qr_leaf, dim3(lv[L].nb, q.batch), dim3(QR_NT), lds_bytes, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    for (int L = (int)lv.size() - 1; L >= 0; --L) {
+        FormArgs f;
+        f.rows = lv[L].rows; f.n = n; f.nb = lv[L].nb; f.k = k;
+        f.top = (L + 1 == (int)lv.size()); f.level0 = (L == 0);
+        f.ws = ws; f.ws_bs = (int64_t)per;
+        f.v_off = lv[L].v_off; f.t_off = lv[L].t_off;
+        f.x_off = f.top ? 0 : lv[L + 1].q_off;
+        f.q_off = lv[L].q_off;
+        f.out = qo;
+        hipLaunchKernelGGL(k_qr_form, dim3(lv[L].nb, q.batch), dim3(QR_NT), lds_bytes, s, f);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tnk

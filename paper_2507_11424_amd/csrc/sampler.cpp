@@ -1,0 +1,322 @@
+// Sequential bitstring sampling from the stored norm boundaries (Appendix,
+// "Sampling from a Tensor Network State", Fig. 7d).
+//
+// Samples run in waves of Z in flight; every per-sample tensor carries a
+// leading sample index z.  For a row b:
+//  * right environments [z, a, b, g, h, k] of (amplitude boundary m, its
+//    conjugate, the row's ket and bra tensors, the stored norm boundary below)
+//    are built right to left;
+//  * qubit by qubit, the left environment is extended with the site projected
+//    on s = 0 and s = 1 in ket and bra (the bra/ket bond of the open site split),
+//    closed against the right environment to give P~(s), the bit is drawn, and
+//    the environment projected on the drawn bit is kept;
+//  * the product of m with the projected row x_b . psi_b is fitted to a new m of
+//    bond <= chi_x by the one-site fit (single layer).
+// q(x) accumulates the drawn conditionals; p(x) is the last amplitude boundary
+// contracted with the last projected row.  Probabilities are FP64; P(s) =
+// max(Re P~(s), 0) / sum, x = 0 iff u < P(0).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tn_core.hpp"
+
+namespace tnb {
+
+namespace {
+
+// [z,a,b,g,h,k] + column -> [z,A,B,G,H,K]; s < 0 sums the physical index.
+Ten env_left(Engine &E, const Ten &L, const Ten &m, const SiteRef &a, const Ten &B, int s) {
+    Ten t1 = E.contract_new(op(L, "zabghk"), op(m, "zauA"), "zbghkuA");
+    Ten out;
+    if (s < 0) {
+        Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop(a, "suhdH"), "zbgkAsdH");
+        E.drop(t1);
+        Ten t3 = E.contract_new(op(t2, "zbgkAsdH"), op(B, "gdeG"), "zbkAsHeG");
+        E.drop(t2);
+        Ten W = E.contract_new(op(m, "zbvB", true), sop(a, "svkeK", true), "zbBskeK");
+        out = E.contract_new(op(t3, "zbkAsHeG"), op(W, "zbBskeK"), "zABGHK");
+        E.drop(t3);
+        E.drop(W);
+    } else {
+        Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop_proj(a, s, "uhdH"), "zbgkAdH");
+        E.drop(t1);
+        Ten t3 = E.contract_new(op(t2, "zbgkAdH"), op(B, "gdeG"), "zbkAHeG");
+        E.drop(t2);
+        Ten W = E.contract_new(op(m, "zbvB", true), sop_proj(a, s, "vkeK", true), "zbBkeK");
+        out = E.contract_new(op(t3, "zbkAHeG"), op(W, "zbBkeK"), "zABGHK");
+        E.drop(t3);
+        E.drop(W);
+    }
+    return out;
+}
+
+// [z,A,B,G,H,K] + column -> [z,a,b,g,h,k] (physical index summed).
+Ten env_right(Engine &E, const Ten &R, const Ten &m, const SiteRef &a, const Ten &B) {
+    Ten t1 = E.contract_new(op(m, "zauA"), op(R, "zABGHK"), "zauBGHK");
+    Ten t2 = E.contract_new(op(t1, "zauBGHK"), sop(a, "suhdH"), "zaBGKshd");
+    E.drop(t1);
+    Ten t3 = E.contract_new(op(t2, "zaBGKshd"), op(B, "gdeG"), "zaBKshge");
+    E.drop(t2);
+    Ten W = E.contract_new(op(m, "zbvB", true), sop(a, "svkeK", true), "zbBskeK");
+    Ten out = E.contract_new(op(t3, "zaBKshge"), op(W, "zbBskeK"), "zabghk");
+    E.drop(t3);
+    E.drop(W);
+    return out;
+}
+
+void unit(Engine &E, Ten &t, int Z, double *logacc = nullptr) {
+    const int64_t per = t.numel() / Z;
+    E.normalise(t.p, t.esz, per, Z, per, logacc, logacc != nullptr, nullptr);
+}
+
+// Single-layer one-site fit of m . X (batched over z) to bond <= chi_x.
+// m[c]: [z, a, u, A]; X[c]: [z, u, h, d, H]; returns [z, y, d, Y]; mlog += log ||.||.
+std::vector<Ten> fit_single(Engine &E, const std::vector<Ten> &m, const std::vector<Ten> &X, const SampleOpts &o,
+                            int row, const uint64_t *sample_idx, double *mlog) {
+    const int L = (int)X.size();
+    const int Z = X[0].d[0];
+    std::vector<int> phys(L);
+    std::vector<int64_t> bin(std::max(L - 1, 0));
+    for (int c = 0; c < L; ++c) phys[c] = X[c].d[3];
+    for (int c = 0; c + 1 < L; ++c) bin[c] = (int64_t)m[c].d[3] * X[c].d[4];
+    bool exact;
+    std::vector<int> t;
+    plan_bonds(phys, bin, o.chi_x, exact, t);
+    std::vector<Ten> Y(L);
+    if (exact && !o.force_fit) {
+        for (int c = 0; c < L; ++c) {
+            Ten e = E.contract_new(op(m[c], "zauA"), op(X[c], "zuhdH"), "zahdAH");
+            e.d = {Z, m[c].d[1] * X[c].d[2], X[c].d[3], m[c].d[3] * X[c].d[4]};
+            Y[c] = e;
+        }
+        canonicalise(E, Y, 1, mlog, true);
+        return Y;
+    }
+    for (int c = 0; c < L; ++c) {
+        const int tl = c > 0 ? t[c - 1] : 1, tr = c + 1 < L ? t[c] : 1;
+        Y[c] = E.make({Z, tl, phys[c], tr});
+        const int64_t per = Y[c].numel() / Z;
+        TN_HIP(tnk::launch_init_tensor(Y[c].p, Y[c].esz, per, Z, per, o.init_seed, 2, (uint64_t)row, (uint64_t)c,
+                                       sample_idx, E.s));
+    }
+    right_canonicalise(E, Y, 1);
+    auto rpart = [&](const Ten &R, int c) {  // [z,a,h,d,Y]
+        Ten t1 = E.contract_new(op(m[c], "zauA"), op(R, "zYAH"), "zauYH");
+        Ten tr = E.contract_new(op(t1, "zauYH"), op(X[c], "zuhdH"), "zahdY");
+        E.drop(t1);
+        return tr;
+    };
+    auto lpart = [&](const Ten &Lf, int c) {  // [z,y,A,d,H]
+        Ten t1 = E.contract_new(op(Lf, "zyah"), op(m[c], "zauA"), "zyhuA");
+        Ten tl = E.contract_new(op(t1, "zyhuA"), op(X[c], "zuhdH"), "zyAdH");
+        E.drop(t1);
+        return tl;
+    };
+    std::vector<Ten> Le(L + 1), Re(L + 1);
+    Re[L] = ones(E, {Z, 1, 1, 1});
+    Le[0] = ones(E, {Z, 1, 1, 1});
+    for (int c = L - 1; c >= 1; --c) {
+        Ten tr = rpart(Re[c + 1], c);
+        Re[c] = E.contract_new(op(Y[c], "zydY", true), op(tr, "zahdY"), "zyah");
+        E.drop(tr);
+    }
+    for (int sw = 0; sw < o.sweeps; ++sw) {
+        for (int c = 0; c + 1 < L; ++c) {
+            Ten tl = lpart(Le[c], c);
+            Ten N = E.contract_new(op(tl, "zyAdH"), op(Re[c + 1], "zYAH"), "zydY");
+            Ten Q;
+            qr_left(E, N, 1, Q, nullptr);
+            E.drop(N);
+            E.drop(Y[c]);
+            Y[c] = Q;
+            if (Le[c + 1].p) E.drop(Le[c + 1]);
+            Le[c + 1] = E.contract_new(op(Y[c], "zydY", true), op(tl, "zyAdH"), "zYAH");
+            E.drop(tl);
+        }
+        for (int c = L - 1; c >= 1; --c) {
+            Ten tr = rpart(Re[c + 1], c);
+            Ten N = E.contract_new(op(Le[c], "zyah"), op(tr, "zahdY"), "zydY");
+            Ten Q;
+            lq_right(E, N, 1, Q, nullptr);
+            E.drop(N);
+            E.drop(Y[c]);
+            Y[c] = Q;
+            if (Re[c].p) E.drop(Re[c]);
+            Re[c] = E.contract_new(op(Y[c], "zydY", true), op(tr, "zahdY"), "zyah");
+            E.drop(tr);
+        }
+    }
+    {
+        Ten tr = rpart(Re[1], 0);
+        Ten N = E.contract_new(op(Le[0], "zyah"), op(tr, "zahdY"), "zydY");
+        E.drop(tr);
+        E.drop(Y[0]);
+        Y[0] = N;
+    }
+    for (auto &x : Le)
+        if (x.p) E.drop(x);
+    for (auto &x : Re)
+        if (x.p) E.drop(x);
+    unit(E, Y[0], Z, mlog);
+    return Y;
+}
+
+// Peak bytes per sample in flight for row sampling (right envs + intermediates).
+double bytes_per_sample(const LView &V, const BoundarySet &B, int chi_x, int esz) {
+    double peak = 0;
+    for (int r = 0; r < V.rows; ++r) {
+        double envs = 0, inter = 0;
+        for (int c = 0; c < V.cols; ++c) {
+            const SiteRef &a = V.at(r, c);
+            const double x = std::min<double>(chi_x, 1 << 20);
+            const double g = B.below[r].site[c].d[0], G = B.below[r].site[c].d[3];
+            const double u = a.dim(1), h = a.dim(2), d = a.dim(3), H = a.dim(4), p = a.dim(0);
+            envs += x * x * G * H * H;
+            const double t2 = x * x * G * H * p * h * d;   // right env S2
+            const double t3 = x * x * H * p * h * g * d;   // right env S3
+            const double w = x * x * p * h * d * H * u;
+            inter = std::max(inter, t2 + t3 + w + x * x * g * h * h * 3);
+        }
+        peak = std::max(peak, envs + inter);
+    }
+    return peak * esz * 1.3;
+}
+
+}  // namespace
+
+void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts &o, uint64_t first, int64_t n,
+            const double *uniforms, uint8_t *bits, double *log_q, double *log_p) {
+    const LView V = make_view(P, 0);
+    const int rows = V.rows, cols = V.cols;
+    int Zw = o.wave;
+    if (Zw <= 0) {
+        size_t freeb = 0, total = 0;
+        TN_HIP(hipMemGetInfo(&freeb, &total));
+        const double per = bytes_per_sample(V, B, o.chi_x, E.esz);
+        const double budget = 0.5 * (double)freeb + 0.5 * (double)E.held();
+        Zw = (int)std::max(1.0, std::min(4096.0, std::floor(budget / std::max(per, 1.0))));
+    }
+    Zw = (int)std::min<int64_t>(Zw, n);
+    // per-wave device state
+    uint64_t *sidx = reinterpret_cast<uint64_t *>(E.raw((size_t)Zw * 8));
+    double *mlog = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
+    double *pt = reinterpret_cast<double *>(E.raw((size_t)Zw * 32));
+    int *flags = reinterpret_cast<int *>(E.raw((size_t)Zw * 4));
+    int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
+    double *amp = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    std::vector<uint64_t> hidx(Zw);
+    std::vector<int> hflags(Zw);
+    try {
+        for (int64_t w0 = 0; w0 < n; w0 += Zw) {
+            const int Z = (int)std::min<int64_t>(Zw, n - w0);
+            for (int z = 0; z < Z; ++z) hidx[z] = first + (uint64_t)(w0 + z);
+            TN_HIP(hipMemcpyAsync(sidx, hidx.data(), (size_t)Z * 8, hipMemcpyHostToDevice, E.s));
+            TN_HIP(hipMemsetAsync(mlog, 0, (size_t)Z * 8, E.s));
+            TN_HIP(hipMemsetAsync(flags, 0, (size_t)Z * 4, E.s));
+            TN_HIP(hipMemsetAsync(log_q + w0, 0, (size_t)Z * 8, E.s));
+            std::vector<Ten> m(cols);
+            for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
+            for (int r = 0; r < rows; ++r) {
+                const DMps &Bb = B.below[r];
+                std::vector<Ten> R(cols + 1);
+                R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
+                for (int c = cols - 1; c >= 1; --c) {
+                    R[c] = env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
+                    unit(E, R[c], Z);
+                }
+                Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
+                for (int c = 0; c < cols; ++c) {
+                    const SiteRef &a = V.at(r, c);
+                    int *xs = xsel + (size_t)c * Zw;
+                    if (a.dim(0) == 1) {
+                        Ten L2 = env_left(E, Lc, m[c], a, Bb.site[c], -1);
+                        E.drop(Lc);
+                        Lc = L2;
+                        unit(E, Lc, Z);
+                        TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
+                        continue;
+                    }
+                    Ten L0 = env_left(E, Lc, m[c], a, Bb.site[c], 0);
+                    Ten L1 = env_left(E, Lc, m[c], a, Bb.site[c], 1);
+                    const int64_t per = L0.numel() / Z;
+                    E.dot(L0.p, R[c + 1].p, L0.esz, per, Z, per, pt);
+                    E.dot(L1.p, R[c + 1].p, L1.esz, per, Z, per, pt + 2 * Zw);
+                    tnk::DrawArgs d{};
+                    d.batch = Z;
+                    d.pt0 = pt;
+                    d.pt1 = pt + 2 * Zw;
+                    d.uniforms = uniforms;
+                    d.u_row0 = w0;
+                    d.n_qubits = P.nq;
+                    d.qubit = P.site_index[(size_t)r * cols + c];
+                    d.seed = o.seed;
+                    d.sample_index = sidx;
+                    d.bits = bits;
+                    d.bits_row0 = w0;
+                    d.log_q = log_q + w0;
+                    d.xsel = xs;
+                    d.flags = flags;
+                    TN_HIP(tnk::launch_draw(d, E.s));
+                    // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
+                    E.drop(Lc);
+                    Lc = E.make(L0.d);
+                    TN_HIP(tnk::launch_select2(L0.p, L1.p, L0.esz, per, per, xs, Z, Lc.p, E.s));
+                    E.drop(L0);
+                    E.drop(L1);
+                    unit(E, Lc, Z);
+                }
+                E.drop(Lc);
+                for (auto &x : R)
+                    if (x.p) E.drop(x);
+                // projected row X_c[z] = A_c[x_c(z)], dims [z, u, h, d, H]
+                std::vector<Ten> X(cols);
+                for (int c = 0; c < cols; ++c) {
+                    const SiteRef &a = V.at(r, c);
+                    X[c] = E.make({Z, a.dim(1), a.dim(2), a.dim(3), a.dim(4)});
+                    const int64_t per = X[c].numel() / Z;
+                    TN_HIP(tnk::launch_select_copy(a.t->p, a.t->esz, per, per, 0, xsel + (size_t)c * Zw, Z, X[c].p,
+                                                   per, E.s));
+                }
+                if (r + 1 < rows) {
+                    std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
+                    for (auto &x : m) E.drop(x);
+                    m = mn;
+                } else {
+                    // amplitude <x|psi> from the last boundary and the last projected row
+                    Ten v = ones(E, {Z, 1, 1});
+                    for (int c = 0; c < cols; ++c) {
+                        Ten t1 = E.contract_new(op(v, "zah"), op(m[c], "zauA"), "zhuA");
+                        Ten Xc = X[c];
+                        Xc.d = {Z, X[c].d[1], X[c].d[2], X[c].d[4]};  // the last row has d = 1
+                        Ten v2 = E.contract_new(op(t1, "zhuA"), op(Xc, "zuhH"), "zAH");
+                        E.drop(t1);
+                        E.drop(v);
+                        v = v2;
+                        if (c + 1 < cols) unit(E, v, Z, mlog);
+                    }
+                    if (log_p) {
+                        TN_HIP(tnk::launch_convert(v.p, v.esz, amp, 16, Z, E.s));
+                        TN_HIP(tnk::launch_logp(amp, mlog, Z, log_p + w0, E.s));
+                    }
+                    E.drop(v);
+                }
+                for (auto &x : X) E.drop(x);
+            }
+            for (auto &x : m) E.drop(x);
+            TN_HIP(hipMemcpyAsync(hflags.data(), flags, (size_t)Z * 4, hipMemcpyDeviceToHost, E.s));
+            E.sync();
+            for (int z = 0; z < Z; ++z)
+                if (hflags[z])
+                    throw TnError(ST_NUMERIC, "sample " + std::to_string(first + w0 + z) +
+                                                  ((hflags[z] & 2) ? ": non-positive or non-finite marginal"
+                                                                   : ": environment vanished or overflowed"));
+        }
+    } catch (...) {
+        E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+        throw;
+    }
+    E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+}
+
+}  // namespace tnb

@@ -1,0 +1,341 @@
+// Small kernels around the contraction engine: FP64 norms and renormalisation
+// (log-scale bookkeeping of the boundary MPSs), element-type conversion, the
+// Philox4x64-10 generator (Salmon et al., SC'11) for random initial guesses and
+// for the sampler's draws, the draw itself, and output bookkeeping.
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace tnk {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double2 ldc(const void *p, int esz, int64_t i) {
+    if (esz == 16) return reinterpret_cast<const double2 *>(p)[i];
+    const float2 f = reinterpret_cast<const float2 *>(p)[i];
+    return make_double2(f.x, f.y);
+}
+__device__ inline void stc(void *p, int esz, int64_t i, double2 v) {
+    if (esz == 16) reinterpret_cast<double2 *>(p)[i] = v;
+    else reinterpret_cast<float2 *>(p)[i] = make_float2((float)v.x, (float)v.y);
+}
+
+__device__ inline double wsum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block in a fixed order (deterministic).
+__device__ inline double bsum(double v) {
+    __shared__ double red[NT / 64];
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+__global__ void __launch_bounds__(NT) k_norm2_part(const void *x, int esz, int64_t n, int64_t bs,
+                                                  int P, double *partial) {
+    const int b = blockIdx.y;
+    const char *xb = reinterpret_cast<const char *>(x) + (int64_t)b * bs * esz;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)P * NT) {
+        const double2 v = ldc(xb, esz, i);
+        s += v.x * v.x + v.y * v.y;
+    }
+    s = bsum(s);
+    if (threadIdx.x == 0) partial[(int64_t)b * P + blockIdx.x] = s;
+}
+
+__global__ void k_sum_parts(const double *partial, int P, int batch, double *out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double s = 0.0;
+    for (int i = 0; i < P; ++i) s += partial[(int64_t)b * P + i];
+    out[b] = s;
+}
+
+__global__ void __launch_bounds__(NT) k_normalise(void *x, int esz, int64_t n, int64_t bs,
+                                                 const double *norm2, double *logscale, int acc,
+                                                 int *flags) {
+    const int b = blockIdx.y;
+    const double q = norm2[b];
+    const bool bad = !(q > 0.0) || !isfinite(q);
+    const double f = bad ? 1.0 : 1.0 / sqrt(q);
+    char *xb = reinterpret_cast<char *>(x) + (int64_t)b * bs * esz;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        double2 v = ldc(xb, esz, i);
+        v.x *= f; v.y *= f;
+        stc(xb, esz, i, v);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (logscale) logscale[b] = (acc ? logscale[b] : 0.0) + (bad ? 0.0 : 0.5 * log(q));
+        if (bad && flags) flags[b] |= 1;
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_convert(const void *src, int se, void *dst, int de, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        stc(dst, de, i, ldc(src, se, i));
+}
+
+__global__ void __launch_bounds__(NT) k_fill(void *x, int esz, int64_t n, double re, double im) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        stc(x, esz, i, make_double2(re, im));
+}
+
+// Philox4x64-10: ten rounds of two 64x64 -> 128-bit products with a Weyl key schedule.
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+__device__ inline double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
+
+__global__ void __launch_bounds__(NT) k_init(void *out, int esz, int64_t n, int64_t bs, uint64_t seed,
+                                            uint64_t tag, uint64_t row, uint64_t site,
+                                            const uint64_t *sample) {
+    const int b = blockIdx.y;
+    const uint64_t smp = sample ? sample[b] : 0ull;
+    char *ob = reinterpret_cast<char *>(out) + (int64_t)b * bs * esz;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        uint64_t c[4] = {(uint64_t)i, site, row, smp};
+        philox4x64_10(c, seed, tag);
+        stc(ob, esz, i, make_double2(2.0 * u53(c[0]) - 1.0, 2.0 * u53(c[1]) - 1.0));
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_dot_part(const void *x, const void *y, int esz, int64_t n,
+                                                int64_t bs, int P, double *partial) {
+    const int b = blockIdx.y;
+    const char *xb = reinterpret_cast<const char *>(x) + (int64_t)b * bs * esz;
+    const char *yb = reinterpret_cast<const char *>(y) + (int64_t)b * bs * esz;
+    double sr = 0.0, si = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)P * NT) {
+        const double2 a = ldc(xb, esz, i), c = ldc(yb, esz, i);
+        sr += a.x * c.x - a.y * c.y;
+        si += a.x * c.y + a.y * c.x;
+    }
+    sr = bsum(sr);
+    si = bsum(si);
+    if (threadIdx.x == 0) {
+        partial[((int64_t)b * P + blockIdx.x) * 2] = sr;
+        partial[((int64_t)b * P + blockIdx.x) * 2 + 1] = si;
+    }
+}
+
+__global__ void k_sum_parts2(const double *partial, int P, int batch, double *out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double sr = 0.0, si = 0.0;
+    for (int i = 0; i < P; ++i) {
+        sr += partial[((int64_t)b * P + i) * 2];
+        si += partial[((int64_t)b * P + i) * 2 + 1];
+    }
+    out[2 * b] = sr;
+    out[2 * b + 1] = si;
+}
+
+__global__ void k_draw(DrawArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.batch) return;
+    const double r0 = a.pt0[2 * b], r1 = a.pt1[2 * b];
+    const double p0 = r0 > 0.0 ? r0 : 0.0;
+    const double p1 = r1 > 0.0 ? r1 : 0.0;
+    const double tot = p0 + p1;
+    int x = 0;
+    double lp = 0.0;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+        a.flags[b] |= 2;
+    } else {
+        const double P0 = p0 / tot;
+        double u;
+        if (a.uniforms) {
+            u = a.uniforms[(a.u_row0 + b) * (int64_t)a.n_qubits + a.qubit];
+        } else {
+            uint64_t c[4] = {(uint64_t)a.qubit, a.sample_index[b], 0ull, 0ull};
+            philox4x64_10(c, a.seed, 3ull);
+            u = u53(c[0]);
+        }
+        x = (u < P0) ? 0 : 1;
+        lp = log(x == 0 ? P0 : p1 / tot);
+    }
+    a.log_q[b] += lp;
+    a.bits[(a.bits_row0 + b) * (int64_t)a.n_qubits + a.qubit] = (uint8_t)x;
+    a.xsel[b] = x;
+}
+
+__global__ void k_select_offsets(const int *xsel, int batch, int64_t base, int64_t stride, int64_t *dst) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) dst[b] = base + (int64_t)xsel[b] * stride;
+}
+
+__global__ void __launch_bounds__(NT) k_select_copy(const void *x, int esz, int64_t n, int64_t ss,
+                                                   int64_t bs, const int *sel, void *out, int64_t obs) {
+    const int b = blockIdx.y;
+    const int64_t src = (int64_t)b * bs + (int64_t)sel[b] * ss;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        stc(out, esz, (int64_t)b * obs + i, ldc(x, esz, src + i));
+}
+
+__global__ void __launch_bounds__(NT) k_select2(const void *x0, const void *x1, int esz, int64_t n, int64_t bs,
+                                               const int *sel, void *out) {
+    const int b = blockIdx.y;
+    const void *x = sel[b] ? x1 : x0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        stc(out, esz, (int64_t)b * bs + i, ldc(x, esz, (int64_t)b * bs + i));
+}
+
+__global__ void __launch_bounds__(NT) k_fill_f64(double *x, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) x[i] = v;
+}
+
+__global__ void k_env_rho(const double *d, double *out) {
+    const int i = threadIdx.x;  // 4 entries
+    const double tr = d[0] + d[6], ti = d[1] + d[7];
+    const double den = tr * tr + ti * ti;
+    if (i < 4) {
+        const double a = d[2 * i], b = d[2 * i + 1];
+        out[2 * i] = (a * tr + b * ti) / den;
+        out[2 * i + 1] = (b * tr - a * ti) / den;
+    }
+}
+
+__global__ void k_env_p2(const double *d, double *p2, double *zz) {
+    if (threadIdx.x != 0) return;
+    const double P0 = d[0], P1 = d[2], P2 = d[4], P3 = d[6];
+    const double S = P0 + P1 + P2 + P3;
+    if (p2) { p2[0] = P0 / S; p2[1] = P1 / S; p2[2] = P2 / S; p2[3] = P3 / S; }
+    if (zz) *zz = (P0 - P1 - P2 + P3) / S;
+}
+
+__global__ void k_logp(const double *amp, const double *mlog, int batch, double *log_p) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const double a = hypot(amp[2 * b], amp[2 * b + 1]);
+    log_p[b] = a > 0.0 ? 2.0 * (mlog[b] + log(a)) : -INFINITY;
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + NT - 1) / NT;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+int reduce_partial_count(int64_t n) {
+    int64_t p = (n + 16383) / 16384;
+    if (p < 1) p = 1;
+    if (p > 256) p = 256;
+    return (int)p;
+}
+
+hipError_t launch_norm2(const void *x, int esz, int64_t n, int batch, int64_t bs, double *partial,
+                        double *out, hipStream_t s) {
+    const int P = reduce_partial_count(n);
+    hipLaunchKernelGGL(k_norm2_part, dim3(P, batch), dim3(NT), 0, s, x, esz, n, bs, P, partial);
+    hipLaunchKernelGGL(k_sum_parts, dim3((batch + 63) / 64), dim3(64), 0, s, partial, P, batch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalise(void *x, int esz, int64_t n, int batch, int64_t bs, const double *norm2,
+                            double *logscale, int acc, int *flags, hipStream_t s) {
+    int g = grid_for(n);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_normalise, dim3(g, batch), dim3(NT), 0, s, x, esz, n, bs, norm2, logscale, acc, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, int se, void *dst, int de, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_convert, dim3(grid_for(n)), dim3(NT), 0, s, src, se, dst, de, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *x, int esz, int64_t n, double re, double im, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(NT), 0, s, x, esz, n, re, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_tensor(void *out, int esz, int64_t n, int batch, int64_t bs, uint64_t seed,
+                              uint64_t tag, uint64_t row, uint64_t site, const uint64_t *sample,
+                              hipStream_t s) {
+    if (n <= 0 || batch <= 0) return hipSuccess;
+    int g = grid_for(n);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_init, dim3(g, batch), dim3(NT), 0, s, out, esz, n, bs, seed, tag, row, site, sample);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const void *x, const void *y, int esz, int64_t n, int batch, int64_t bs,
+                      double *partial, double *out, hipStream_t s) {
+    const int P = reduce_partial_count(n);
+    hipLaunchKernelGGL(k_dot_part, dim3(P, batch), dim3(NT), 0, s, x, y, esz, n, bs, P, partial);
+    hipLaunchKernelGGL(k_sum_parts2, dim3((batch + 63) / 64), dim3(64), 0, s, partial, P, batch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_draw(const DrawArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_draw, dim3((a.batch + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_offsets(const int *xsel, int batch, int64_t base, int64_t stride, int64_t *dst,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_select_offsets, dim3((batch + 63) / 64), dim3(64), 0, s, xsel, batch, base, stride, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_copy(const void *x, int esz, int64_t n, int64_t ss, int64_t bs, const int *sel,
+                              int batch, void *out, int64_t obs, hipStream_t s) {
+    int g = grid_for(n);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_select_copy, dim3(g, batch), dim3(NT), 0, s, x, esz, n, ss, bs, sel, out, obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_select2(const void *x0, const void *x1, int esz, int64_t n, int64_t bs, const int *sel,
+                          int batch, void *out, hipStream_t s) {
+    int g = grid_for(n);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_select2, dim3(g, batch), dim3(NT), 0, s, x0, x1, esz, n, bs, sel, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(NT), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_env_rho, dim3(1), dim3(64), 0, s, dots, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t s) {
+    hipLaunchKernelGGL(k_env_p2, dim3(1), dim3(64), 0, s, dots, p2, zz);
+    return hipGetLastError();
+}
+
+hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, hipStream_t s) {
+    hipLaunchKernelGGL(k_logp, dim3((batch + 63) / 64), dim3(64), 0, s, amp, mlog, batch, log_p);
+    return hipGetLastError();
+}
+
+}  // namespace tnk

@@ -1,0 +1,89 @@
+// Boundary-MPS contraction and sampling on the engine (host orchestration).
+#pragma once
+
+#include "engine.hpp"
+
+namespace tnb {
+
+// Site tensors staged in the compute precision, dims {p, u, l, d, r}.
+struct PepsDev {
+    int rows = 0, cols = 0, nq = 0;
+    std::vector<Ten> site;
+    std::vector<int> phys, site_index;
+    const Ten &at(int r, int c) const { return site[(size_t)r * cols + c]; }
+};
+
+// A site seen through a lattice transformation: view slot i (0..4 = s,u,l,d,r)
+// reads slot perm[i] of the stored tensor.  No data is moved.
+struct SiteRef {
+    const Ten *t = nullptr;
+    int perm[5] = {0, 1, 2, 3, 4};
+    int dim(int i) const { return t->d[perm[i]]; }
+};
+
+struct LView {
+    int rows = 0, cols = 0;
+    std::vector<SiteRef> s;
+    const SiteRef &at(int r, int c) const { return s[(size_t)r * cols + c]; }
+};
+
+// direction 0: rows as stored; 1: mirrored top-bottom; 2: rows and columns
+// exchanged; 3: exchanged then mirrored.
+LView make_view(const PepsDev &P, int direction);
+Op sop(const SiteRef &a, const std::string &letters5, bool conj = false);
+// Physical index fixed to s: letters for (u, l, d, r).
+Op sop_proj(const SiteRef &a, int s, const std::string &letters4, bool conj = false);
+
+struct FitOpts {
+    int chi = 16;
+    int sweeps = 2;
+    bool force_fit = false;
+    uint64_t seed = 0;
+};
+
+// Double-layer boundary MPS, site c dims {yl, u, v, yr} (ket phys u, bra phys v).
+struct DMps {
+    std::vector<Ten> site;
+};
+
+struct BoundarySet {
+    std::vector<DMps> below;   // below[r] approximates the rows under row r
+    double *logs = nullptr;    // device [rows]: log of the norm divided out of below[r]
+    std::vector<int> mode;     // per r: 1 exact product, 2 fitted
+    int rows = 0;
+};
+
+void free_mps(Engine &E, DMps &m);
+Ten ones(Engine &E, const std::vector<int> &dims);
+// QR of T as batch x m x n (first nb dims batch, n = last dim); R optional.
+void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R);
+// LQ of T as batch x m x n (m = dim nb, n = the rest); L optional.
+void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *L);
+// Canonical form by QR then LQ sweeps, centre (site 0) normalised into logscale.
+void canonicalise(Engine &E, std::vector<Ten> &Y, int nb, double *logscale, bool acc);
+void right_canonicalise(Engine &E, std::vector<Ten> &Y, int nb);
+void free_set(Engine &E, BoundarySet &b);
+
+void plan_bonds(const std::vector<int> &phys, const std::vector<int64_t> &bond_in, int chi,
+                bool &exact_ok, std::vector<int> &t);
+
+BoundarySet boundary_set(Engine &E, const LView &V, const FitOpts &o, uint64_t tag);
+// log|Z| and arg Z from closing row 0 of the view against below[0]; synchronises.
+void norm_close(Engine &E, const LView &V, const BoundarySet &B, double *logabs, double *arg);
+
+void environments(Engine &E, const PepsDev &P, const FitOpts &o, double *rho1, double *zz_h,
+                  double *zz_v, double *p2_h, double *p2_v);
+
+struct SampleOpts {
+    int chi_x = 16;
+    int sweeps = 2;
+    bool force_fit = false;
+    uint64_t init_seed = 0;
+    uint64_t seed = 0;
+    int wave = 0;  // samples per wave (0 = automatic)
+};
+
+void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts &o, uint64_t first,
+            int64_t n, const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
+
+}  // namespace tnb

@@ -1,0 +1,112 @@
+"""Numerics of the HIP engine primitives through the C ABI test hooks:
+the complex contraction kernel in every precision against a float64 NumPy
+einsum, and the FP64 Householder QR (orthogonality, reconstruction, triangular R)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 3e-6, "bf16x3": 3e-5, "bf16x6": 3e-6}
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import paper_2507_11424_amd as tnb
+    h = tnb.Handle(0)
+    yield h
+    h.close()
+
+
+def _rand(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2)
+
+
+CASES = [
+    # (A letters, B letters, C letters, dims) -- shapes span several tiles and ragged tails
+    ("ik", "kj", "ij", dict(i=130, k=70, j=97)),
+    ("ik", "kj", "ji", dict(i=130, k=70, j=97)),          # output contiguous along M (swap path)
+    ("yghk", "gdeG", "yhkdeG", dict(y=9, g=7, h=3, k=3, d=2, e=2, G=11)),
+    ("ykeGsuH", "svkeK", "yGuHvK", dict(y=5, k=3, e=2, G=6, s=2, u=3, H=3, v=3, K=3)),
+    ("zab", "zbc", "zac", dict(z=5, a=33, b=17, c=65)),   # batched
+    ("zbghkuA", "suhdH", "zbgkAsdH", dict(z=3, b=4, g=5, h=2, k=2, u=2, A=6, s=2, d=2, H=3)),
+    ("ik", "kj", "ij", dict(i=1, k=300, j=1)),            # dot product
+    ("ik", "kj", "ij", dict(i=2000, k=5, j=16)),          # skinny N
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("conj", [(False, False), (True, False), (False, True)])
+def test_contract_matches_einsum(handle, prec, case, conj):
+    import torch
+    ia, ib, ic, dims = CASES[case]
+    rng = np.random.default_rng(100 + case)
+    A = _rand(rng, [dims[c] for c in ia])
+    B = _rand(rng, [dims[c] for c in ib])
+    ref = np.einsum(f"{ia},{ib}->{ic}", A.conj() if conj[0] else A, B.conj() if conj[1] else B)
+    td = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+        ref = np.einsum(f"{ia},{ib}->{ic}", A.conj() if conj[0] else A, B.conj() if conj[1] else B)
+    dA = torch.from_numpy(A).to("cuda", td)
+    dB = torch.from_numpy(B).to("cuda", td)
+    dC = torch.zeros([dims[c] for c in ic], dtype=td, device="cuda")
+    handle.test_contract(prec, ia, dA, ib, dB, ic, dC, conjA=conj[0], conjB=conj[1])
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.complex128)
+    # error relative to the scale of the products (sum of |a||b| terms)
+    scale = np.einsum(f"{ia},{ib}->{ic}", np.abs(A), np.abs(B))
+    err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+    assert err < TOL[prec], err
+
+
+def test_contract_accumulate(handle):
+    import torch
+    rng = np.random.default_rng(7)
+    A, B, C0 = _rand(rng, (70, 40)), _rand(rng, (40, 90)), _rand(rng, (70, 90))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.from_numpy(C0.copy()).cuda()
+    handle.test_contract("fp64", "ik", dA, "kj", dB, "ij", dC, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.abs(dC.cpu().numpy() - (C0 + A @ B)).max() < 1e-11
+
+
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 2), (700, 33, 3), (16, 64, 1), (128, 64, 1),
+                                       (300, 100, 1), (1, 1, 1), (5, 3, 4), (20000, 8, 1)])
+@pytest.mark.parametrize("esz", [16, 8])
+def test_qr(handle, m, n, batch, esz):
+    import torch
+    rng = np.random.default_rng(m * 7 + n)
+    A = _rand(rng, (batch, m, n))
+    if esz == 8:
+        A = A.astype(np.complex64).astype(np.complex128)
+    td = torch.complex128 if esz == 16 else torch.complex64
+    k = min(m, n)
+    dA = torch.from_numpy(A).to("cuda", td)
+    dQ = torch.zeros((batch, m, k), dtype=td, device="cuda")
+    dR = torch.zeros((batch, k, n), dtype=td, device="cuda")
+    handle.test_qr(dA, dQ, dR)
+    torch.cuda.synchronize()
+    Q = dQ.cpu().numpy().astype(np.complex128)
+    R = dR.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if esz == 16 else 2e-6
+    for b in range(batch):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(k)).max() < tol * max(m, 16)
+        assert np.abs(Q[b] @ R[b] - A[b]).max() < tol * max(m, 16) * np.abs(A[b]).max()
+        assert np.abs(np.tril(R[b], -1)).max() == 0.0
+
+
+def test_qr_rank_deficient(handle):
+    import torch
+    rng = np.random.default_rng(3)
+    A = _rand(rng, (1, 512, 8)) @ _rand(rng, (1, 8, 64))  # rank 8
+    A[0, :, 5] = 0
+    dA = torch.from_numpy(A).cuda()
+    dQ = torch.zeros((1, 512, 64), dtype=torch.complex128, device="cuda")
+    dR = torch.zeros((1, 64, 64), dtype=torch.complex128, device="cuda")
+    handle.test_qr(dA, dQ, dR)
+    torch.cuda.synchronize()
+    Q, R = dQ.cpu().numpy()[0], dR.cpu().numpy()[0]
+    assert np.all(np.isfinite(Q))
+    assert np.abs(Q @ R - A[0]).max() < 1e-10 * np.abs(A).max()

@@ -1,0 +1,134 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs: norms in all four contraction directions, environments, and
+samples (bits, log q, log p), in exact and truncated regimes, FP64 and the
+reduced-precision GEMM modes."""
+import math
+
+import numpy as np
+import pytest
+
+from peps_inputs import square_lattice, brick_lattice, random_peps, make_config, sample_uniforms
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import paper_2507_11424_amd as tnb
+    h = tnb.Handle(0)
+    yield h
+    h.close()
+
+
+def dev_peps(lat, T, dtype="c128"):
+    import paper_2507_11424_amd as tnb
+    return tnb.Peps.from_numpy(lat, T, dtype=dtype)
+
+
+def opts(**kw):
+    import paper_2507_11424_amd as tnb
+    return tnb.make_opts(**kw)
+
+
+STATES = {
+    "c1": lambda: make_config("c1")[:2],
+    "sq4x4D3": lambda: (lambda l: (l, random_peps(l, "haar", 0.6, 51)))(square_lattice(4, 4, 3)),
+    "brick5x4D2": lambda: (lambda l: (l, random_peps(l, "haar", 0.5, 52)))(brick_lattice(5, 4, 2)),
+    "sq3x5D2": lambda: (lambda l: (l, random_peps(l, "product0", 0.4, 53)))(square_lattice(3, 5, 2)),
+}
+
+
+@pytest.mark.parametrize("name,chi", [("c1", 16), ("sq4x4D3", 4), ("sq4x4D3", 9), ("brick5x4D2", 3),
+                                      ("sq3x5D2", 2), ("sq4x4D3", 81)])
+@pytest.mark.parametrize("direction", [0, 1, 2, 3])
+@pytest.mark.parametrize("force_fit", [False, True])
+def test_norm_fp64(handle, name, chi, direction, force_fit):
+    lat, T = STATES[name]()
+    ref = oracle.norm(T, chi, sweeps=2, seed=0, direction=direction, force_fit=force_fit)
+    got = handle.boundary_contract(dev_peps(lat, T), opts(chi=chi, direction=direction, force_fit=force_fit))
+    assert abs(got[0] - ref[0]) < 1e-10, (got, ref)
+    assert abs(got[1] - ref[1]) < 1e-9
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_norm_sweeps_and_seed(handle, sweeps):
+    lat, T = STATES["sq4x4D3"]()
+    ref = oracle.norm(T, 5, sweeps=sweeps, seed=77)
+    got = handle.boundary_contract(dev_peps(lat, T), opts(chi=5, sweeps=sweeps, init_seed=77))
+    assert abs(got[0] - ref[0]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4), ("bf16x6", 1e-5)])
+def test_norm_reduced_precision(handle, prec, tol):
+    lat, T = STATES["sq4x4D3"]()
+    T64 = [[t.astype(np.complex64).astype(np.complex128) for t in row] for row in T]
+    ref = oracle.norm(T64, 9)
+    got = handle.boundary_contract(dev_peps(lat, T64, "c64"), opts(chi=9, prec=prec))
+    assert abs(got[0] - ref[0]) < tol, (got, ref)
+
+
+def test_norm_c2_chi32(handle):
+    lat, T, cfg = make_config("c2")
+    ref = oracle.norm(T, 32)
+    got = handle.boundary_contract(dev_peps(lat, T), opts(chi=32))
+    assert abs(got[0] - ref[0]) < 1e-10, (got, ref)
+
+
+@pytest.mark.parametrize("name,chi", [("c1", 16), ("sq4x4D3", 4), ("brick5x4D2", 3)])
+def test_environments_fp64(handle, name, chi):
+    lat, T = STATES[name]()
+    ref = oracle.environments(T, chi)
+    got = handle.environments(dev_peps(lat, T), opts(chi=chi))
+    rho = got["rho1"].cpu().numpy()
+    assert np.nanmax(np.abs(rho - ref["rho1"])) < 1e-10
+    assert np.array_equal(np.isnan(rho.real), np.isnan(ref["rho1"].real))
+    for k in ("zz_h", "zz_v", "p2_h", "p2_v"):
+        g = got[k].cpu().numpy()
+        assert np.nanmax(np.abs(g - ref[k])) < 1e-10, k
+
+
+@pytest.mark.parametrize("name,chi,chi_x,force", [("c1", 16, 16, False), ("c1", 16, 16, True),
+                                                   ("sq4x4D3", 4, 3, False), ("brick5x4D2", 3, 2, False),
+                                                   ("sq3x5D2", 2, 2, True)])
+@pytest.mark.parametrize("given_uniforms", [True, False])
+def test_sample_fp64(handle, name, chi, chi_x, force, given_uniforms):
+    import torch
+    lat, T = STATES[name]()
+    n = 24
+    u = sample_uniforms(9, n, lat.n_qubits) if given_uniforms else None
+    rb, rq, rp = oracle.sample(T, lat.site_index, chi, chi_x, n, seed=123, first=5, force_fit=force,
+                               uniforms=u)
+    P = dev_peps(lat, T)
+    o = opts(chi=chi, chi_x=chi_x, force_fit=force)
+    bits, lq, lp = handle.sample(P, o, n, seed=123, first=5,
+                                 uniforms=torch.from_numpy(u) if u is not None else None)
+    bits, lq, lp = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy()
+    assert np.array_equal(bits, rb)
+    assert np.abs(lq - rq).max() < 1e-9
+    assert np.abs(lp - rp).max() < 1e-9
+
+
+def test_sample_split_runs_reproduce_one_run(handle):
+    lat, T = STATES["sq4x4D3"]()
+    P = dev_peps(lat, T)
+    o = opts(chi=4, chi_x=3)
+    b_all, q_all, _ = handle.sample(P, o, 20, seed=5, first=0)
+    b1, q1, _ = handle.sample(P, o, 7, seed=5, first=0)
+    b2, q2, _ = handle.sample(P, o, 13, seed=5, first=7)
+    import torch
+    assert torch.equal(torch.cat([b1, b2]), b_all)
+    assert torch.equal(torch.cat([q1, q2]), q_all)
+
+
+def test_sample_exact_matches_statevector(handle):
+    lat, T, cfg = make_config("c1")
+    psi = oracle.statevector(T, lat.site_index)
+    p = np.abs(psi) ** 2
+    Z = p.sum()
+    bits, lq, lp = handle.sample(dev_peps(lat, T), opts(chi=16, chi_x=16), 200, seed=11)
+    bits, lq, lp = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy()
+    for b, q, pp in zip(bits, lq, lp):
+        x = tuple(int(v) for v in b)
+        assert abs(q - math.log(p[x] / Z)) < 1e-10
+        assert abs(pp - math.log(p[x])) < 1e-10
