@@ -26,9 +26,14 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 
 template <typename T> struct Tr;
+// Accumulator layout of the 16x16 MFMA forms: lane l, register r holds row
+//   FP64 (16x16x4 f64):      4 r + l / 16
+//   FP32 / BF16 16x16 forms: 4 (l / 16) + r
+// and column l % 16 in both.
 template <> struct Tr<double> {
     using C2 = double2;
     using Acc = v4d;
+    __device__ static inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
     __device__ static inline Acc mma(double a, double b, Acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -36,6 +41,7 @@ template <> struct Tr<double> {
 template <> struct Tr<float> {
     using C2 = float2;
     using Acc = v4f;
+    __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
     __device__ static inline Acc mma(float a, float b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -173,7 +179,7 @@ gett_mfma(GettArgs p) {
                     }
             }
         }
-        // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+        // epilogue: see Tr<T>::row for the accumulator layout
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int n = n0 + wn * WTN + j * 16 + (lane & 15);
@@ -183,7 +189,7 @@ gett_mfma(GettArgs p) {
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + r;
+                    const int m = m0 + wm * WTM + i * 16 + Tr<T>::row(lane, r);
                     if (m >= p.M) continue;
                     C2 *dst = Cb + p.c_moff[m] + cn;
                     C2 v;

@@ -65,6 +65,60 @@ Ten env_right(Engine &E, const Ten &R, const Ten &m, const SiteRef &a, const Ten
     return out;
 }
 
+// Sites without an up bond (u = 1) let the ket and bra row tensors and the norm
+// boundary below be contracted into a sample-independent column transfer
+// matrix T_s[g,h,k,G,H,K] = sum_{d,e} B[g,d,e,G] A[s,h,d,H] conj(A[s,k,e,K])
+// (s < 0: summed over s).  An environment step is then one square GEMM over
+// (g,h,k) shared by every sample of the wave, instead of contracting B, A and
+// conj(A) per sample.
+Ten transfer(Engine &E, const SiteRef &a, const Ten &B, int s) {
+    if (s < 0) {
+        Ten x1 = E.contract_new(op(B, "gdeG"), sop(a, "suhdH"), "geGshH");
+        Ten T = E.contract_new(op(x1, "geGshH"), sop(a, "sukeK", true), "ghkGHK");
+        E.drop(x1);
+        return T;
+    }
+    Ten x1 = E.contract_new(op(B, "gdeG"), sop_proj(a, s, "uhdH"), "geGhH");
+    Ten T = E.contract_new(op(x1, "geGhH"), sop_proj(a, s, "ukeK", true), "ghkGHK");
+    E.drop(x1);
+    return T;
+}
+
+// Left step through a u = 1 site with its transfer matrix: [z,a,b,g,h,k] -> [z,A,B,G,H,K].
+Ten env_left_T(Engine &E, const Ten &L, const Ten &m, const Ten &T) {
+    Ten t1 = E.contract_new(op(L, "zabghk"), op(m, "zauA"), "zAbghk");
+    Ten t2 = E.contract_new(op(t1, "zAbghk"), op(T, "ghkGHK"), "zAbGHK");
+    E.drop(t1);
+    Ten out = E.contract_new(op(t2, "zAbGHK"), op(m, "zbvB", true), "zABGHK");
+    E.drop(t2);
+    return out;
+}
+
+// Right step through a u = 1 site: [z,A,B,G,H,K] -> [z,a,b,g,h,k].
+Ten env_right_T(Engine &E, const Ten &R, const Ten &m, const Ten &T) {
+    Ten t1 = E.contract_new(op(R, "zABGHK"), op(m, "zbvB", true), "zAbGHK");
+    Ten t2 = E.contract_new(op(t1, "zAbGHK"), op(T, "ghkGHK"), "zAbghk");
+    E.drop(t1);
+    Ten out = E.contract_new(op(m, "zauA"), op(t2, "zAbghk"), "zabghk");
+    E.drop(t2);
+    return out;
+}
+
+// Cost model (multiply-adds per sample for one left step with both projections)
+// of the direct order against the transfer-matrix route, which needs u = 1 and
+// a transfer matrix of modest size.
+bool transfer_pays(const SiteRef &a, const Ten &B, const Ten &m) {
+    if (a.dim(1) != 1) return false;
+    const double x = std::max(m.d[1], m.d[3]);
+    const double g = B.d[0], G = B.d[3], h = a.dim(2), H = a.dim(4), d = a.dim(3), p = a.dim(0);
+    const double tsize = g * h * h * G * H * H;
+    if (tsize > (double)(1 << 26)) return false;
+    const double direct = x * x * x * g * h * h + x * x * g * h * p * d * H * h + x * x * h * p * H * d * G * g * d +
+                          x * x * x * G * H * H * h * p * d;
+    const double viaT = x * x * x * g * h * h + p * x * x * g * h * h * G * H * H + p * x * x * x * G * H * H;
+    return viaT < direct;
+}
+
 void unit(Engine &E, Ten &t, int Z, double *logacc = nullptr) {
     const int64_t per = t.numel() / Z;
     E.normalise(t.p, t.esz, per, Z, per, logacc, logacc != nullptr, nullptr);
@@ -219,10 +273,24 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
             for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
             for (int r = 0; r < rows; ++r) {
                 const DMps &Bb = B.below[r];
+                // sites that take the transfer-matrix route, and their matrices
+                std::vector<int> useT(cols, 0);
+                std::vector<Ten> Ts(cols), T0(cols), T1(cols);
+                for (int c = 0; c < cols; ++c) {
+                    const SiteRef &a = V.at(r, c);
+                    if (!transfer_pays(a, Bb.site[c], m[c])) continue;
+                    useT[c] = 1;
+                    Ts[c] = transfer(E, a, Bb.site[c], -1);
+                    if (a.dim(0) == 2) {
+                        T0[c] = transfer(E, a, Bb.site[c], 0);
+                        T1[c] = transfer(E, a, Bb.site[c], 1);
+                    }
+                }
                 std::vector<Ten> R(cols + 1);
                 R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
                 for (int c = cols - 1; c >= 1; --c) {
-                    R[c] = env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
+                    R[c] = useT[c] ? env_right_T(E, R[c + 1], m[c], Ts[c])
+                                   : env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
                     unit(E, R[c], Z);
                 }
                 Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
@@ -230,15 +298,21 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     const SiteRef &a = V.at(r, c);
                     int *xs = xsel + (size_t)c * Zw;
                     if (a.dim(0) == 1) {
-                        Ten L2 = env_left(E, Lc, m[c], a, Bb.site[c], -1);
+                        Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left(E, Lc, m[c], a, Bb.site[c], -1);
                         E.drop(Lc);
                         Lc = L2;
                         unit(E, Lc, Z);
                         TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
                         continue;
                     }
-                    Ten L0 = env_left(E, Lc, m[c], a, Bb.site[c], 0);
-                    Ten L1 = env_left(E, Lc, m[c], a, Bb.site[c], 1);
+                    Ten L0, L1;
+                    if (useT[c]) {
+                        L0 = env_left_T(E, Lc, m[c], T0[c]);
+                        L1 = env_left_T(E, Lc, m[c], T1[c]);
+                    } else {
+                        L0 = env_left(E, Lc, m[c], a, Bb.site[c], 0);
+                        L1 = env_left(E, Lc, m[c], a, Bb.site[c], 1);
+                    }
                     const int64_t per = L0.numel() / Z;
                     E.dot(L0.p, R[c + 1].p, L0.esz, per, Z, per, pt);
                     E.dot(L1.p, R[c + 1].p, L1.esz, per, Z, per, pt + 2 * Zw);
@@ -269,6 +343,9 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                 E.drop(Lc);
                 for (auto &x : R)
                     if (x.p) E.drop(x);
+                for (int c = 0; c < cols; ++c)
+                    for (Ten *t : {&Ts[c], &T0[c], &T1[c]})
+                        if (t->p) E.drop(*t);
                 // projected row X_c[z] = A_c[x_c(z)], dims [z, u, h, d, H]
                 std::vector<Ten> X(cols);
                 for (int c = 0; c < cols; ++c) {

@@ -1,0 +1,53 @@
+"""Writes the stored expected values of the full-size parity tests.
+
+Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
+``peps_inputs``; nothing here touches the GPU library.  Run from the repo root:
+
+    python tests/golden/make_golden.py c3_norm       # ~10 min on 8 cores
+    python tests/golden/make_golden.py c3_samples    # a few samples at chi_x = 8
+"""
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from peps_inputs import make_config, sample_uniforms  # noqa: E402
+import oracle  # noqa: E402
+from oracle import boundary as ob  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def c3_norm():
+    lat, T, cfg = make_config("c3")
+    t0 = time.time()
+    below, logs, info = ob.boundary_set(T, 64, 2, 0, 0)
+    z = ob.close_row(T[0], below[0])
+    out = dict(config="c3", chi=64, sweeps=2, init_seed=0, direction=0,
+               log_abs_Z=sum(logs) + math.log(abs(z)), arg_Z=math.atan2(z.imag, z.real),
+               row_logs=logs, modes=[i["mode"] if i else None for i in info],
+               oracle_seconds=time.time() - t0,
+               command="python tests/golden/make_golden.py c3_norm")
+    json.dump(out, open(os.path.join(HERE, "c3_norm.json"), "w"), indent=1)
+    print(out)
+
+
+def c3_samples(n=2, chi_x=8):
+    lat, T, cfg = make_config("c3")
+    t0 = time.time()
+    below, logs, info = ob.boundary_set(T, 64, 2, 0, 0)
+    u = sample_uniforms(31, n, lat.n_qubits)
+    bits, lq, lp = oracle.sample(T, lat.site_index, 64, chi_x, n, seed=0, first=0, uniforms=u, below=below)
+    out = dict(config="c3", chi=64, chi_x=chi_x, sweeps=2, init_seed=0, uniforms_seed=31, n=n,
+               bits=bits.tolist(), log_q=lq.tolist(), log_p=lp.tolist(), oracle_seconds=time.time() - t0,
+               command=f"python tests/golden/make_golden.py c3_samples")
+    json.dump(out, open(os.path.join(HERE, "c3_samples_chix8.json"), "w"), indent=1)
+    print({k: v for k, v in out.items() if k != "bits"})
+
+
+if __name__ == "__main__":
+    {"c3_norm": c3_norm, "c3_samples": c3_samples}[sys.argv[1]]()
