@@ -15,6 +15,9 @@ Plain, slow, obviously correct NumPy (complex128) following Rudolph & Tindall,
                       boundaries, q(x) and p(x) (Appendix, sampling);
 * ``environments`` -- one-site density matrices, <Z>, nearest-neighbour <ZZ>
                       (Results, Fig. 4: direct contraction);
+* ``verify``       -- independent p(x) by a separate single-layer contraction
+                      of <x|psi>, the norm estimate E_q[p/q], the sample KLD
+                      and importance-sampled <Z> (Methods, sampling; Eq. kld);
 * ``philox``       -- Philox4x64-10 (Salmon et al. 2011) for random initial
                       guesses and draws.
 
@@ -30,3 +33,4 @@ from .statevector import statevector, brute_force_amplitude  # noqa: F401
 from .boundary import boundary_set, norm, fit_double, plan_bonds, flip_vertical  # noqa: F401
 from .sampler import sample, sample_one, fit_single, SamplingError  # noqa: F401
 from .environments import environments, z_expectation  # noqa: F401
+from .verify import amplitude, amplitudes, sample_stats  # noqa: F401

@@ -30,6 +30,7 @@ TAG_INIT_DOWN = 0
 TAG_INIT_UP = 1
 TAG_INIT_SAMPLER = 2
 TAG_DRAW = 3
+TAG_INIT_VERIFY = 4
 
 
 def philox4x64_10(counter, key):

@@ -75,9 +75,10 @@ def _canonicalise_exact3(Y):
 
 
 def fit_single(m, X, chi_x: int, sweeps: int, seed: int, row_id: int, sample: int,
-               force_fit: bool = False):
+               force_fit: bool = False, tag: int = TAG_INIT_SAMPLER):
     """Approximate m . X by an MPS of bond <= chi_x (one-site fit).
-    Envs: L[y, a, h] (output bond, input bond, MPO bond)."""
+    Envs: L[y, a, h] (output bond, input bond, MPO bond). ``tag`` names the
+    Philox stream of the random initial guess."""
     L = len(X)
     phys = [Xc.shape[2] for Xc in X]
     bond_in = [m[c].shape[2] * X[c].shape[3] for c in range(L - 1)]
@@ -89,7 +90,7 @@ def fit_single(m, X, chi_x: int, sweeps: int, seed: int, row_id: int, sample: in
     for c in range(L):
         tl = t[c - 1] if c > 0 else 1
         tr = t[c] if c < L - 1 else 1
-        Y.append(init_tensor_vec(seed, TAG_INIT_SAMPLER, row_id, c, sample, (tl, phys[c], tr)))
+        Y.append(init_tensor_vec(seed, tag, row_id, c, sample, (tl, phys[c], tr)))
     Y = right_canonicalise(Y)
     one = np.ones((1, 1, 1), dtype=np.complex128)
 
