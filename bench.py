@@ -39,69 +39,88 @@ def parse():
     ap.add_argument("--chi-x", type=int, default=None)
     ap.add_argument("--no-env", action="store_true", help="leave the density matrices out of the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's heuristic tile choice instead of timing the candidates")
+    ap.add_argument("--plan-report", default="", help="write the per-shape contraction timing table here")
+    ap.add_argument("--copy-ref", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(lat, T, chi, chi_x, budget):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload:
-    the absorption of the last row(s) into the norm boundary (contraction
-    TFLOP/s), and the sampling of whole rows of one sample (extrapolated to
-    samples/s over all rows)."""
+def copy_reference(nbytes: int):
+    """A plain device-to-device copy of known size: reads and writes nbytes once."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
+def cpu_baseline(lat, T, chi, chi_x, contraction_flops):
+    """The FP64 oracle, as it stands, on the host cores, on a bounded sample of
+    the workload: one sampler environment step (the oracle's env_right) for each
+    kind of site of a row, at the steady-state shapes of the workload (bond chi_x
+    amplitude boundary, bond chi norm boundary; seeded stand-in values), and one
+    fit site update (left partial, derivative, QR, environment update) for each
+    kind of site.  Every site of a sample costs one right step and two projected
+    left steps (about one full step), so a sample is extrapolated as
+    2 x (sum of the right steps over all sites); the norm as sweeps x 2 site
+    updates per site per row."""
     import numpy as np
-    import oracle
     from oracle import boundary as ob
     from oracle import sampler as osm
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    # contraction: absorb rows bottom-up until the budget is spent
-    rows = len(T)
-    below = [None] * rows
-    below[rows - 1] = ob.trivial_boundary(T[rows - 1])
-    t0 = time.perf_counter()
-    done = 0
-    flops = 0.0
-    for r in range(rows - 1, 0, -1):
-        below[r - 1], _, _ = ob.fit_double(below[r], T[r], chi, 2, 0, 0, r)
-        done += 1
-        if time.perf_counter() - t0 > budget / 2:
-            break
-    t_con = time.perf_counter() - t0
-    # sampling: one sample's rows (the stored boundaries below each sampled row are needed;
-    # rows whose boundary was not computed reuse the deepest one computed, which has the same shapes)
-    deepest = min(r for r in range(rows) if below[r] is not None)
-    t0 = time.perf_counter()
-    rows_done = 0
-    m = [np.ones((1, 1, 1), dtype=np.complex128) for _ in T[0]]
-    u = np.full(lat.n_qubits, 0.5)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    rng = np.random.default_rng(0)
+    cn = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)  # noqa: E731
+    rows, cols = len(T), len(T[0])
+    kinds = {}
+    for r in range(1, rows - 1):
+        for c in range(1, cols - 1):
+            A = T[r][c]
+            kinds.setdefault((A.shape[1], A.shape[3]), (r, c))
+    t_env, t_fit = {}, {}
+    # the sampler step is timed for the kind with the largest down bond (the costliest
+    # on the GPU) and used for every kind, which understates the oracle's time
+    env_kind = max(kinds, key=lambda k: (k[1], k[0]))
+    for (du, dd), (r, c) in kinds.items():
+        A = T[r][c]
+        h, H = A.shape[2], A.shape[4]
+        m = cn(chi_x, du, chi_x)
+        B = cn(chi, dd, dd, chi)
+        R = cn(chi_x, chi_x, chi, H, H)
+        if (du, dd) == env_kind:
+            t0 = time.perf_counter()
+            osm.env_right(R, m, A, B)
+            t_env[(du, dd)] = time.perf_counter() - t0
+            print(f"cpu baseline: sampler env step (u={du}, d={dd}) {t_env[(du, dd)]:.2f} s",
+                  file=sys.stderr, flush=True)
+        Le = cn(chi, chi, h, h)
+        Re = cn(chi, chi, H, H)
+        t0 = time.perf_counter()
+        t3 = ob.left_partial(Le, B, A)
+        N = np.einsum("yGuHvK,YGHK->yuvY", t3, Re, optimize=True)
+        Q, _ = ob.qr_reduced(N.reshape(-1, N.shape[3]))
+        np.einsum("yuvY,yGuHvK->YGHK", Q.reshape(N.shape).conj(), t3, optimize=True)
+        t_fit[(du, dd)] = time.perf_counter() - t0
+        print(f"cpu baseline: fit site update (u={du}, d={dd}) {t_fit[(du, dd)]:.2f} s",
+              file=sys.stderr, flush=True)
+    per_sample = 0.0
+    per_norm = 0.0
     for r in range(rows):
-        B = below[r] if below[r] is not None else below[deepest]
-        tr = time.perf_counter()
-        row = T[r]
-        cols = len(row)
-        R = [None] * (cols + 1)
-        R[cols] = np.ones((1,) * 5, dtype=np.complex128)
-        for c in range(cols - 1, 0, -1):
-            R[c] = osm._unit(osm.env_right(R[c + 1], m[c], row[c], B[c]))
-        L = np.ones((1,) * 5, dtype=np.complex128)
-        xs = []
         for c in range(cols):
-            Ls = [osm.env_left(L, m[c], row[c], B[c], s) for s in (0, 1)]
-            P = [np.sum(Ls[s] * R[c + 1]).real for s in (0, 1)]
-            x = 0 if P[0] >= P[1] else 1
-            xs.append(x)
-            L = osm._unit(Ls[x])
-        if r + 1 < rows:
-            X = [row[c][xs[c]] for c in range(cols)]
-            m, _ = osm.fit_single(m, X, chi_x, 2, 0, r, 0)
-        rows_done += 1
-        if time.perf_counter() - t0 > budget / 2:
-            break
-    t_smp = time.perf_counter() - t0
-    per_row = t_smp / rows_done
-    return dict(value=1.0 / (per_row * rows), unit="samples/s", cores=int(threads), kind="oracle",
-                sample=f"one sample: {rows_done} of {rows} rows sampled in {t_smp:.1f} s, extrapolated to all "
-                       f"rows; norm boundary: {done} of {rows - 1} row absorptions in {t_con:.1f} s",
-                seconds_per_row_absorption=t_con / done)
+            A = T[r][c]
+            k = (A.shape[1], A.shape[3])
+            per_sample += 2.0 * t_env[env_kind]
+            per_norm += 4.0 * t_fit.get(k, 0.0) if r > 0 else 0.0
+    return dict(value=1.0 / per_sample, unit="samples/s", cores=threads, kind="oracle",
+                sample=(f"one sampler environment step (site kind u,d = {env_kind}, used for every site) "
+                        f"and one fit site update per kind of site {sorted(kinds)} at chi={chi}, "
+                        f"chi_x={chi_x}, seeded stand-in values, timed once each "
+                        f"({sum(t_env.values()) + sum(t_fit.values()):.1f} s) and extrapolated over "
+                        f"{rows}x{cols} sites: {per_sample:.0f} s per sample, {per_norm:.0f} s per norm"),
+                contraction_tflops=contraction_flops / per_norm / 1e12 if per_norm > 0 else None)
 
 
 def main():
@@ -109,6 +128,9 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.copy_ref:
+        copy_reference(a.copy_ref)
+        return
     import numpy as np
     import torch
     import paper_2507_11424_amd as tnb
@@ -121,45 +143,68 @@ def main():
     dev_dtype = "c128" if a.prec == "fp64" else "c64"
     stream = torch.cuda.current_stream(0)
     h = tnb.Handle(0, stream)
+    # tile configurations are timed on each new contraction shape during warmup
+    h.set_autotune(not a.no_autotune)
     # inputs resident in HBM before timing (stored as the configured type, computed in the mode's type)
     P = tnb.Peps.from_numpy(lat, T, dtype=dev_dtype, device="cuda:0")
     o = tnb.make_opts(chi=chi, chi_x=chi_x, prec=a.prec)
 
+    phases = ("contract", "environments", "sample")
+
     def step(timing=False):
+        """One pass of the hot path; returns log|Z| and per-phase (seconds, counters)."""
         h.set_timing(timing)
+        rec = {}
         t0 = time.perf_counter()
         lz, _ = h.boundary_contract(P, o)
-        c1 = h.counters()
-        t_con = time.perf_counter() - t0
+        rec["contract"] = (time.perf_counter() - t0, h.counters())
         if not a.no_env:
             # one-site marginals of every qubit (pairs are left out at this size)
+            t0 = time.perf_counter()
             h.environments(P, o, want_zz=False, want_p2=False)
-        bits, lq, lp = h.sample(P, o, a.samples, seed=17)
-        c2 = h.counters()
-        return lz, t_con, c1, c2
+            torch.cuda.synchronize()
+            rec["environments"] = (time.perf_counter() - t0, h.counters())
+        t0 = time.perf_counter()
+        h.sample(P, o, a.samples, seed=17)
+        torch.cuda.synchronize()
+        rec["sample"] = (time.perf_counter() - t0, h.counters())
+        return lz, rec
 
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
+        tw = time.perf_counter()
         step()
+        print(f"warmup step {i} done in {time.perf_counter() - tw:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    # the contraction kernel's device time comes from HIP events recorded on the
+    # handle's stream around every launch inside the timed steps (no host waits
+    # between launches; the events are read when each call returns)
     t0 = time.perf_counter()
-    con_t = 0.0
-    con_flops = 0.0
-    smp_flops = 0.0
-    for _ in range(a.steps):
-        lz, t_con, c1, c2 = step()
-        con_t += t_con
-        con_flops += c1["gemm_flops"]
-        smp_flops += c2["gemm_flops"]
+    acc = {k: [0.0, 0.0] for k in phases}
+    gemm_ms = gemm_flops = qr_ms = 0.0
+    launches = 0
+    for i in range(a.steps):
+        lz, rec = step(timing=True)
+        for k, (sec, c) in rec.items():
+            acc[k][0] += sec
+            acc[k][1] += c["gemm_flops"]
+            gemm_ms += c["gemm_ms"]
+            gemm_flops += c["gemm_flops"]
+            qr_ms += c["qr_ms"]
+            launches += c["gemm_launches"]
+        print(f"timed step {i} done ({time.perf_counter() - t0:.1f} s so far)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-kernel device time of the contraction engine, from HIP events on the handle's stream
-    _, _, ct1, ct2 = step(timing=True)
     h.set_timing(False)
-    gemm_ms = ct1["gemm_ms"] + ct2["gemm_ms"]
-    gemm_flops = ct1["gemm_flops"] + ct2["gemm_flops"]
-    launches = ct1["gemm_launches"] + ct2["gemm_launches"]
+    if a.plan_report:
+        with open(a.plan_report, "w") as f:
+            f.write(h.plan_report(40))
+    gemm_ms /= a.steps
+    gemm_flops /= a.steps
+    qr_ms /= a.steps
+    launches //= a.steps
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     samples = a.samples * a.steps
+    con_t, con_f = acc["contract"]
     out = {
         "metric": METRIC,
         "value": samples / dt,
@@ -175,17 +220,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.config}: {lat.name}, {lat.n_qubits} qubits, chi={chi}, chi_x={chi_x}, "
                                f"{cfg['dtype']} input, {a.samples} samples per step",
-                   "samples_per_step": a.samples, "prec": a.prec},
-        "contraction_tflops": con_flops / con_t / 1e12 if con_t > 0 else None,
-        "contraction_ms": 1e3 * con_t / a.steps,
+                   "samples_per_step": a.samples, "prec": a.prec, "autotune": not a.no_autotune},
+        "contraction_tflops": con_f / con_t / 1e12 if con_t > 0 else None,
+        "phases": {k: {"ms_per_step": 1e3 * v[0] / a.steps, "tflop_per_step": v[1] / a.steps / 1e12,
+                       "tflops": v[1] / v[0] / 1e12 if v[0] > 0 else None} for k, v in acc.items()},
         "log_abs_Z": lz,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[a.prec], "traffic": None,
                      "kernel": "gett (complex contraction engine)", "launches_per_step": launches,
-                     "algorithmic_flops_per_step": gemm_flops},
+                     "algorithmic_flops_per_step": gemm_flops, "kernel_ms_per_step": gemm_ms,
+                     "qr_ms_per_step": qr_ms},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(lat, T, chi, chi_x, a.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(lat, T, chi, chi_x, con_f / a.steps)
     print(json.dumps(out))
     h.close()
 

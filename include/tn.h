@@ -145,6 +145,36 @@ tn_status tn_sample(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
                     uint64_t seed, uint64_t first_sample, int64_t n,
                     const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
 
+/* Independent check of given bitstrings (Methods, sampling paragraphs: p(x)
+ * recomputed by a separate contraction of <x|psi> rather than taken from the
+ * sampler).  The single-layer network <x|psi> is contracted row by row, top
+ * down, with boundary MPSs of bond <= opts->chi_x fitted by the one-site fit
+ * (the paper uses twice the PEPS bond dimension for this check); the initial
+ * guesses use Philox4x64-10 key (init_seed, 4) with the sample index
+ * first_sample + i in the counter, a stream disjoint from the sampler's.
+ *   bits  : device [n][N] uint8 (0/1, qubit q at column site_index), read only;
+ *   log_p : device [n] doubles, 2 log|<x|psi>| (-inf for a zero amplitude);
+ *   arg   : optional device [n] doubles, arg <x|psi> in (-pi, pi].
+ * Independent of the cached boundary set; asynchronous on the handle's stream. */
+tn_status tn_amplitude(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
+                       uint64_t first_sample, int64_t n, const uint8_t *bits,
+                       double *log_p, double *arg);
+
+/* Sample-quality metrics from per-sample log q and log p (device [n] doubles,
+ * natural logs), with w_i = p(x_i)/q(x_i) (Methods, the unbiased norm
+ * estimator, Eq. kld and the importance-sampling formula, read in its
+ * self-normalised form):
+ *   out[0] = log((1/n) sum_i w_i), the estimate of log <psi|psi>;
+ *   out[1] = (1/n) sum_i (log q_i - log p_i + log_Z), the sample KLD against
+ *            p / Z with log_Z from tn_boundary_contract;
+ *   out[2] = (sum w)^2 / sum w^2, the effective sample size;
+ * out is host memory (3 doubles).  z_is (optional device [n_qubits] doubles)
+ * receives sum_i w_i (1 - 2 x_iq) / sum_i w_i, which needs bits (device
+ * [n][n_qubits] uint8).  n must be > 0.  Synchronises the stream. */
+tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8_t *bits,
+                          const double *log_q, const double *log_p, double log_Z,
+                          double *out, double *z_is);
+
 /* Text of the last error on this handle ("" if none).  Valid until the next call. */
 const char *tn_last_error(const tn_handle *h);
 
@@ -156,8 +186,26 @@ const char *tn_last_error(const tn_handle *h);
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
                           double *gemm_ms, double *qr_ms, int64_t *qr_launches);
 
-/* Enables (1) or disables (0) per-kernel HIP-event timing (adds host syncs). */
+/* Enables (1) or disables (0) per-launch HIP-event timing: an event pair is
+ * recorded around every contraction and QR launch on the handle's stream and read
+ * when a call returns (no waits between launches). */
 tn_status tn_set_timing(tn_handle *h, int enable);
+
+/* Enables (1) or disables (0) autotuning of the contraction kernels.  When on,
+ * the first call of each contraction shape that overwrites its output times
+ * every tile configuration and split-K choice of the GETT kernel on that call's
+ * operands (waiting for the stream) and keeps the fastest for the handle's
+ * lifetime; results differ from the untuned choice only in the rounding of the
+ * K summation order.  cache_path (host string, may be NULL) names a text file
+ * whose choices are loaded now and to which new choices are appended; a missing
+ * file is not an error.  Errors: TN_ERR_INVALID for a NULL handle. */
+tn_status tn_set_autotune(tn_handle *h, int enable, const char *cache_path);
+
+/* Writes into buf (host, len bytes, NUL-terminated, truncated if short) a
+ * tab-separated table of the `top` contraction shapes with the most device time
+ * recorded in timing mode since the handle was created: milliseconds, calls,
+ * TFLOP/s and the shape (letters, M, N, K, batch, tile, split). */
+tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
 
 /* ---------------------------------------------------------------------------
  * Kernel test hooks: run one engine primitive on caller buffers so that its
@@ -170,7 +218,9 @@ tn_status tn_set_timing(tn_handle *h, int enable);
  *   Enqueued on the handle's stream.
  * tn_test_qr: reduced Householder QR (FP64 arithmetic) of `batch` row-major
  *   m x n DEVICE matrices of element size esz (16 or 8 bytes): Q is m x k,
- *   R is k x n, k = min(m, n).  Enqueued on the handle's stream.
+ *   R is k x n, k = min(m, n).  With R == NULL, only an orthonormal basis Q of
+ *   the column space is formed, by the fit's shifted CholeskyQR3 (m >= n,
+ *   n <= 64; Householder otherwise).  Enqueued on the handle's stream.
  */
 tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims,
                            int conjA, const char *ib, const void *B, const int32_t *bdims, int conjB,

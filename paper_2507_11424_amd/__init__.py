@@ -30,7 +30,8 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 
 # every symbol declared in include/tn.h
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
-           "tn_sample", "tn_last_error", "tn_get_counters", "tn_set_timing", "tn_test_contract", "tn_test_qr"]
+           "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing", "tn_set_autotune",
+           "tn_plan_report", "tn_test_contract", "tn_test_qr"]
 
 
 class TnError(RuntimeError):
@@ -72,16 +73,22 @@ def lib(path: Optional[str] = None):
     L.tn_boundary_contract.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), dp, dp]
     L.tn_environments.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), vp, vp, vp, vp, vp]
     L.tn_sample.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, u64, i64, vp, vp, vp, vp]
+    L.tn_amplitude.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, i64, vp, vp, vp]
+    L.tn_sample_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
     L.tn_last_error.argtypes = [vp]
     L.tn_last_error.restype = ctypes.c_char_p
     L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64)]
     L.tn_set_timing.argtypes = [vp, ctypes.c_int]
+    L.tn_set_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
+    L.tn_plan_report.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    L.tn_plan_report.restype = ctypes.c_int
     L.tn_test_contract.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int]
     L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
-              "tn_get_counters", "tn_set_timing", "tn_test_contract", "tn_test_qr"):
+              "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
+              "tn_test_qr", "tn_amplitude", "tn_sample_stats"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -220,6 +227,51 @@ class Handle:
                                     ctypes.c_void_p(lp.data_ptr()) if lp is not None else None))
         return bits, lq, lp
 
+    def amplitude(self, peps: Peps, opts: c_opts, bits, first: int = 0, want_arg: bool = False):
+        """log p(x) = 2 log|<x|psi>| (and arg <x|psi>) for bitstrings bits [n][N]
+        by a separate contraction with bond opts.chi_x (see tn_amplitude)."""
+        import torch
+        dev = peps.tensors[0].device
+        bits = bits.to(device=dev, dtype=torch.uint8).contiguous()
+        if bits.dim() != 2 or bits.shape[1] != peps.n_qubits:
+            raise ValueError("bits must have shape [n][N]")
+        n = bits.shape[0]
+        lp = torch.empty((n,), dtype=torch.float64, device=dev)
+        ar = torch.empty((n,), dtype=torch.float64, device=dev) if want_arg else None
+        self._check(lib().tn_amplitude(self.h, ctypes.byref(peps.c), ctypes.byref(opts), first, n,
+                                       ctypes.c_void_p(bits.data_ptr()), ctypes.c_void_p(lp.data_ptr()),
+                                       ctypes.c_void_p(ar.data_ptr()) if ar is not None else None))
+        return (lp, ar) if want_arg else lp
+
+    def sample_stats(self, log_q, log_p, log_Z: float, bits=None):
+        """Norm estimate, sample KLD, effective sample size and (with bits) the
+        importance-sampled <Z_q> (see tn_sample_stats)."""
+        import torch
+        dev = log_q.device
+        lq = log_q.to(dtype=torch.float64).contiguous()
+        lp = log_p.to(device=dev, dtype=torch.float64).contiguous()
+        if lq.shape != lp.shape or lq.dim() != 1:
+            raise ValueError("log_q and log_p must be 1-d of equal length")
+        n = lq.shape[0]
+        out = (ctypes.c_double * 3)()
+        zis = None
+        bp = None
+        nq = 0
+        if bits is not None:
+            bits = bits.to(device=dev, dtype=torch.uint8).contiguous()
+            if bits.dim() != 2 or bits.shape[0] != n:
+                raise ValueError("bits must have shape [n][N]")
+            nq = bits.shape[1]
+            zis = torch.empty((nq,), dtype=torch.float64, device=dev)
+            bp = ctypes.c_void_p(bits.data_ptr())
+        self._check(lib().tn_sample_stats(self.h, n, nq, bp, ctypes.c_void_p(lq.data_ptr()),
+                                          ctypes.c_void_p(lp.data_ptr()), float(log_Z), out,
+                                          ctypes.c_void_p(zis.data_ptr()) if zis is not None else None))
+        res = dict(log_norm_est=out[0], kld=out[1], ess=out[2])
+        if zis is not None:
+            res["z_is"] = zis
+        return res
+
     def counters(self):
         f, ms, qms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         n, qn = ctypes.c_int64(), ctypes.c_int64()
@@ -230,6 +282,17 @@ class Handle:
 
     def set_timing(self, on: bool):
         self._check(lib().tn_set_timing(self.h, 1 if on else 0))
+
+    def set_autotune(self, on: bool, cache_path: str | None = None):
+        """Times the GETT tile configurations on each new contraction shape and
+        keeps the fastest (see tn_set_autotune)."""
+        self._check(lib().tn_set_autotune(self.h, 1 if on else 0,
+                                          None if cache_path is None else cache_path.encode()))
+
+    def plan_report(self, top: int = 30) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(lib().tn_plan_report(self.h, top, buf, len(buf)))
+        return buf.value.decode()
 
     # ---------------------------------------------------------------- test hooks
     def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
@@ -244,4 +307,5 @@ class Handle:
         batch = int(np.prod(A.shape[:-2])) if A.dim() > 2 else 1
         esz = 16 if A.element_size() == 16 else 8
         self._check(lib().tn_test_qr(self.h, m, n, batch, esz, ctypes.c_void_p(A.data_ptr()),
-                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(R.data_ptr())))
+                                     ctypes.c_void_p(Q.data_ptr()),
+                                     ctypes.c_void_p(R.data_ptr()) if R is not None else None))

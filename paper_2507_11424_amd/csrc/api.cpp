@@ -116,6 +116,7 @@ void begin(tn_handle *h, const tn_opts *o) {
     h->err.clear();
     TN_HIP(hipSetDevice(h->device));
     if (o) h->E->set_prec((int)o->prec);
+    h->E->collect_timing();
     h->E->ctr.reset();
 }
 
@@ -235,14 +236,9 @@ tn_status tn_environments(tn_handle *h, const tn_peps *p, const tn_opts *o, doub
         begin(h, o);
         validate(p, o);
         if (!rho1) throw TnError(ST_INVALID, "null rho1");
-        PepsDev P = stage(*h->E, p);
-        try {
-            environments(*h->E, P, fit_opts(o), rho1, zz_h, zz_v, p2_h, p2_v);
-        } catch (...) {
-            unstage(*h->E, P);
-            throw;
-        }
-        unstage(*h->E, P);
+        // the bottom-up boundary set is shared with the norm and the sampler (cached)
+        const BoundarySet &S = cached_set(h, p, o, false);
+        environments(*h->E, h->cache_peps, fit_opts(o), &S, rho1, zz_h, zz_v, p2_h, p2_v);
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);
@@ -275,11 +271,74 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
     }
 }
 
+tn_status tn_amplitude(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t first, int64_t n,
+                       const uint8_t *bits, double *log_p, double *arg) {
+    try {
+        begin(h, o);
+        validate(p, o);
+        if (n < 0) throw TnError(ST_INVALID, "n must be >= 0");
+        if (n == 0) return TN_OK;
+        if (!bits || !log_p) throw TnError(ST_INVALID, "null bits or log_p");
+        SampleOpts so;
+        so.chi_x = o->chi_x;
+        so.sweeps = o->sweeps;
+        so.force_fit = o->init == 1;
+        so.init_seed = o->init_seed;
+        so.init_tag = 4;
+        PepsDev P = stage(*h->E, p);
+        try {
+            amplitude(*h->E, P, so, first, n, bits, log_p, arg);
+        } catch (...) {
+            unstage(*h->E, P);
+            throw;
+        }
+        unstage(*h->E, P);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8_t *bits, const double *log_q,
+                          const double *log_p, double log_Z, double *out, double *z_is) {
+    try {
+        if (!h || !h->E) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        if (n <= 0) throw TnError(ST_INVALID, "n must be > 0");
+        if (!log_q || !log_p || !out) throw TnError(ST_INVALID, "null log_q, log_p or out");
+        if (z_is && (!bits || n_qubits <= 0)) throw TnError(ST_INVALID, "z_is needs bits and n_qubits > 0");
+        Engine &E = *h->E;
+        double *dev = reinterpret_cast<double *>(E.raw(3 * sizeof(double)));
+        try {
+            TN_HIP(tnk::launch_sample_stats(log_q, log_p, n, log_Z, z_is ? bits : nullptr, n_qubits, dev, z_is, E.s));
+            TN_HIP(hipMemcpyAsync(out, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, E.s));
+            E.sync();
+        } catch (...) {
+            E.unraw(dev);
+            throw;
+        }
+        E.unraw(dev);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
 const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "null handle"; }
 
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
                           double *qr_ms, int64_t *qr_launches) {
     if (!h || !h->E) return TN_ERR_INVALID;
+    try {
+        const_cast<Engine *>(h->E.get())->collect_timing();
+    } catch (const TnError &e) {
+        return (tn_status)e.code;
+    }
     const Counters &c = h->E->ctr;
     if (gemm_flops) *gemm_flops = c.gemm_flops;
     if (gemm_launches) *gemm_launches = c.gemm_launches;
@@ -289,10 +348,39 @@ tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_
     return TN_OK;
 }
 
+tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len) {
+    if (!h || !h->E || !buf || len == 0) return TN_ERR_INVALID;
+    try {
+        const_cast<Engine *>(h->E.get())->collect_timing();
+    } catch (const TnError &e) {
+        return (tn_status)e.code;
+    }
+    const std::string s = h->E->plan_report(top);
+    const size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+    return TN_OK;
+}
+
 tn_status tn_set_timing(tn_handle *h, int enable) {
     if (!h || !h->E) return TN_ERR_INVALID;
     h->E->timing = enable != 0;
     return TN_OK;
+}
+
+tn_status tn_set_autotune(tn_handle *h, int enable, const char *cache_path) {
+    if (!h || !h->E) return TN_ERR_INVALID;
+    try {
+        h->err.clear();
+        h->E->set_autotune(enable != 0, cache_path ? std::string(cache_path) : std::string());
+        return TN_OK;
+    } catch (const TnError &e) {
+        h->err = e.what();
+        return (tn_status)e.code;
+    } catch (const std::exception &e) {
+        h->err = e.what();
+        return TN_ERR_INVALID;
+    }
 }
 
 // ---------------------------------------------------------------- test hooks
@@ -331,7 +419,8 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
         a.A = A; a.a_esz = esz; a.a_bs = (int64_t)m * n; a.a_rs = n; a.a_cs = 1;
         a.Q = Q; a.q_esz = esz; a.q_bs = (int64_t)m * k; a.q_rs = k; a.q_cs = 1;
         a.R = R; a.r_esz = esz; a.r_bs = (int64_t)k * n; a.r_rs = n; a.r_cs = 1;
-        h->E->qr(a);
+        if (R) h->E->qr(a);
+        else h->E->orthonormalise(a);
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);

@@ -116,7 +116,9 @@ void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R) {
     a.A = T.p; a.a_esz = T.esz; a.a_bs = m * n; a.a_rs = n; a.a_cs = 1; a.a_conj = 0;
     a.Q = Q.p; a.q_esz = Q.esz; a.q_bs = m * k; a.q_rs = k; a.q_cs = 1; a.q_conj = 0;
     a.R = R ? R->p : nullptr; a.r_esz = T.esz; a.r_bs = k * n; a.r_rs = n; a.r_cs = 1; a.r_conj = 0;
-    E.qr(a);
+    // the fit needs only an orthonormal basis of the column space
+    if (R) E.qr(a);
+    else E.orthonormalise(a);
 }
 
 // LQ of T seen as batch x m x n (m = dim nb, n = the rest): T = L Q, Q rows orthonormal.
@@ -141,7 +143,8 @@ void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *Lf) {
     a.A = T.p; a.a_esz = T.esz; a.a_bs = m * n; a.a_rs = 1; a.a_cs = n; a.a_conj = 1;
     a.Q = Q.p; a.q_esz = Q.esz; a.q_bs = k * n; a.q_rs = 1; a.q_cs = n; a.q_conj = 1;
     a.R = Lf ? Lf->p : nullptr; a.r_esz = T.esz; a.r_bs = m * k; a.r_rs = 1; a.r_cs = k; a.r_conj = 1;
-    E.qr(a);
+    if (Lf) E.qr(a);
+    else E.orthonormalise(a);
 }
 
 void plan_bonds(const std::vector<int> &phys, const std::vector<int64_t> &bond_in, int chi,

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <set>
+#include <fstream>
 #include <sstream>
 
 namespace tnb {
@@ -90,17 +91,61 @@ void Pool::trim() {
 
 // ---------------------------------------------------------------- engine
 
-Engine::Engine(int dev, hipStream_t st, size_t cap) : s(st), device(dev), pool_(cap) {
-    TN_HIP(hipEventCreate(&ev0_));
-    TN_HIP(hipEventCreate(&ev1_));
-}
+Engine::Engine(int dev, hipStream_t st, size_t cap) : s(st), device(dev), pool_(cap) {}
 
 Engine::~Engine() {
     (void)hipStreamSynchronize(s);
     for (auto &kv : plans_)
         if (kv.second->dev) (void)hipFree(kv.second->dev);
-    if (ev0_) (void)hipEventDestroy(ev0_);
-    if (ev1_) (void)hipEventDestroy(ev1_);
+    for (auto &e : ev_) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+}
+
+Engine::EvPair &Engine::next_pair(int kind) {
+    if (ev_used_ == ev_.size()) {
+        EvPair e{};
+        TN_HIP(hipEventCreate(&e.a));
+        TN_HIP(hipEventCreate(&e.b));
+        ev_.push_back(e);
+    }
+    EvPair &e = ev_[ev_used_++];
+    e.kind = kind;
+    e.plan = nullptr;
+    return e;
+}
+
+void Engine::collect_timing() {
+    if (ev_used_ == 0) return;
+    sync();
+    for (size_t i = 0; i < ev_used_; ++i) {
+        float ms = 0.f;
+        TN_HIP(hipEventElapsedTime(&ms, ev_[i].a, ev_[i].b));
+        if (ev_[i].kind == 0) ctr.gemm_ms += ms;
+        else ctr.qr_ms += ms;
+        if (ev_[i].plan) {
+            ev_[i].plan->ms += ms;
+            ev_[i].plan->calls += 1;
+        }
+    }
+    ev_used_ = 0;
+}
+
+std::string Engine::plan_report(int top) const {
+    std::vector<const Plan *> v;
+    for (auto &kv : plans_) v.push_back(kv.second.get());
+    std::sort(v.begin(), v.end(), [](const Plan *a, const Plan *b) { return a->ms > b->ms; });
+    std::ostringstream os;
+    os << "ms\tcalls\tTFLOP/s\tplan\n";
+    for (int i = 0; i < (int)v.size() && i < top; ++i) {
+        const Plan *p = v[i];
+        if (p->calls == 0) continue;
+        const double tf = p->ms > 0 ? p->flops * p->calls / (p->ms * 1e-3) / 1e12 : 0.0;
+        os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << " cfg=" << p->cfg
+           << " split=" << p->base.ksplit << (p->tuned ? " tuned" : "") << '\n';
+    }
+    return os.str();
 }
 
 Ten Engine::make(const std::vector<int> &dims, int e) {
@@ -139,7 +184,7 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
         ks << '|';
     };
     addk(A); addk(B); addk(C);
-    const std::string key = ks.str();
+    const std::string key = std::to_string(prec) + '#' + ks.str();  // plans are per precision
     auto it = plans_.find(key);
     if (it != plans_.end()) return it->second.get();
 
@@ -283,13 +328,127 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     g.a_kfast = (la && kl.find(la) != std::string::npos && stride(opA, la) == 1) ? 1 : 0;
     g.b_kfast = (lb && kl.find(lb) != std::string::npos && stride(opB, lb) == 1) ? 1 : 0;
     (void)kml; (void)knl;
-    if (kN <= 16) P->cfg = tnk::CFG_64x16;
-    else if (kM >= 8192 && kN >= 128 && K >= 16) P->cfg = tnk::CFG_128x64;
-    else P->cfg = tnk::CFG_64x64;
+    P->kM = kM; P->kN = kN; P->K = K; P->Z = Z;
+    P->key = key;
     P->flops = 8.0 * (double)M * (double)N * (double)K * (double)Z;
+    {
+        std::ostringstream d;
+        d << A.idx << ',' << B.idx << "->" << C.idx << " M=" << M << " N=" << N << " K=" << K << " batch=" << Z
+          << (swap ? " swapped" : "");
+        P->desc = d.str();
+    }
+    auto tc = tune_cache_.find(P->key);
+    if (tc != tune_cache_.end()) {
+        set_split(P.get(), tc->second.first, tc->second.second);
+        P->tuned = true;
+    } else {
+        int cfg;
+        if (kN <= 16) cfg = tnk::CFG_64x16;
+        else if (kM >= 8192 && kN >= 128 && K >= 16) cfg = tnk::CFG_128x64;
+        else cfg = tnk::CFG_64x64;
+        set_split(P.get(), cfg, 0);
+    }
     Plan *raw = P.get();
     plans_[key] = std::move(P);
     return raw;
+}
+
+// ksplit_hint: 0 = heuristic (split K when the output tiles alone cannot fill
+// the chip and K is long), otherwise the number of K slices wanted.
+void Engine::set_split(Plan *P, int cfg, int ksplit_hint) {
+    tnk::GettArgs &g = P->base;
+    P->cfg = cfg;
+    const int64_t K = P->K;
+    int64_t ks = 1;
+    if (ksplit_hint > 0) {
+        ks = std::min<int64_t>(ksplit_hint, std::max<int64_t>(K / 32, 1));
+    } else {
+        int bm = 64, bn = 64;
+        tnk::gett_tile(cfg, prec, &bm, &bn);
+        const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
+        if (tiles < 512 && K >= 256) ks = std::min<int64_t>((1024 + tiles - 1) / tiles, K / 128);
+    }
+    g.ksplit = 1;
+    g.kchunk = (int)K;
+    if (ks > 1) {
+        int64_t chunk = (K + ks - 1) / ks;
+        chunk = (chunk + 31) / 32 * 32;
+        g.kchunk = (int)chunk;
+        g.ksplit = (int)((K + chunk - 1) / chunk);
+    }
+}
+
+void Engine::set_autotune(bool on, const std::string &cache_path) {
+    autotune_ = on;
+    tune_path_ = cache_path;
+    if (!on || cache_path.empty()) return;
+    std::ifstream f(cache_path);
+    std::string k;
+    int cfg, ks;
+    while (f >> k >> cfg >> ks)
+        if (cfg >= 0 && cfg < tnk::CFG_COUNT && cfg != tnk::CFG_128x128 && ks >= 1) tune_cache_[k] = {cfg, ks};
+}
+
+// Times every candidate (tile configuration x split-K choice) on the call's own
+// operands; only for calls that overwrite C, so repeated launches leave the
+// same result.  The last launch of the caller then runs with the winner.
+void Engine::tune(Plan *P, tnk::GettArgs g) {
+    struct Cand { int cfg, ks; };
+    std::vector<Cand> cands;
+    const int cfgs[3] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64};
+    for (int c : cfgs) {
+        if (c == tnk::CFG_128x64 && P->kM < 128) continue;
+        if (c == tnk::CFG_64x16 && P->kN > 64) continue;
+        int bm = 64, bn = 64;
+        tnk::gett_tile(c, prec, &bm, &bn);
+        const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
+        cands.push_back({c, 1});
+        for (int64_t ks = 2; ks <= 16; ks *= 2) {
+            if (P->K < 64 * ks) break;
+            if (tiles * ks > 8 * 1024) break;
+            cands.push_back({c, (int)ks});
+        }
+    }
+    hipEvent_t e0, e1;
+    TN_HIP(hipEventCreate(&e0));
+    TN_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    Cand win{P->cfg, std::max(P->base.ksplit, 1)};
+    const tnk::GettArgs saved = P->base;
+    try {
+        for (const Cand &c : cands) {
+            set_split(P, c.cfg, c.ks);
+            tnk::GettArgs t = g;
+            t.ksplit = P->base.ksplit;
+            t.kchunk = P->base.kchunk;
+            void *part = t.ksplit > 1 ? pool_.get((size_t)t.ksplit * t.batch * (size_t)t.M * t.N * esz) : nullptr;
+            t.part = part;
+            TN_HIP(tnk::launch_gett(t, prec, c.cfg, s));  // warm
+            TN_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 3; ++r) TN_HIP(tnk::launch_gett(t, prec, c.cfg, s));
+            TN_HIP(hipEventRecord(e1, s));
+            TN_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            TN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (part) pool_.put(part);
+            if (ms < best) { best = ms; win = c; }
+        }
+    } catch (...) {
+        P->base = saved;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        throw;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    P->base = saved;
+    set_split(P, win.cfg, win.ks);
+    P->tuned = true;
+    tune_cache_[P->key] = {win.cfg, win.ks};
+    if (!tune_path_.empty()) {
+        std::ofstream f(tune_path_, std::ios::app);
+        f << P->key << ' ' << win.cfg << ' ' << win.ks << '\n';
+    }
 }
 
 void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
@@ -303,15 +462,26 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     g.conjA = (P->swapped ? B.conj : A.conj) ? 1 : 0;
     g.conjB = (P->swapped ? A.conj : B.conj) ? 1 : 0;
     g.accumulate = accumulate ? 1 : 0;
-    if (timing) TN_HIP(hipEventRecord(ev0_, s));
-    TN_HIP(tnk::launch_gett(g, prec, P->cfg, s));
-    if (timing) {
-        TN_HIP(hipEventRecord(ev1_, s));
-        TN_HIP(hipEventSynchronize(ev1_));
-        float ms = 0.f;
-        TN_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
-        ctr.gemm_ms += ms;
+    if (autotune_ && !P->tuned && !accumulate) {
+        tune(P, g);
+        g.ksplit = P->base.ksplit;
+        g.kchunk = P->base.kchunk;
     }
+    void *part = nullptr;
+    if (g.ksplit > 1) {
+        part = pool_.get((size_t)g.ksplit * g.batch * (size_t)g.M * g.N * esz);
+        g.part = part;
+    }
+    // inside the QR the enclosing event pair already times the launch
+    EvPair *ev = (timing && !in_qr_) ? &next_pair(0) : nullptr;
+    if (ev) {
+        ev->plan = P;
+        TN_HIP(hipEventRecord(ev->a, s));
+    }
+    TN_HIP(tnk::launch_gett(g, prec, P->cfg, s));
+    if (ev) TN_HIP(hipEventRecord(ev->b, s));
+    if (part) pool_.put(part);
+    if (in_qr_) return;
     ctr.gemm_flops += P->flops;
     ctr.gemm_launches += 1;
 }
@@ -333,17 +503,56 @@ Ten Engine::contract_new(const Op &A, const Op &B, const std::string &ic) {
 void Engine::qr(const tnk::QrArgs &a) {
     const size_t ws = tnk::qr_workspace_bytes(a.m, a.n, a.batch);
     void *w = pool_.get(ws);
-    if (timing) TN_HIP(hipEventRecord(ev0_, s));
+    EvPair *ev = timing ? &next_pair(1) : nullptr;
+    if (ev) TN_HIP(hipEventRecord(ev->a, s));
     TN_HIP(tnk::launch_qr(a, w, s));
-    if (timing) {
-        TN_HIP(hipEventRecord(ev1_, s));
-        TN_HIP(hipEventSynchronize(ev1_));
-        float ms = 0.f;
-        TN_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
-        ctr.qr_ms += ms;
-    }
+    if (ev) TN_HIP(hipEventRecord(ev->b, s));
     ctr.qr_launches += 1;
     pool_.put(w);
+}
+
+void Engine::orthonormalise(const tnk::QrArgs &a) {
+    const int m = a.m, n = a.n, Z = a.batch;
+    if (n > 64 || m < n) {
+        qr(a);
+        return;
+    }
+    const int saved = prec;
+    set_prec(tnk::P_FP64);
+    in_qr_ = true;
+    Ten X = make({Z, m, n}, 16), Y = make({Z, m, n}, 16);
+    Ten G = make({Z, n, n}, 16), Ri = make({Z, n, n}, 16);
+    EvPair *ev = timing ? &next_pair(1) : nullptr;
+    try {
+        if (ev) TN_HIP(hipEventRecord(ev->a, s));
+        TN_HIP(tnk::launch_strided_copy(a.A, a.a_esz, a.a_bs, a.a_rs, a.a_cs, X.p, 16, (int64_t)m * n, n, 1, m, n, Z,
+                                        a.a_conj, s));
+        const double u = 1.1102230246251565e-16;
+        for (int pass = 0; pass < 3; ++pass) {
+            contract(op(X, "bij", true), op(X, "bik"), op(G, "bjk"));
+            // shift relative to tr(G)/n; tr(G) bounds ||A||_2^2
+            const double shift = pass == 0 ? 11.0 * ((double)m * n + (double)n * (n + 1)) * u * n : 0.0;
+            const double clamp = pass == 0 ? 1e-300 : 1e-14;
+            TN_HIP(tnk::launch_chol_inv(reinterpret_cast<const double *>(G.p), n, Z, shift, clamp,
+                                        reinterpret_cast<double *>(Ri.p), nullptr, s));
+            contract(op(X, "bij"), op(Ri, "bjk"), op(Y, "bik"));
+            std::swap(X, Y);
+        }
+        TN_HIP(tnk::launch_strided_copy(X.p, 16, (int64_t)m * n, n, 1, a.Q, a.q_esz, a.q_bs, a.q_rs, a.q_cs, m, n, Z,
+                                        a.q_conj, s));
+        if (ev) TN_HIP(hipEventRecord(ev->b, s));
+    } catch (...) {
+        in_qr_ = false;
+        set_prec(saved);
+        throw;
+    }
+    in_qr_ = false;
+    set_prec(saved);
+    drop(X);
+    drop(Y);
+    drop(G);
+    drop(Ri);
+    ctr.qr_launches += 1;
 }
 
 void Engine::norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out) {

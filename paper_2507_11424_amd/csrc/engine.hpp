@@ -82,6 +82,12 @@ struct Plan {
     bool swapped = false;
     void *dev = nullptr;  // table storage
     double flops = 0;     // 8 * M * N * K * batch
+    std::string desc;     // "A,B->C M=.. N=.. K=.. batch=.. cfg=.. split=.."
+    std::string key;      // cache key (shape signature)
+    double ms = 0;        // device time accumulated in timing mode
+    int64_t calls = 0;
+    bool tuned = false;   // tile configuration chosen by measurement
+    int64_t kM = 0, kN = 0, K = 0, Z = 0;
 };
 
 struct Counters {
@@ -117,6 +123,11 @@ class Engine {
 
     // Reduced QR (FP64) of `batch` matrices; see tnk::QrArgs.
     void qr(const tnk::QrArgs &a);
+    // Q factor only (R is not formed), m >= n, n <= 64: shifted CholeskyQR3 in
+    // FP64 -- three passes of Gram matrix (MFMA), Cholesky and R^{-1} (one
+    // workgroup), Q <- Q R^{-1} (MFMA); the first pass adds the shift
+    // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots.
+    void orthonormalise(const tnk::QrArgs &a);
     // norm2 per batch item into dev[batch]; normalise in place; logscale +=.
     void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
     void normalise(void *x, int e, int64_t n, int batch, int64_t bs, double *logscale, bool acc,
@@ -129,12 +140,31 @@ class Engine {
     size_t held() const { return pool_.held(); }
 
     void sync() { TN_HIP(hipStreamSynchronize(s)); }
+    // Waits for the stream and adds the elapsed times of the event pairs recorded
+    // since the last collection to the counters (timing mode).
+    void collect_timing();
+    // Text table of the contraction plans by accumulated device time (timing mode).
+    std::string plan_report(int top) const;
+    // Autotuning: on the first call of a contraction shape, every tile
+    // configuration (and split-K choice) is timed on the real operands and the
+    // fastest kept.  Choices are read from / appended to `cache_path` if given.
+    void set_autotune(bool on, const std::string &cache_path);
 
   private:
     Pool pool_;
     std::unordered_map<std::string, std::unique_ptr<Plan>> plans_;
     Plan *plan(const Op &A, const Op &B, const Op &C);
-    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    // event pairs recorded around launches in timing mode: kind 0 = contraction, 1 = QR
+    struct EvPair { hipEvent_t a, b; int kind; Plan *plan; };
+    std::vector<EvPair> ev_;
+    size_t ev_used_ = 0;
+    bool in_qr_ = false;  // contractions issued by the QR are booked as QR work
+    bool autotune_ = false;
+    std::string tune_path_;
+    std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)
+    void set_split(Plan *P, int cfg, int ksplit_hint);
+    void tune(Plan *P, tnk::GettArgs g);
+    EvPair &next_pair(int kind);
 };
 
 }  // namespace tnb

@@ -100,8 +100,8 @@ void unit1(Engine &E, Ten &t) { E.normalise(t.p, t.esz, t.numel(), 1, 0, nullptr
 
 }  // namespace
 
-void environments(Engine &E, const PepsDev &P, const FitOpts &o, double *rho1, double *zz_h, double *zz_v,
-                  double *p2_h, double *p2_v) {
+void environments(Engine &E, const PepsDev &P, const FitOpts &o, const BoundarySet *below_in, double *rho1,
+                  double *zz_h, double *zz_v, double *p2_h, double *p2_v) {
     const int rows = P.rows, cols = P.cols;
     const double nan = __builtin_nan("");
     TN_HIP(tnk::launch_fill_f64(rho1, (int64_t)rows * cols * 8, nan, E.s));
@@ -112,7 +112,9 @@ void environments(Engine &E, const PepsDev &P, const FitOpts &o, double *rho1, d
     if (p2_v && rows > 1) TN_HIP(tnk::launch_fill_f64(p2_v, (int64_t)(rows - 1) * cols * 4, nan, E.s));
     const LView V = make_view(P, 0);
     const LView F = make_view(P, 1);
-    BoundarySet below = boundary_set(E, V, o, 0);
+    BoundarySet own;
+    if (!below_in) own = boundary_set(E, V, o, 0);
+    const BoundarySet &below = below_in ? *below_in : own;
     BoundarySet fb = boundary_set(E, F, o, 1);
     auto above = [&](int r) -> const DMps & { return fb.below[rows - 1 - r]; };
     double *dots = reinterpret_cast<double *>(E.raw(8 * 8));
@@ -188,13 +190,13 @@ void environments(Engine &E, const PepsDev &P, const FitOpts &o, double *rho1, d
         }
     } catch (...) {
         E.unraw(dots);
-        free_set(E, below);
+        free_set(E, own);
         free_set(E, fb);
         throw;
     }
     E.sync();
     E.unraw(dots);
-    free_set(E, below);
+    free_set(E, own);
     free_set(E, fb);
 }
 

@@ -56,6 +56,8 @@ __device__ inline int xcd_remap(int t, int ntiles) {
 
 // --------------------------------------------------------------------------
 // FP64 / FP32: one MFMA 16x16x4 per real product, 4 per complex product.
+// Two LDS stages: the tile for step k+1 is loaded from HBM into registers while
+// step k computes, then stored to the other stage; one barrier per step.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 gett_mfma(GettArgs p) {
@@ -68,8 +70,8 @@ gett_mfma(GettArgs p) {
     constexpr int LB = (BK * BN) / NT;
     constexpr int PA = BM + 2, PB = BN + 2;
     static_assert(LA >= 1 && LB >= 1 && NT % BK == 0 && NT >= BM && NT >= BN, "tile");
-    __shared__ T sA[2][BK][PA];
-    __shared__ T sB[2][BK][PB];
+    __shared__ T sA[2][2][BK][PA];  // [stage][re/im][k][m]
+    __shared__ T sB[2][2][BK][PB];
 
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
@@ -120,38 +122,46 @@ gett_mfma(GettArgs p) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = T(0); accI[i][j][r] = T(0); }
 
+        const int kbeg = blockIdx.z * p.kchunk;
+        const int kend = min(p.K, kbeg + p.kchunk);
         C2 ra[LA], rb[LB];
         auto gload = [&](int k0) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 const int k = k0 + ak[i];
                 C2 v; v.x = T(0); v.y = T(0);
-                if (amo[i] >= 0 && k < p.K) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
+                if (amo[i] >= 0 && k < kend) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
                 ra[i] = v;
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
                 const int k = k0 + bk[i];
                 C2 v; v.x = T(0); v.y = T(0);
-                if (bno[i] >= 0 && k < p.K) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
+                if (bno[i] >= 0 && k < kend) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
                 rb[i] = v;
             }
         };
-        gload(0);
-        for (int k0 = 0; k0 < p.K; k0 += BK) {
-            __syncthreads();
+        auto lstore = [&](int st) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
-                sA[0][ak[i]][am[i]] = ra[i].x;
-                sA[1][ak[i]][am[i]] = sgnA * ra[i].y;
+                sA[st][0][ak[i]][am[i]] = ra[i].x;
+                sA[st][1][ak[i]][am[i]] = sgnA * ra[i].y;
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
-                sB[0][bk[i]][bn[i]] = rb[i].x;
-                sB[1][bk[i]][bn[i]] = sgnB * rb[i].y;
+                sB[st][0][bk[i]][bn[i]] = rb[i].x;
+                sB[st][1][bk[i]][bn[i]] = sgnB * rb[i].y;
             }
-            __syncthreads();
-            if (k0 + BK < p.K) gload(k0 + BK);
+        };
+        // the previous batch item's last step may still read stage 0
+        __syncthreads();
+        gload(kbeg);
+        lstore(0);
+        __syncthreads();
+        int st = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += BK, st ^= 1) {
+            const bool more = k0 + BK < kend;
+            if (more) gload(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
@@ -159,14 +169,14 @@ gett_mfma(GettArgs p) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
                     const int mm = wm * WTM + i * 16 + (lane & 15);
-                    arv[i] = sA[0][kr][mm];
-                    aiv[i] = sA[1][kr][mm];
+                    arv[i] = sA[st][0][kr][mm];
+                    aiv[i] = sA[st][1][kr][mm];
                 }
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
                     const int nn = wn * WTN + j * 16 + (lane & 15);
-                    brv[j] = sB[0][kr][nn];
-                    biv[j] = sB[1][kr][nn];
+                    brv[j] = sB[st][0][kr][nn];
+                    biv[j] = sB[st][1][kr][nn];
                 }
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
@@ -178,27 +188,65 @@ gett_mfma(GettArgs p) {
                         accI[i][j] = Tr<T>::mma(aiv[i], brv[j], accI[i][j]);
                     }
             }
+            if (more) {
+                // the other stage was last read in the previous step, before the
+                // barrier that ended it
+                lstore(st ^ 1);
+                __syncthreads();
+            }
         }
         // epilogue: see Tr<T>::row for the accumulator layout
+        C2 *Pb = p.ksplit > 1
+                     ? reinterpret_cast<C2 *>(p.part) + ((int64_t)blockIdx.z * p.batch + b) * (int64_t)p.M * p.N
+                     : nullptr;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int n = n0 + wn * WTN + j * 16 + (lane & 15);
             if (n >= p.N) continue;
-            const int64_t cn = p.c_noff[n];
+            const int64_t cn = Pb ? 0 : p.c_noff[n];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int m = m0 + wm * WTM + i * 16 + Tr<T>::row(lane, r);
                     if (m >= p.M) continue;
-                    C2 *dst = Cb + p.c_moff[m] + cn;
                     C2 v;
                     v.x = accR[i][j][r];
                     v.y = accI[i][j][r];
+                    if (Pb) {
+                        Pb[(int64_t)m * p.N + n] = v;
+                        continue;
+                    }
+                    C2 *dst = Cb + p.c_moff[m] + cn;
                     if (p.accumulate) { const C2 o = *dst; v.x += o.x; v.y += o.y; }
                     *dst = v;
                 }
         }
+    }
+}
+
+// Sums the split-K partial products in slice order and writes C through its tables.
+template <typename C2>
+__global__ void __launch_bounds__(256) splitk_reduce(GettArgs p) {
+    const int64_t per = (int64_t)p.M * p.N;
+    const int64_t total = per * p.batch;
+    const C2 *P = reinterpret_cast<const C2 *>(p.part);
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int b = (int)(e / per);
+        const int64_t mn = e - (int64_t)b * per;
+        const int m = (int)(mn / p.N), n = (int)(mn - (int64_t)m * p.N);
+        double sr = 0.0, si = 0.0;
+        for (int z = 0; z < p.ksplit; ++z) {
+            const C2 v = P[(int64_t)z * total + e];
+            sr += v.x;
+            si += v.y;
+        }
+        C2 *dst = reinterpret_cast<C2 *>(p.C) + p.c_boff[b] + p.c_moff[m] + p.c_noff[n];
+        if (p.accumulate) { sr += dst->x; si += dst->y; }
+        C2 o;
+        o.x = sr;
+        o.y = si;
+        *dst = o;
     }
 }
 
@@ -236,9 +284,11 @@ gett_bf16(GettArgs p) {
     constexpr int LB = (BK * BN) / NT;
     constexpr int KP = BK + 8;  // padded k extent (bf16 elements), keeps 16-byte alignment
     static_assert(LA >= 1 && LB >= 1 && NT % BK == 0 && NT >= BM && NT >= BN, "tile");
-    // planes: [re/im][part][row][k]
-    __shared__ __attribute__((aligned(16))) unsigned short sA[2][NP][BM][KP];
-    __shared__ __attribute__((aligned(16))) unsigned short sB[2][NP][BN][KP];
+    // two LDS stages when they fit in the 160 KiB of a CU, else one
+    constexpr int S = (2 * 2 * NP * (BM + BN) * KP * 2 <= 160 * 1024) ? 2 : 1;
+    // planes: [stage][re/im][part][row][k]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[S][2][NP][BM][KP];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[S][2][NP][BN][KP];
 
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
@@ -285,33 +335,33 @@ gett_bf16(GettArgs p) {
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
+        const int kbeg = blockIdx.z * p.kchunk;
+        const int kend = min(p.K, kbeg + p.kchunk);
         float2 ra[LA], rb[LB];
         auto gload = [&](int k0) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 const int k = k0 + ak[i];
                 float2 v = make_float2(0.f, 0.f);
-                if (amo[i] >= 0 && k < p.K) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
+                if (amo[i] >= 0 && k < kend) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
                 ra[i] = v;
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
                 const int k = k0 + bk[i];
                 float2 v = make_float2(0.f, 0.f);
-                if (bno[i] >= 0 && k < p.K) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
+                if (bno[i] >= 0 && k < kend) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
                 rb[i] = v;
             }
         };
-        gload(0);
-        for (int k0 = 0; k0 < p.K; k0 += BK) {
-            __syncthreads();
+        auto lstore = [&](int st) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 unsigned short hr[NP], hi[NP];
                 split_bf16<NP>(ra[i].x, hr);
                 split_bf16<NP>(sgnA * ra[i].y, hi);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) { sA[0][q][am[i]][ak[i]] = hr[q]; sA[1][q][am[i]][ak[i]] = hi[q]; }
+                for (int q = 0; q < NP; ++q) { sA[st][0][q][am[i]][ak[i]] = hr[q]; sA[st][1][q][am[i]][ak[i]] = hi[q]; }
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
@@ -319,10 +369,17 @@ gett_bf16(GettArgs p) {
                 split_bf16<NP>(rb[i].x, hr);
                 split_bf16<NP>(sgnB * rb[i].y, hi);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) { sB[0][q][bn[i]][bk[i]] = hr[q]; sB[1][q][bn[i]][bk[i]] = hi[q]; }
+                for (int q = 0; q < NP; ++q) { sB[st][0][q][bn[i]][bk[i]] = hr[q]; sB[st][1][q][bn[i]][bk[i]] = hi[q]; }
             }
-            __syncthreads();
-            if (k0 + BK < p.K) gload(k0 + BK);
+        };
+        __syncthreads();  // the previous batch item's last step may still read stage 0
+        gload(kbeg);
+        lstore(0);
+        __syncthreads();
+        int st = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) gload(k0 + BK);
             const int kc = (lane >> 4) * 8;
             v8s a[2][NP][FM], bfr[2][NP][FN];
 #pragma unroll
@@ -331,10 +388,10 @@ gett_bf16(GettArgs p) {
                 for (int q = 0; q < NP; ++q) {
 #pragma unroll
                     for (int i = 0; i < FM; ++i)
-                        a[c][q][i] = *reinterpret_cast<const v8s *>(&sA[c][q][wm * WTM + i * 16 + (lane & 15)][kc]);
+                        a[c][q][i] = *reinterpret_cast<const v8s *>(&sA[st][c][q][wm * WTM + i * 16 + (lane & 15)][kc]);
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
-                        bfr[c][q][j] = *reinterpret_cast<const v8s *>(&sB[c][q][wn * WTN + j * 16 + (lane & 15)][kc]);
+                        bfr[c][q][j] = *reinterpret_cast<const v8s *>(&sB[st][c][q][wn * WTN + j * 16 + (lane & 15)][kc]);
                 }
             // negated imaginary parts of A for the Re C term (sign bit flip is exact)
             v8s an[NP][FM];
@@ -361,20 +418,34 @@ gett_bf16(GettArgs p) {
                                 __builtin_bit_cast(v8bf, a[1][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accI[i][j], 0, 0, 0);
                         }
                 }
+            if (more) {
+                if (S == 1) __syncthreads();  // single stage: every wave has read it
+                const int nx = (S == 2) ? (st ^ 1) : 0;
+                lstore(nx);
+                __syncthreads();
+                st = nx;
+            }
         }
+        float2 *Pb = p.ksplit > 1
+                         ? reinterpret_cast<float2 *>(p.part) + ((int64_t)blockIdx.z * p.batch + b) * (int64_t)p.M * p.N
+                         : nullptr;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int n = n0 + wn * WTN + j * 16 + (lane & 15);
             if (n >= p.N) continue;
-            const int64_t cn = p.c_noff[n];
+            const int64_t cn = Pb ? 0 : p.c_noff[n];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + r;
                     if (m >= p.M) continue;
-                    float2 *dst = Cb + p.c_moff[m] + cn;
                     float2 v = make_float2(accR[i][j][r], accI[i][j][r]);
+                    if (Pb) {
+                        Pb[(int64_t)m * p.N + n] = v;
+                        continue;
+                    }
+                    float2 *dst = Cb + p.c_moff[m] + cn;
                     if (p.accumulate) { const float2 o = *dst; v.x += o.x; v.y += o.y; }
                     *dst = v;
                 }
@@ -387,7 +458,18 @@ hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStre
     const int tiles = ((a.M + bm - 1) / bm) * ((a.N + bn - 1) / bn);
     const int gy = a.batch < 65535 ? a.batch : 65535;
     if (tiles <= 0 || a.batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kernel, dim3(tiles, gy), dim3(nt), 0, s, a);
+    const int gz = a.ksplit > 1 ? a.ksplit : 1;
+    hipLaunchKernelGGL(kernel, dim3(tiles, gy, gz), dim3(nt), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename C2>
+hipError_t launch_reduce(const GettArgs &a, hipStream_t s) {
+    if (a.ksplit <= 1) return hipSuccess;
+    const int64_t total = (int64_t)a.M * a.N * a.batch;
+    int64_t g = (total + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(splitk_reduce<C2>, dim3((unsigned)g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -403,8 +485,16 @@ void gett_tile(int cfg, int prec, int *bm, int *bn) {
     (void)prec;
 }
 
+static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t s);
+
 hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+    hipError_t e = launch_main(a, prec, cfg, s);
+    if (e != hipSuccess || a.ksplit <= 1) return e;
+    return prec == P_FP64 ? launch_reduce<double2>(a, s) : launch_reduce<float2>(a, s);
+}
+
+static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t s) {
     if (prec == P_FP64) {
         switch (cfg) {
             case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);

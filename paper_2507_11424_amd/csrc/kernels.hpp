@@ -24,6 +24,11 @@ struct GettArgs {
     int accumulate;      // 1: C += product, 0: C = product
     int a_kfast;         // 1: A is contiguous along k (load lanes along k), 0: along m
     int b_kfast;         // 1: B is contiguous along k, 0: along n
+    // split-K: ksplit slices of kchunk (multiple of 32) along k; slice z writes
+    // its partial product to part[z][b][m][n] (dense, storage type) and a
+    // reduction in fixed slice order writes C.  ksplit = 1: direct epilogue.
+    int ksplit, kchunk;
+    void *part;
 };
 
 // Tile configurations of the contraction kernel.
@@ -52,6 +57,18 @@ struct QrArgs {
 };
 size_t qr_workspace_bytes(int m, int n, int batch);
 hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
+
+// Cholesky of Hermitian G (batch x n x n, complex128, only the upper triangle is
+// read) as G + shift * tr(G)/n * I = R^H R, and Rinv = R^{-1} (upper triangular,
+// complex128, batch x n x n).  A pivot below clamp * tr(G)/n is raised to it
+// (flags[b] |= 4 when that happens).  One workgroup per matrix; n <= 128.
+hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv,
+                           int *flags, hipStream_t s);
+// out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element
+// strides (bs, rs, cs) on both sides, element sizes ie / oe, conjugation if conj.
+hipError_t launch_strided_copy(const void *in, int ie, int64_t ibs, int64_t irs, int64_t ics, void *out, int oe,
+                               int64_t obs, int64_t ors, int64_t ocs, int m, int n, int batch, int conj,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------- small kernels
 // out[b] = sum |x[b][i]|^2 over n complex elements (FP64 accumulation), batch
@@ -109,7 +126,14 @@ hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s);
 // dots [4][2] = complex P~(s, t) -> p2[4] = Re P / sum Re P (if p2), zz = sum (-1)^(s+t) Re P / sum Re P.
 hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t s);
 // Final amplitude -> log p.
-hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p,
+// xs[z] = bits[(row0 + z) * n_qubits + qubit] (0/1) for z < batch.
+hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs,
+                              hipStream_t s);
+// out[3] = {log mean(p/q), mean(log q - log p + log_Z), effective sample size};
+// z_is[n_qubits] (optional) = importance-weighted <Z_q> from bits [n][n_qubits].
+hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t n, double log_Z,
+                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s);
+hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
                        hipStream_t s);
 
 }  // namespace tnk

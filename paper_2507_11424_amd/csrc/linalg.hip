@@ -368,7 +368,111 @@ size_t global_qr_bytes(int m, int n, size_t *w, size_t *y, size_t *t, size_t *b)
     return off;
 }
 
+// ---------------------------------------------------------------- Cholesky + inverse
+// One workgroup per matrix, n <= 64, matrix in LDS.  Right-looking upper
+// Cholesky G + sI = R^H R, then R^{-1} by back substitution, one column per thread.
+__global__ void __launch_bounds__(256) k_chol_inv(const double2 *G, int n, double shift, double clamp, double2 *Rinv,
+                                                 int *flags) {
+    __shared__ double2 R[64][65];
+    __shared__ double2 Ri[64][65];
+    __shared__ double scale;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const double2 *Gb = G + (int64_t)b * n * n;
+    for (int e = t; e < n * n; e += 256) {
+        const int i = e / n, j = e % n;
+        const double2 g = j >= i ? Gb[i * n + j] : Gb[j * n + i];
+        R[i][j] = j >= i ? g : make_double2(g.x, -g.y);
+    }
+    __syncthreads();
+    if (t == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) tr += R[i][i].x;
+        scale = tr / n;
+    }
+    __syncthreads();
+    const double sh = shift * scale, cl = clamp * scale;
+    if (t < n) R[t][t].x += sh;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        double d = R[k][k].x;
+        if (!(d >= cl)) {
+            if (t == 0 && flags) flags[b] |= 4;
+            d = cl > 0.0 ? cl : 1e-300;
+        }
+        const double rkk = sqrt(d);
+        __syncthreads();
+        for (int j = k + t; j < n; j += 256) {
+            if (j == k) R[k][k] = make_double2(rkk, 0.0);
+            else { R[k][j].x /= rkk; R[k][j].y /= rkk; }
+        }
+        __syncthreads();
+        const int w = n - k - 1;
+        for (int e = t; e < w * w; e += 256) {
+            const int i = k + 1 + e / w, j = k + 1 + e % w;
+            if (j < i) continue;
+            const double2 a = R[k][i], c = R[k][j];  // conj(a) * c
+            R[i][j].x -= a.x * c.x + a.y * c.y;
+            R[i][j].y -= a.x * c.y - a.y * c.x;
+        }
+        __syncthreads();
+    }
+    if (t < n) {
+        const int j = t;
+        for (int i = j + 1; i < n; ++i) Ri[i][j] = make_double2(0.0, 0.0);
+        Ri[j][j] = make_double2(1.0 / R[j][j].x, 0.0);
+        for (int i = j - 1; i >= 0; --i) {
+            double sr = 0.0, si = 0.0;
+            for (int k = i + 1; k <= j; ++k) {
+                const double2 a = R[i][k], c = Ri[k][j];
+                sr += a.x * c.x - a.y * c.y;
+                si += a.x * c.y + a.y * c.x;
+            }
+            const double inv = 1.0 / R[i][i].x;
+            Ri[i][j] = make_double2(-sr * inv, -si * inv);
+        }
+    }
+    __syncthreads();
+    double2 *Ob = Rinv + (int64_t)b * n * n;
+    for (int e = t; e < n * n; e += 256) {
+        const int i = e / n, j = e % n;
+        Ob[e] = i <= j ? Ri[i][j] : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_strided_copy(const char *in, int ie, int64_t ibs, int64_t irs, int64_t ics,
+                                                     char *out, int oe, int64_t obs, int64_t ors, int64_t ocs, int m,
+                                                     int n, int batch, int conj) {
+    const int64_t per = (int64_t)m * n, total = per * batch;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int b = (int)(e / per);
+        const int64_t r = e - (int64_t)b * per;
+        const int i = (int)(r / n), j = (int)(r - (int64_t)i * n);
+        double2 v = ld_c(in, ie, (int64_t)b * ibs + (int64_t)i * irs + (int64_t)j * ics, conj);
+        st_c(out, oe, (int64_t)b * obs + (int64_t)i * ors + (int64_t)j * ocs, v, 0);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, int *flags,
+                           hipStream_t s) {
+    if (n > 64 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(256), 0, s, reinterpret_cast<const double2 *>(G), n, shift, clamp,
+                       reinterpret_cast<double2 *>(Rinv), flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_copy(const void *in, int ie, int64_t ibs, int64_t irs, int64_t ics, void *out, int oe,
+                               int64_t obs, int64_t ors, int64_t ocs, int m, int n, int batch, int conj,
+                               hipStream_t s) {
+    const int64_t total = (int64_t)m * n * batch;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_strided_copy, dim3((unsigned)g), dim3(256), 0, s, reinterpret_cast<const char *>(in), ie, ibs,
+                       irs, ics, reinterpret_cast<char *>(out), oe, obs, ors, ocs, m, n, batch, conj);
+    return hipGetLastError();
+}
 
 size_t qr_workspace_bytes(int m, int n, int batch) {
     if (m <= 0 || n <= 0) return 0;

@@ -151,8 +151,8 @@ std::vector<Ten> fit_single(Engine &E, const std::vector<Ten> &m, const std::vec
         const int tl = c > 0 ? t[c - 1] : 1, tr = c + 1 < L ? t[c] : 1;
         Y[c] = E.make({Z, tl, phys[c], tr});
         const int64_t per = Y[c].numel() / Z;
-        TN_HIP(tnk::launch_init_tensor(Y[c].p, Y[c].esz, per, Z, per, o.init_seed, 2, (uint64_t)row, (uint64_t)c,
-                                       sample_idx, E.s));
+        TN_HIP(tnk::launch_init_tensor(Y[c].p, Y[c].esz, per, Z, per, o.init_seed, (uint64_t)o.init_tag,
+                                       (uint64_t)row, (uint64_t)c, sample_idx, E.s));
     }
     right_canonicalise(E, Y, 1);
     auto rpart = [&](const Ten &R, int c) {  // [z,a,h,d,Y]
@@ -214,6 +214,29 @@ std::vector<Ten> fit_single(Engine &E, const std::vector<Ten> &m, const std::vec
         if (x.p) E.drop(x);
     unit(E, Y[0], Z, mlog);
     return Y;
+}
+
+// <x|psi> from the last amplitude boundary and the last projected row (whose
+// down legs have dimension 1): log_p[z] = 2 (mlog[z] + log|v_z|), arg[z] =
+// arg v_z (optional); amp is [Z] complex128 scratch.
+void last_row_amplitude(Engine &E, const std::vector<Ten> &m, const std::vector<Ten> &X, double *mlog, double *amp,
+                        double *log_p, double *arg) {
+    const int cols = (int)X.size();
+    const int Z = X[0].d[0];
+    Ten v = ones(E, {Z, 1, 1});
+    for (int c = 0; c < cols; ++c) {
+        Ten t1 = E.contract_new(op(v, "zah"), op(m[c], "zauA"), "zhuA");
+        Ten Xc = X[c];
+        Xc.d = {Z, X[c].d[1], X[c].d[2], X[c].d[4]};
+        Ten v2 = E.contract_new(op(t1, "zhuA"), op(Xc, "zuhH"), "zAH");
+        E.drop(t1);
+        E.drop(v);
+        v = v2;
+        if (c + 1 < cols) unit(E, v, Z, mlog);
+    }
+    TN_HIP(tnk::launch_convert(v.p, v.esz, amp, 16, Z, E.s));
+    TN_HIP(tnk::launch_logp(amp, mlog, Z, log_p, arg, E.s));
+    E.drop(v);
 }
 
 // Peak bytes per sample in flight for row sampling (right envs + intermediates).
@@ -359,24 +382,8 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
                     for (auto &x : m) E.drop(x);
                     m = mn;
-                } else {
-                    // amplitude <x|psi> from the last boundary and the last projected row
-                    Ten v = ones(E, {Z, 1, 1});
-                    for (int c = 0; c < cols; ++c) {
-                        Ten t1 = E.contract_new(op(v, "zah"), op(m[c], "zauA"), "zhuA");
-                        Ten Xc = X[c];
-                        Xc.d = {Z, X[c].d[1], X[c].d[2], X[c].d[4]};  // the last row has d = 1
-                        Ten v2 = E.contract_new(op(t1, "zhuA"), op(Xc, "zuhH"), "zAH");
-                        E.drop(t1);
-                        E.drop(v);
-                        v = v2;
-                        if (c + 1 < cols) unit(E, v, Z, mlog);
-                    }
-                    if (log_p) {
-                        TN_HIP(tnk::launch_convert(v.p, v.esz, amp, 16, Z, E.s));
-                        TN_HIP(tnk::launch_logp(amp, mlog, Z, log_p + w0, E.s));
-                    }
-                    E.drop(v);
+                } else if (log_p) {
+                    last_row_amplitude(E, m, X, mlog, amp, log_p + w0, nullptr);
                 }
                 for (auto &x : X) E.drop(x);
             }
@@ -394,6 +401,74 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
         throw;
     }
     E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+}
+
+void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first, int64_t n, const uint8_t *bits,
+               double *log_p, double *arg) {
+    const LView V = make_view(P, 0);
+    const int rows = V.rows, cols = V.cols;
+    int Zw = o.wave;
+    if (Zw <= 0) {
+        // peak per sample: the exact product m . X of one row and the fit's
+        // intermediates, a few chi_x^2 D^3-sized tensors per site
+        double per = 0;
+        for (int r = 0; r < rows; ++r) {
+            double row = 0;
+            for (int c = 0; c < cols; ++c) {
+                const SiteRef &a = V.at(r, c);
+                const double x = o.chi_x;
+                row += 6.0 * x * x * a.dim(1) * a.dim(2) * a.dim(3) * a.dim(4) / std::max(1, std::min(a.dim(1), a.dim(3)));
+            }
+            per = std::max(per, row);
+        }
+        per *= E.esz;
+        size_t freeb = 0, total = 0;
+        TN_HIP(hipMemGetInfo(&freeb, &total));
+        const double budget = 0.5 * (double)freeb + 0.5 * (double)E.held();
+        Zw = (int)std::max(1.0, std::min(4096.0, std::floor(budget / std::max(per, 1.0))));
+    }
+    Zw = (int)std::min<int64_t>(Zw, n);
+    uint64_t *sidx = reinterpret_cast<uint64_t *>(E.raw((size_t)Zw * 8));
+    double *mlog = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
+    int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
+    double *amp = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    std::vector<uint64_t> hidx(Zw);
+    try {
+        for (int64_t w0 = 0; w0 < n; w0 += Zw) {
+            const int Z = (int)std::min<int64_t>(Zw, n - w0);
+            for (int z = 0; z < Z; ++z) hidx[z] = first + (uint64_t)(w0 + z);
+            TN_HIP(hipMemcpyAsync(sidx, hidx.data(), (size_t)Z * 8, hipMemcpyHostToDevice, E.s));
+            TN_HIP(tnk::launch_fill_f64(mlog, Z, 0.0, E.s));
+            std::vector<Ten> m(cols);
+            for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
+            for (int r = 0; r < rows; ++r) {
+                std::vector<Ten> X(cols);
+                for (int c = 0; c < cols; ++c) {
+                    const SiteRef &a = V.at(r, c);
+                    int *xs = xsel + (size_t)c * Zw;
+                    const int q = P.site_index[(size_t)r * cols + c];
+                    if (a.dim(0) == 1 || q < 0) TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
+                    else TN_HIP(tnk::launch_bits_select(bits, P.nq, w0, q, Z, xs, E.s));
+                    X[c] = E.make({Z, a.dim(1), a.dim(2), a.dim(3), a.dim(4)});
+                    const int64_t per = X[c].numel() / Z;
+                    TN_HIP(tnk::launch_select_copy(a.t->p, a.t->esz, per, per, 0, xs, Z, X[c].p, per, E.s));
+                }
+                if (r + 1 < rows) {
+                    std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
+                    for (auto &x : m) E.drop(x);
+                    m = mn;
+                } else {
+                    last_row_amplitude(E, m, X, mlog, amp, log_p + w0, arg ? arg + w0 : nullptr);
+                }
+                for (auto &x : X) E.drop(x);
+            }
+            for (auto &x : m) E.drop(x);
+        }
+    } catch (...) {
+        E.unraw(sidx); E.unraw(mlog); E.unraw(xsel); E.unraw(amp);
+        throw;
+    }
+    E.unraw(sidx); E.unraw(mlog); E.unraw(xsel); E.unraw(amp);
 }
 
 }  // namespace tnb

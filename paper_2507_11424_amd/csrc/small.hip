@@ -221,11 +221,76 @@ __global__ void k_env_p2(const double *d, double *p2, double *zz) {
     if (zz) *zz = (P0 - P1 - P2 + P3) / S;
 }
 
-__global__ void k_logp(const double *amp, const double *mlog, int batch, double *log_p) {
+__global__ void k_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     const double a = hypot(amp[2 * b], amp[2 * b + 1]);
     log_p[b] = a > 0.0 ? 2.0 * (mlog[b] + log(a)) : -INFINITY;
+    if (arg) arg[b] = atan2(amp[2 * b + 1], amp[2 * b]);
+}
+
+// xs[z] = bits[(row0 + z) * n_qubits + qubit]: the given bit of every sample of
+// a wave, as the selector of the projected row tensor.
+__global__ void k_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= batch) return;
+    xs[z] = bits[(row0 + z) * n_qubits + qubit] ? 1 : 0;
+}
+
+// Sample-quality metrics over n samples, one workgroup of SN threads, fixed
+// reduction order.  w_i = exp(lw_i - max lw), lw = log p - log q:
+// out[0] = log((1/n) sum p/q), out[1] = (1/n) sum (log q - log p + log Z),
+// out[2] = (sum w)^2 / sum w^2; z_is[q] = sum_i w_i (1 - 2 x_iq) / sum_i w_i.
+constexpr int SN = 256;
+__device__ double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = SN / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SN) k_sample_stats(const double *lq, const double *lp, int64_t n, double logZ,
+                                                     const uint8_t *bits, int64_t nq, double *out, double *z_is) {
+    __shared__ double red[SN];
+    double mx = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += SN) mx = fmax(mx, lp[i] - lq[i]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = SN / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const double top = red[0];
+    __syncthreads();
+    double s1 = 0.0, s2 = 0.0, kl = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += SN) {
+        const double w = exp(lp[i] - lq[i] - top);
+        s1 += w;
+        s2 += w * w;
+        kl += lq[i] - lp[i] + logZ;
+    }
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    kl = block_sum(kl, red);
+    if (threadIdx.x == 0) {
+        out[0] = top + log(s1 / (double)n);
+        out[1] = kl / (double)n;
+        out[2] = s1 * s1 / s2;
+    }
+    if (!z_is) return;
+    for (int64_t q = threadIdx.x; q < nq; q += SN) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double w = exp(lp[i] - lq[i] - top);
+            acc += bits[i * nq + q] ? -w : w;
+        }
+        z_is[q] = acc / s1;
+    }
 }
 
 int grid_for(int64_t n) {
@@ -333,8 +398,23 @@ hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, hipStream_t s) {
-    hipLaunchKernelGGL(k_logp, dim3((batch + 63) / 64), dim3(64), 0, s, amp, mlog, batch, log_p);
+hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs,
+                              hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bits_select, dim3((batch + 63) / 64), dim3(64), 0, s, bits, n_qubits, row0, qubit, batch, xs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t n, double log_Z,
+                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_stats, dim3(1), dim3(SN), 0, s, log_q, log_p, n, log_Z, bits, n_qubits, out, z_is);
+    return hipGetLastError();
+}
+
+hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_logp, dim3((batch + 63) / 64), dim3(64), 0, s, amp, mlog, batch, log_p, arg);
     return hipGetLastError();
 }
 

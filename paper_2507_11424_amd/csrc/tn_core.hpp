@@ -71,8 +71,9 @@ BoundarySet boundary_set(Engine &E, const LView &V, const FitOpts &o, uint64_t t
 // log|Z| and arg Z from closing row 0 of the view against below[0]; synchronises.
 void norm_close(Engine &E, const LView &V, const BoundarySet &B, double *logabs, double *arg);
 
-void environments(Engine &E, const PepsDev &P, const FitOpts &o, double *rho1, double *zz_h,
-                  double *zz_v, double *p2_h, double *p2_v);
+// below: the bottom-up boundary set of P with the same options (computed here if null).
+void environments(Engine &E, const PepsDev &P, const FitOpts &o, const BoundarySet *below, double *rho1,
+                  double *zz_h, double *zz_v, double *p2_h, double *p2_v);
 
 struct SampleOpts {
     int chi_x = 16;
@@ -81,9 +82,17 @@ struct SampleOpts {
     uint64_t init_seed = 0;
     uint64_t seed = 0;
     int wave = 0;  // samples per wave (0 = automatic)
+    int init_tag = 2;  // Philox stream of the fit's random initial guesses
 };
 
 void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts &o, uint64_t first,
             int64_t n, const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
+
+// <x|psi> for given bitstrings bits [n][nq] (device) by single-layer boundary
+// MPSs of bond <= o.chi_x from the top row down; log_p [n] = 2 log|<x|psi>|,
+// arg [n] (optional) = its phase.  Sample index first + i keys the Philox
+// stream (tag o.init_tag) of the fits' initial guesses.
+void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first, int64_t n, const uint8_t *bits,
+               double *log_p, double *arg);
 
 }  // namespace tnb

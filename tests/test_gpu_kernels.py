@@ -31,6 +31,8 @@ CASES = [
     ("zbghkuA", "suhdH", "zbgkAsdH", dict(z=3, b=4, g=5, h=2, k=2, u=2, A=6, s=2, d=2, H=3)),
     ("ik", "kj", "ij", dict(i=1, k=300, j=1)),            # dot product
     ("ik", "kj", "ij", dict(i=2000, k=5, j=16)),          # skinny N
+    ("ik", "kj", "ij", dict(i=70, k=4100, j=50)),         # split-K with a ragged last slice
+    ("zki", "zkj", "zij", dict(z=3, k=1000, i=64, j=64)),  # batched split-K, K-contiguous A and B
 ]
 
 
@@ -59,6 +61,51 @@ def test_contract_matches_einsum(handle, prec, case, conj):
     scale = np.einsum(f"{ia},{ib}->{ic}", np.abs(A), np.abs(B))
     err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
     assert err < TOL[prec], err
+
+
+@pytest.fixture(scope="module")
+def tuned_handle(tmp_path_factory):
+    import paper_2507_11424_amd as tnb
+    h = tnb.Handle(0)
+    path = tmp_path_factory.mktemp("tune") / "choices.txt"
+    h.set_autotune(True, str(path))
+    yield h, path
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_autotuned_contract_matches_einsum(tuned_handle, prec, case):
+    """First call times the candidate tile/split-K configurations (relaunching
+    the kernel several times into C), second call runs the winner; both must
+    match, and an accumulating call on the tuned plan must add exactly once."""
+    import torch
+    h, path = tuned_handle
+    ia, ib, ic, dims = CASES[case]
+    rng = np.random.default_rng(300 + case)
+    A = _rand(rng, [dims[c] for c in ia])
+    B = _rand(rng, [dims[c] for c in ib])
+    td = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+    ref = np.einsum(f"{ia},{ib}->{ic}", A, B)
+    scale = np.einsum(f"{ia},{ib}->{ic}", np.abs(A), np.abs(B))
+    dA = torch.from_numpy(A).to("cuda", td)
+    dB = torch.from_numpy(B).to("cuda", td)
+    for call in range(2):
+        dC = torch.zeros([dims[c] for c in ic], dtype=td, device="cuda")
+        h.test_contract(prec, ia, dA, ib, dB, ic, dC)
+        torch.cuda.synchronize()
+        got = dC.cpu().numpy().astype(np.complex128)
+        err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+        assert err < TOL[prec], (call, err)
+    h.test_contract(prec, ia, dA, ib, dB, ic, dC, accumulate=True)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(got - 2 * ref) / np.maximum(scale, 1e-300))
+    assert err < 2 * TOL[prec], err
+    assert path.exists() and path.read_text().strip()
 
 
 def test_contract_accumulate(handle):
@@ -95,6 +142,33 @@ def test_qr(handle, m, n, batch, esz):
         assert np.abs(Q[b].conj().T @ Q[b] - np.eye(k)).max() < tol * max(m, 16)
         assert np.abs(Q[b] @ R[b] - A[b]).max() < tol * max(m, 16) * np.abs(A[b]).max()
         assert np.abs(np.tril(R[b], -1)).max() == 0.0
+
+
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (700, 33, 2), (512, 8, 5)])
+@pytest.mark.parametrize("esz", [16, 8])
+@pytest.mark.parametrize("cond", [1.0, 1e6, 1e12])
+def test_orthonormalise(handle, m, n, batch, esz, cond):
+    # Q only (shifted CholeskyQR3): orthonormal columns spanning the columns of A,
+    # also for ill-conditioned A (singular values spread over `cond`)
+    import torch
+    rng = np.random.default_rng(m + n + int(np.log10(cond)))
+    U, _ = np.linalg.qr(_rand(rng, (batch, m, n)))
+    V, _ = np.linalg.qr(_rand(rng, (batch, n, n)))
+    s = np.logspace(0, -np.log10(cond), n)
+    A = (U * s[None, None, :]) @ V
+    if esz == 8:
+        A = A.astype(np.complex64).astype(np.complex128)
+    td = torch.complex128 if esz == 16 else torch.complex64
+    dA = torch.from_numpy(A).to("cuda", td)
+    dQ = torch.zeros((batch, m, n), dtype=td, device="cuda")
+    handle.test_qr(dA, dQ, None)
+    torch.cuda.synchronize()
+    Q = dQ.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if esz == 16 else 1e-5
+    for b in range(batch):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(n)).max() < tol * 10
+        proj = Q[b] @ (Q[b].conj().T @ A[b])
+        assert np.abs(proj - A[b]).max() < tol * 10 * np.abs(A[b]).max()
 
 
 def test_qr_rank_deficient(handle):
