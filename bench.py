@@ -48,12 +48,13 @@ def parse():
 
 
 def copy_reference(nbytes: int):
-    """A plain device-to-device copy of known size: reads and writes nbytes once."""
+    """A plain elementwise kernel of known traffic: reads nbytes and writes
+    nbytes once per launch (a shader kernel, so the HBM counters see it)."""
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
 

@@ -327,6 +327,29 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     const char lb = opB.idx.empty() ? 0 : opB.idx.back();
     g.a_kfast = (la && kl.find(la) != std::string::npos && stride(opA, la) == 1) ? 1 : 0;
     g.b_kfast = (lb && kl.find(lb) != std::string::npos && stride(opB, lb) == 1) ? 1 : 0;
+    // affine k tables need no table reads in the kernel
+    auto affine = [](const std::vector<int64_t> &t, int *ks) {
+        const int64_t s1 = t.size() > 1 ? t[1] : 0;
+        for (size_t k = 0; k < t.size(); ++k)
+            if (t[k] != (int64_t)k * s1) return false;
+        *ks = (int)s1;
+        return true;
+    };
+    g.a_ks = g.b_ks = 0;
+    g.a_kaff = affine(kak, &g.a_ks) ? 1 : 0;
+    g.b_kaff = affine(kbk, &g.b_ks) ? 1 : 0;
+    // operand windows (bytes) reachable from a batch item's base
+    auto window = [&](const std::vector<int64_t> &r, const std::vector<int64_t> &k) {
+        int64_t mr = 0, mk = 0;
+        for (int64_t x : r) mr = std::max(mr, x);
+        for (int64_t x : k) mk = std::max(mk, x);
+        return (mr + mk + 1) * (int64_t)esz;
+    };
+    const int64_t wa = window(kam, kak), wb = window(kbn, kbk);
+    if (wa > (int64_t)tnk::GETT_MAX_WINDOW || wb > (int64_t)tnk::GETT_MAX_WINDOW)
+        throw TnError(ST_UNSUPPORTED, "contraction operand spans more than 2 GiB per batch item: " + key);
+    g.a_bytes = (uint32_t)wa;
+    g.b_bytes = (uint32_t)wb;
     (void)kml; (void)knl;
     P->kM = kM; P->kN = kN; P->K = K; P->Z = Z;
     P->key = key;
@@ -368,6 +391,8 @@ void Engine::set_split(Plan *P, int cfg, int ksplit_hint) {
         const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
         if (tiles < 512 && K >= 256) ks = std::min<int64_t>((1024 + tiles - 1) / tiles, K / 128);
     }
+    // a k table staged in LDS bounds the K slice of a block
+    if (!g.a_kaff || !g.b_kaff) ks = std::max<int64_t>(ks, (K + tnk::GETT_KTAB - 1) / tnk::GETT_KTAB);
     g.ksplit = 1;
     g.kchunk = (int)K;
     if (ks > 1) {
@@ -451,9 +476,63 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
     }
 }
 
+// Bytes an operand spans per batch item (letters shared by all three operands
+// index the batch and are applied through the batch base).
+static int64_t op_window(const Op &o, const Op &x, const Op &y) {
+    int64_t w = 0;
+    for (size_t i = 0; i < o.idx.size(); ++i) {
+        const char c = o.idx[i];
+        if (x.idx.find(c) != std::string::npos && y.idx.find(c) != std::string::npos) continue;
+        w += (int64_t)(o.dims[i] - 1) * o.str[i];
+    }
+    return (w + 1) * (int64_t)o.esz;
+}
+
+// Restricts letter c of o (if present) to [i0, i0 + n).
+static Op slice(const Op &o, char c, int i0, int n) {
+    Op r = o;
+    const size_t i = o.idx.find(c);
+    if (i == std::string::npos) return r;
+    r.p = static_cast<const char *>(o.p) + (int64_t)i0 * o.str[i] * o.esz;
+    r.dims[i] = n;
+    return r;
+}
+
 void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     if (A.esz != esz || B.esz != esz || C.esz != esz)
         throw TnError(ST_INVALID, "operand element size does not match the compute precision");
+    // The kernel addresses A and B through buffer resources of < 2 GiB per
+    // batch item; a larger operand is cut along its widest-stride letter into
+    // slices that fit (a summed letter accumulates over its slices).
+    const int64_t lim = (int64_t)tnk::GETT_MAX_WINDOW;
+    const int64_t wa = op_window(A, B, C), wb = op_window(B, A, C);
+    if (wa > lim || wb > lim) {
+        const Op &X = wa > lim ? A : B;
+        const Op &Y = wa > lim ? B : A;
+        const int64_t w = wa > lim ? wa : wb;
+        int best = -1;
+        int64_t span = 0;
+        for (size_t i = 0; i < X.idx.size(); ++i) {
+            const char c = X.idx[i];
+            if (X.dims[i] < 2) continue;
+            if (Y.idx.find(c) != std::string::npos && C.idx.find(c) != std::string::npos) continue;
+            const int64_t sp = (int64_t)(X.dims[i] - 1) * X.str[i];
+            if (sp > span) { span = sp; best = (int)i; }
+        }
+        if (best < 0) throw TnError(ST_UNSUPPORTED, "contraction operand cannot be cut below 2 GiB");
+        const char c = X.idx[best];
+        const int dim = X.dims[best];
+        const int64_t step = X.str[best] * (int64_t)X.esz;
+        const int64_t rest = w - (int64_t)(dim - 1) * step;
+        const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, (lim - rest) / step + 1));
+        const bool summed = C.idx.find(c) == std::string::npos;
+        for (int i0 = 0; i0 < dim; i0 += chunk) {
+            const int n = std::min(chunk, dim - i0);
+            contract(slice(A, c, i0, n), slice(B, c, i0, n), slice(C, c, i0, n),
+                     summed ? (accumulate || i0 > 0) : accumulate);
+        }
+        return;
+    }
     Plan *P = plan(A, B, C);
     tnk::GettArgs g = P->base;
     g.A = P->swapped ? B.p : A.p;

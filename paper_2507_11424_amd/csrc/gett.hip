@@ -55,11 +55,61 @@ __device__ inline int xcd_remap(int t, int ntiles) {
 }
 
 // --------------------------------------------------------------------------
+// Operand staging shared by the kernels.
+//
+// Operands are read with raw buffer loads: the resource covers the operand's
+// window for the batch item, and an offset of 2^31 (beyond every window) makes
+// the hardware return zero, so the tile's ragged edges need no branches and all
+// loads of a stage issue back to back.  k offsets are affine (k * ks, kept in
+// registers) or come from the k table, staged into LDS once per block.
+constexpr uint32_t OOB = 0x80000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    // the base is the same for the whole workgroup (batch item); say so, so
+    // that the resource lives in scalar registers
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    void *u = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    // dword 3 of a gfx9 buffer resource: 32-bit data format, no swizzle
+    return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+template <typename C2> __device__ inline C2 bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ inline double2 bload<double2>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+template <> __device__ inline float2 bload<float2>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// Per-thread view of one operand tile: L elements at (row r[i], k index k[i])
+// inside the tile; row offsets resolved once per block.
+template <int L>
+struct Stager {
+    int ro[L];   // element offset of the row (m or n), -1 outside the matrix
+    int kk[L];   // k index inside the tile
+    const int *kt;  // LDS k table (block's K slice) or null when affine
+    int ks, kbeg, kend;
+    __device__ inline uint32_t off(int i, int k0, int esz) const {
+        const int k = k0 + kk[i];
+        const bool ok = ro[i] >= 0 && k < kend;
+        const int kc = k < kend ? k : kend - 1;
+        const int ko = kt ? kt[kc - kbeg] : kc * ks;
+        return ok ? (uint32_t)(ro[i] + ko) * (uint32_t)esz : OOB;
+    }
+};
+
+// Copies the block's K slice of a k table into LDS.
+__device__ inline void stage_ktab(int *dst, const int32_t *tab, int kbeg, int klen, int tid, int nt) {
+    for (int k = tid; k < klen; k += nt) dst[k] = tab[kbeg + k];
+}
+
+// --------------------------------------------------------------------------
 // FP64 / FP32: one MFMA 16x16x4 per real product, 4 per complex product.
 // Two LDS stages: the tile for step k+1 is loaded from HBM into registers while
 // step k computes, then stored to the other stage; one barrier per step.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN>
-__global__ void __launch_bounds__(64 * WGM * WGN)
+__global__ void __launch_bounds__(64 * WGM * WGN, 2)
 gett_mfma(GettArgs p) {
     using C2 = typename Tr<T>::C2;
     using Acc = typename Tr<T>::Acc;
@@ -69,9 +119,11 @@ gett_mfma(GettArgs p) {
     constexpr int LA = (BM * BK) / NT;
     constexpr int LB = (BK * BN) / NT;
     constexpr int PA = BM + 2, PB = BN + 2;
+    constexpr int ESZ = (int)sizeof(C2);
     static_assert(LA >= 1 && LB >= 1 && NT % BK == 0 && NT >= BM && NT >= BN, "tile");
     __shared__ T sA[2][2][BK][PA];  // [stage][re/im][k][m]
     __shared__ T sB[2][2][BK][PB];
+    extern __shared__ int ktab[];   // non-affine k tables of the block's K slice
 
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
@@ -79,30 +131,33 @@ gett_mfma(GettArgs p) {
     const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
     const int m0 = (tile / tiles_n) * BM;
     const int n0 = (tile % tiles_n) * BN;
+    const int kbeg = blockIdx.z * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
 
-    // per-thread load coordinates inside the tile
-    int am[LA], ak[LA], bk[LB], bn[LB];
+    int am[LA], bn[LB];
+    Stager<LA> sa;
+    Stager<LB> sb;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
-        if (p.a_kfast) { ak[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
-        else           { am[i] = tid % BM; ak[i] = tid / BM + (NT / BM) * i; }
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-        if (p.b_kfast) { bk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
-        else           { bn[i] = tid % BN; bk[i] = tid / BN + (NT / BN) * i; }
-    }
-    int amo[LA], bno[LB];
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
+        if (p.a_kfast) { sa.kk[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
+        else           { am[i] = tid % BM; sa.kk[i] = tid / BM + (NT / BM) * i; }
         const int m = m0 + am[i];
-        amo[i] = (m < p.M) ? p.a_moff[m] : -1;
+        sa.ro[i] = (m < p.M) ? p.a_moff[m] : -1;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
+        if (p.b_kfast) { sb.kk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
+        else           { bn[i] = tid % BN; sb.kk[i] = tid / BN + (NT / BN) * i; }
         const int n = n0 + bn[i];
-        bno[i] = (n < p.N) ? p.b_noff[n] : -1;
+        sb.ro[i] = (n < p.N) ? p.b_noff[n] : -1;
     }
+    sa.ks = p.a_ks; sb.ks = p.b_ks;
+    sa.kbeg = sb.kbeg = kbeg;
+    sa.kend = sb.kend = kend;
+    sa.kt = p.a_kaff ? nullptr : ktab;
+    sb.kt = p.b_kaff ? nullptr : ktab + (p.a_kaff ? 0 : p.kchunk);
+    if (!p.a_kaff) stage_ktab(ktab, p.a_koff, kbeg, kend - kbeg, tid, NT);
+    if (!p.b_kaff) stage_ktab(const_cast<int *>(sb.kt), p.b_koff, kbeg, kend - kbeg, tid, NT);
 
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -110,8 +165,8 @@ gett_mfma(GettArgs p) {
     const T sgnB = p.conjB ? T(-1) : T(1);
 
     for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
-        const C2 *Ab = reinterpret_cast<const C2 *>(p.A) + p.a_boff[b];
-        const C2 *Bb = reinterpret_cast<const C2 *>(p.B) + p.b_boff[b];
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(reinterpret_cast<const C2 *>(p.A) + p.a_boff[b], p.a_bytes);
+        const __amdgpu_buffer_rsrc_t rB = make_rsrc(reinterpret_cast<const C2 *>(p.B) + p.b_boff[b], p.b_bytes);
         C2 *Cb = reinterpret_cast<C2 *>(p.C) + p.c_boff[b];
 
         Acc accR[FM][FN], accI[FM][FN];
@@ -122,38 +177,32 @@ gett_mfma(GettArgs p) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = T(0); accI[i][j][r] = T(0); }
 
-        const int kbeg = blockIdx.z * p.kchunk;
-        const int kend = min(p.K, kbeg + p.kchunk);
         C2 ra[LA], rb[LB];
         auto gload = [&](int k0) {
+            uint32_t oa[LA], ob[LB];
 #pragma unroll
-            for (int i = 0; i < LA; ++i) {
-                const int k = k0 + ak[i];
-                C2 v; v.x = T(0); v.y = T(0);
-                if (amo[i] >= 0 && k < kend) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
-                ra[i] = v;
-            }
+            for (int i = 0; i < LA; ++i) oa[i] = sa.off(i, k0, ESZ);
 #pragma unroll
-            for (int i = 0; i < LB; ++i) {
-                const int k = k0 + bk[i];
-                C2 v; v.x = T(0); v.y = T(0);
-                if (bno[i] >= 0 && k < kend) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
-                rb[i] = v;
-            }
+            for (int i = 0; i < LB; ++i) ob[i] = sb.off(i, k0, ESZ);
+#pragma unroll
+            for (int i = 0; i < LA; ++i) ra[i] = bload<C2>(rA, oa[i]);
+#pragma unroll
+            for (int i = 0; i < LB; ++i) rb[i] = bload<C2>(rB, ob[i]);
         };
         auto lstore = [&](int st) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
-                sA[st][0][ak[i]][am[i]] = ra[i].x;
-                sA[st][1][ak[i]][am[i]] = sgnA * ra[i].y;
+                sA[st][0][sa.kk[i]][am[i]] = ra[i].x;
+                sA[st][1][sa.kk[i]][am[i]] = sgnA * ra[i].y;
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
-                sB[st][0][bk[i]][bn[i]] = rb[i].x;
-                sB[st][1][bk[i]][bn[i]] = sgnB * rb[i].y;
+                sB[st][0][sb.kk[i]][bn[i]] = rb[i].x;
+                sB[st][1][sb.kk[i]][bn[i]] = sgnB * rb[i].y;
             }
         };
-        // the previous batch item's last step may still read stage 0
+        // the previous batch item's last step may still read stage 0; the first
+        // pass also publishes the LDS k tables
         __syncthreads();
         gload(kbeg);
         lstore(0);
@@ -163,8 +212,8 @@ gett_mfma(GettArgs p) {
             const bool more = k0 + BK < kend;
             if (more) gload(k0 + BK);
 #pragma unroll
-            for (int kk = 0; kk < BK / 4; ++kk) {
-                const int kr = kk * 4 + (lane >> 4);
+            for (int kq = 0; kq < BK / 4; ++kq) {
+                const int kr = kq * 4 + (lane >> 4);
                 T arv[FM], aiv[FM], brv[FN], biv[FN];
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
@@ -183,8 +232,13 @@ gett_mfma(GettArgs p) {
 #pragma unroll
                     for (int j = 0; j < FN; ++j) {
                         accR[i][j] = Tr<T>::mma(arv[i], brv[j], accR[i][j]);
-                        accR[i][j] = Tr<T>::mma(-aiv[i], biv[j], accR[i][j]);
                         accI[i][j] = Tr<T>::mma(arv[i], biv[j], accI[i][j]);
+                    }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        accR[i][j] = Tr<T>::mma(-aiv[i], biv[j], accR[i][j]);
                         accI[i][j] = Tr<T>::mma(aiv[i], brv[j], accI[i][j]);
                     }
             }
@@ -225,7 +279,6 @@ gett_mfma(GettArgs p) {
     }
 }
 
-// Sums the split-K partial products in slice order and writes C through its tables.
 template <typename C2>
 __global__ void __launch_bounds__(256) splitk_reduce(GettArgs p) {
     const int64_t per = (int64_t)p.M * p.N;
@@ -290,43 +343,48 @@ gett_bf16(GettArgs p) {
     __shared__ __attribute__((aligned(16))) unsigned short sA[S][2][NP][BM][KP];
     __shared__ __attribute__((aligned(16))) unsigned short sB[S][2][NP][BN][KP];
 
+    extern __shared__ int ktab[];   // non-affine k tables of the block's K slice
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
     const int tiles_m = (p.M + BM - 1) / BM;
     const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
     const int m0 = (tile / tiles_n) * BM;
     const int n0 = (tile % tiles_n) * BN;
+    const int kbeg = blockIdx.z * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
 
-    int am[LA], ak[LA], bk[LB], bn[LB];
+    int am[LA], bn[LB];
+    Stager<LA> sa;
+    Stager<LB> sb;
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
-        if (p.a_kfast) { ak[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
-        else           { am[i] = tid % BM; ak[i] = tid / BM + (NT / BM) * i; }
-    }
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-        if (p.b_kfast) { bk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
-        else           { bn[i] = tid % BN; bk[i] = tid / BN + (NT / BN) * i; }
-    }
-    int amo[LA], bno[LB];
-#pragma unroll
-    for (int i = 0; i < LA; ++i) {
+        if (p.a_kfast) { sa.kk[i] = tid % BK; am[i] = tid / BK + (NT / BK) * i; }
+        else           { am[i] = tid % BM; sa.kk[i] = tid / BM + (NT / BM) * i; }
         const int m = m0 + am[i];
-        amo[i] = (m < p.M) ? p.a_moff[m] : -1;
+        sa.ro[i] = (m < p.M) ? p.a_moff[m] : -1;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
+        if (p.b_kfast) { sb.kk[i] = tid % BK; bn[i] = tid / BK + (NT / BK) * i; }
+        else           { bn[i] = tid % BN; sb.kk[i] = tid / BN + (NT / BN) * i; }
         const int n = n0 + bn[i];
-        bno[i] = (n < p.N) ? p.b_noff[n] : -1;
+        sb.ro[i] = (n < p.N) ? p.b_noff[n] : -1;
     }
+    sa.ks = p.a_ks; sb.ks = p.b_ks;
+    sa.kbeg = sb.kbeg = kbeg;
+    sa.kend = sb.kend = kend;
+    sa.kt = p.a_kaff ? nullptr : ktab;
+    sb.kt = p.b_kaff ? nullptr : ktab + (p.a_kaff ? 0 : p.kchunk);
+    if (!p.a_kaff) stage_ktab(ktab, p.a_koff, kbeg, kend - kbeg, tid, NT);
+    if (!p.b_kaff) stage_ktab(const_cast<int *>(sb.kt), p.b_koff, kbeg, kend - kbeg, tid, NT);
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave / WGN, wn = wave % WGN;
     const float sgnA = p.conjA ? -1.f : 1.f;
     const float sgnB = p.conjB ? -1.f : 1.f;
 
     for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
-        const float2 *Ab = reinterpret_cast<const float2 *>(p.A) + p.a_boff[b];
-        const float2 *Bb = reinterpret_cast<const float2 *>(p.B) + p.b_boff[b];
+        const __amdgpu_buffer_rsrc_t rA = make_rsrc(reinterpret_cast<const float2 *>(p.A) + p.a_boff[b], p.a_bytes);
+        const __amdgpu_buffer_rsrc_t rB = make_rsrc(reinterpret_cast<const float2 *>(p.B) + p.b_boff[b], p.b_bytes);
         float2 *Cb = reinterpret_cast<float2 *>(p.C) + p.c_boff[b];
         v4f accR[FM][FN], accI[FM][FN];
 #pragma unroll
@@ -335,24 +393,17 @@ gett_bf16(GettArgs p) {
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
-        const int kbeg = blockIdx.z * p.kchunk;
-        const int kend = min(p.K, kbeg + p.kchunk);
         float2 ra[LA], rb[LB];
         auto gload = [&](int k0) {
+            uint32_t oa[LA], ob[LB];
 #pragma unroll
-            for (int i = 0; i < LA; ++i) {
-                const int k = k0 + ak[i];
-                float2 v = make_float2(0.f, 0.f);
-                if (amo[i] >= 0 && k < kend) v = Ab[(int64_t)amo[i] + p.a_koff[k]];
-                ra[i] = v;
-            }
+            for (int i = 0; i < LA; ++i) oa[i] = sa.off(i, k0, 8);
 #pragma unroll
-            for (int i = 0; i < LB; ++i) {
-                const int k = k0 + bk[i];
-                float2 v = make_float2(0.f, 0.f);
-                if (bno[i] >= 0 && k < kend) v = Bb[(int64_t)bno[i] + p.b_koff[k]];
-                rb[i] = v;
-            }
+            for (int i = 0; i < LB; ++i) ob[i] = sb.off(i, k0, 8);
+#pragma unroll
+            for (int i = 0; i < LA; ++i) ra[i] = bload<float2>(rA, oa[i]);
+#pragma unroll
+            for (int i = 0; i < LB; ++i) rb[i] = bload<float2>(rB, ob[i]);
         };
         auto lstore = [&](int st) {
 #pragma unroll
@@ -361,7 +412,7 @@ gett_bf16(GettArgs p) {
                 split_bf16<NP>(ra[i].x, hr);
                 split_bf16<NP>(sgnA * ra[i].y, hi);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) { sA[st][0][q][am[i]][ak[i]] = hr[q]; sA[st][1][q][am[i]][ak[i]] = hi[q]; }
+                for (int q = 0; q < NP; ++q) { sA[st][0][q][am[i]][sa.kk[i]] = hr[q]; sA[st][1][q][am[i]][sa.kk[i]] = hi[q]; }
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
@@ -369,10 +420,12 @@ gett_bf16(GettArgs p) {
                 split_bf16<NP>(rb[i].x, hr);
                 split_bf16<NP>(sgnB * rb[i].y, hi);
 #pragma unroll
-                for (int q = 0; q < NP; ++q) { sB[st][0][q][bn[i]][bk[i]] = hr[q]; sB[st][1][q][bn[i]][bk[i]] = hi[q]; }
+                for (int q = 0; q < NP; ++q) { sB[st][0][q][bn[i]][sb.kk[i]] = hr[q]; sB[st][1][q][bn[i]][sb.kk[i]] = hi[q]; }
             }
         };
-        __syncthreads();  // the previous batch item's last step may still read stage 0
+        // the previous batch item's last step may still read stage 0; the first
+        // pass also publishes the LDS k tables
+        __syncthreads();
         gload(kbeg);
         lstore(0);
         __syncthreads();
@@ -459,7 +512,17 @@ hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStre
     const int gy = a.batch < 65535 ? a.batch : 65535;
     if (tiles <= 0 || a.batch <= 0) return hipSuccess;
     const int gz = a.ksplit > 1 ? a.ksplit : 1;
-    hipLaunchKernelGGL(kernel, dim3(tiles, gy, gz), dim3(nt), 0, s, a);
+    if ((!a.a_kaff || !a.b_kaff) && a.kchunk > GETT_KTAB) return hipErrorInvalidValue;
+    const size_t dyn = (size_t)((a.a_kaff ? 0 : a.kchunk) + (a.b_kaff ? 0 : a.kchunk)) * sizeof(int);
+    static bool attr = false;  // one per kernel instantiation
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)(2 * GETT_KTAB * sizeof(int)));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(kernel, dim3(tiles, gy, gz), dim3(nt), dyn, s, a);
     return hipGetLastError();
 }
 
@@ -500,7 +563,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_mfma<double, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_mfma<double, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
-            default: return launch_k(gett_mfma<double, 128, 128, 8, 2, 2>, a, 128, 128, 256, s);
+            default: return hipErrorInvalidValue;
         }
     }
     if (prec == P_FP32) {
@@ -508,7 +571,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_mfma<float, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_mfma<float, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_mfma<float, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
-            default: return launch_k(gett_mfma<float, 128, 128, 8, 2, 2>, a, 128, 128, 256, s);
+            default: return hipErrorInvalidValue;
         }
     }
     if (prec == P_BF16X3) {
@@ -516,14 +579,14 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_bf16<2, 64, 64, 2, 2>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_bf16<2, 128, 64, 2, 2>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_bf16<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
-            default: return launch_k(gett_bf16<2, 128, 128, 2, 2>, a, 128, 128, 256, s);
+            default: return hipErrorInvalidValue;
         }
     }
     switch (cfg) {
         case CFG_64x64: return launch_k(gett_bf16<3, 64, 64, 2, 2>, a, 64, 64, 256, s);
         case CFG_128x64: return launch_k(gett_bf16<3, 128, 64, 2, 2>, a, 128, 64, 256, s);
         case CFG_64x16: return launch_k(gett_bf16<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
-        default: return launch_k(gett_bf16<3, 128, 128, 2, 2>, a, 128, 128, 256, s);
+        default: return hipErrorInvalidValue;
     }
 }
 

@@ -29,7 +29,18 @@ struct GettArgs {
     // reduction in fixed slice order writes C.  ksplit = 1: direct epilogue.
     int ksplit, kchunk;
     void *part;
+    // k offsets: affine (offset of k = k * ks, no table read) or read from the
+    // k table, which the kernel stages into LDS once (kchunk <= GETT_KTAB).
+    int a_kaff, b_kaff;
+    int a_ks, b_ks;
+    // operand windows in bytes from each batch item's base (all offsets
+    // reachable through the tables); operands are read with buffer loads whose
+    // range check returns zero for padding, so a window must stay below 2^31.
+    uint32_t a_bytes, b_bytes;
 };
+// Largest K slice a block handles when a k table is not affine (LDS table).
+constexpr int GETT_KTAB = 1024;
+constexpr uint32_t GETT_MAX_WINDOW = 0x7FFFFFF0u;
 
 // Tile configurations of the contraction kernel.
 enum GettCfg : int {

@@ -416,19 +416,38 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double2 *G, int n, doubl
         }
         __syncthreads();
     }
-    if (t < n) {
-        const int j = t;
-        for (int i = j + 1; i < n; ++i) Ri[i][j] = make_double2(0.0, 0.0);
-        Ri[j][j] = make_double2(1.0 / R[j][j].x, 0.0);
-        for (int i = j - 1; i >= 0; --i) {
-            double sr = 0.0, si = 0.0;
-            for (int k = i + 1; k <= j; ++k) {
-                const double2 a = R[i][k], c = Ri[k][j];
-                sr += a.x * c.x - a.y * c.y;
-                si += a.x * c.y + a.y * c.x;
+    // R^{-1} column j by back substitution, four lanes per column (the lanes of
+    // a column are adjacent in one wave): each sums every fourth term of
+    // sum_{k>i} R[i][k] Ri[k][j], a butterfly adds the four, every lane writes
+    // the (identical) result; the wave's LDS accesses are ordered, so later
+    // steps of the column read it.
+    {
+        const int j = t >> 2, q = t & 3;
+        if (j < n) {
+            if (q == 0) {
+                for (int i = j + 1; i < n; ++i) Ri[i][j] = make_double2(0.0, 0.0);
+                Ri[j][j] = make_double2(1.0 / R[j][j].x, 0.0);
             }
-            const double inv = 1.0 / R[i][i].x;
-            Ri[i][j] = make_double2(-sr * inv, -si * inv);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int i = n - 2; i >= 0; --i) {
+            double sr = 0.0, si = 0.0;
+            if (j < n && i < j) {
+                for (int k = i + 1 + q; k <= j; k += 4) {
+                    const double2 a = R[i][k], c = Ri[k][j];
+                    sr += a.x * c.x - a.y * c.y;
+                    si += a.x * c.y + a.y * c.x;
+                }
+            }
+            sr += __shfl_xor(sr, 1);
+            si += __shfl_xor(si, 1);
+            sr += __shfl_xor(sr, 2);
+            si += __shfl_xor(si, 2);
+            if (j < n && i < j) {
+                const double inv = 1.0 / R[i][i].x;
+                Ri[i][j] = make_double2(-sr * inv, -si * inv);
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();

@@ -184,3 +184,40 @@ def test_qr_rank_deficient(handle):
     Q, R = dQ.cpu().numpy()[0], dR.cpu().numpy()[0]
     assert np.all(np.isfinite(Q))
     assert np.abs(Q @ R - A[0]).max() < 1e-10 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("layout", ["ik,kj->ij", "ki,kj->ij"])
+def test_contract_operand_over_2gib(handle, layout):
+    """An operand spanning more than 2 GiB is cut into slices on the host (the
+    kernel's buffer resources address < 2 GiB); rows sampled across the cuts
+    must match float64 NumPy.  With "ki" the cut letter is the summed one, so
+    the slices accumulate."""
+    import torch
+    ia, rest = layout.split(",")
+    ib, ic = rest.split("->")
+    big = (1 << 23) + 5           # 2^23 + 5 rows x 16 x 16 B = 2.15 GB
+    g = torch.Generator(device="cuda").manual_seed(3)
+    if ia == "ik":
+        A = torch.randn((big, 16), dtype=torch.complex128, device="cuda", generator=g)
+        B = torch.randn((16, 8), dtype=torch.complex128, device="cuda", generator=g)
+        C = torch.empty((big, 8), dtype=torch.complex128, device="cuda")
+    else:  # summed letter is the long one: C[i, j] = sum_k A[k, i] B[k, j]
+        A = torch.randn((big, 16), dtype=torch.complex128, device="cuda", generator=g)
+        B = torch.randn((big, 8), dtype=torch.complex128, device="cuda", generator=g)
+        C = torch.empty((16, 8), dtype=torch.complex128, device="cuda")
+    handle.test_contract("fp64", ia, A, ib, B, ic, C)
+    torch.cuda.synchronize()
+    if ia == "ik":
+        rows = np.array([0, 1, 77, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, big - 2, big - 1])
+        a = A[torch.from_numpy(rows).cuda()].cpu().numpy()
+        ref = a @ B.cpu().numpy()
+        got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+        scale = np.abs(a) @ np.abs(B.cpu().numpy())
+    else:
+        a, b = A.cpu().numpy(), B.cpu().numpy()
+        ref = a.T @ b
+        got = C.cpu().numpy()
+        scale = np.abs(a).T @ np.abs(b)
+    del A, B
+    torch.cuda.empty_cache()
+    assert np.max(np.abs(got - ref) / scale) < 1e-12
