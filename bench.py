@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's heuristic tile choice instead of timing the candidates")
+    ap.add_argument("--tune-cache", default="",
+                    help="text file of tile choices: loaded if present, new choices appended")
     ap.add_argument("--plan-report", default="", help="write the per-shape contraction timing table here")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
@@ -145,7 +147,7 @@ def main():
     stream = torch.cuda.current_stream(0)
     h = tnb.Handle(0, stream)
     # tile configurations are timed on each new contraction shape during warmup
-    h.set_autotune(not a.no_autotune)
+    h.set_autotune(not a.no_autotune, a.tune_cache or None)
     # inputs resident in HBM before timing (stored as the configured type, computed in the mode's type)
     P = tnb.Peps.from_numpy(lat, T, dtype=dev_dtype, device="cuda:0")
     o = tnb.make_opts(chi=chi, chi_x=chi_x, prec=a.prec)
@@ -181,16 +183,17 @@ def main():
     # between launches; the events are read when each call returns)
     t0 = time.perf_counter()
     acc = {k: [0.0, 0.0] for k in phases}
-    gemm_ms = gemm_flops = qr_ms = 0.0
+    gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = 0.0
     launches = 0
     for i in range(a.steps):
         lz, rec = step(timing=True)
         for k, (sec, c) in rec.items():
             acc[k][0] += sec
-            acc[k][1] += c["gemm_flops"]
+            acc[k][1] += c["gemm_flops"] - c["qr_gemm_flops"]
             gemm_ms += c["gemm_ms"]
             gemm_flops += c["gemm_flops"]
             qr_ms += c["qr_ms"]
+            qr_gemm_flops += c["qr_gemm_flops"]
             launches += c["gemm_launches"]
         print(f"timed step {i} done ({time.perf_counter() - t0:.1f} s so far)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -202,6 +205,7 @@ def main():
     gemm_ms /= a.steps
     gemm_flops /= a.steps
     qr_ms /= a.steps
+    qr_gemm_flops /= a.steps
     launches //= a.steps
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     samples = a.samples * a.steps
@@ -228,8 +232,13 @@ def main():
         "log_abs_Z": lz,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[a.prec], "traffic": None,
-                     "kernel": "gett (complex contraction engine)", "launches_per_step": launches,
-                     "algorithmic_flops_per_step": gemm_flops, "kernel_ms_per_step": gemm_ms,
+                     "kernel": "gett (complex contraction engine, all tile variants, with its split-K "
+                               "reduction)",
+                     "launches_per_step": launches,
+                     "kernel_avg_us": 1e3 * gemm_ms / launches if launches else None,
+                     "algorithmic_flops_per_step": gemm_flops,
+                     "of_which_orthonormalisation_flops": qr_gemm_flops,
+                     "kernel_ms_per_step": gemm_ms,
                      "qr_ms_per_step": qr_ms},
     }
     if not a.no_cpu_baseline:

@@ -178,13 +178,18 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
 /* Text of the last error on this handle ("" if none).  Valid until the next call. */
 const char *tn_last_error(const tn_handle *h);
 
-/* Work counters of the last call: the algorithmic flops of every contraction
- * issued (8 real flops per complex multiply-add, summed over the actual index
- * dimensions), their count, and -- when timing is enabled -- the summed device
- * time of the contraction and of the QR kernels in milliseconds (HIP events on
- * the handle's stream).  Any pointer may be NULL. */
+/* Work counters of the last call: the flops of every contraction kernel
+ * launch (8 real flops per complex multiply-add, summed over the actual index
+ * dimensions), the launch count, and -- when timing is enabled -- the summed
+ * device time of those launches and of the QR / orthonormalisation calls in
+ * milliseconds (HIP events on the handle's stream).  The orthonormalisation
+ * issues contractions of its own (Gram matrices, triangular solves): they are
+ * included in gemm_* and in qr_ms, and their flops are also reported in
+ * qr_gemm_flops, so gemm_flops - qr_gemm_flops is the method's own work.
+ * Any pointer may be NULL. */
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
-                          double *gemm_ms, double *qr_ms, int64_t *qr_launches);
+                          double *gemm_ms, double *qr_ms, int64_t *qr_launches,
+                          double *qr_gemm_flops);
 
 /* Enables (1) or disables (0) per-launch HIP-event timing: an event pair is
  * recorded around every contraction and QR launch on the handle's stream and read

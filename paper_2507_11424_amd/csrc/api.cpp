@@ -332,7 +332,7 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
 const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "null handle"; }
 
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
-                          double *qr_ms, int64_t *qr_launches) {
+                          double *qr_ms, int64_t *qr_launches, double *qr_gemm_flops) {
     if (!h || !h->E) return TN_ERR_INVALID;
     try {
         const_cast<Engine *>(h->E.get())->collect_timing();
@@ -345,6 +345,7 @@ tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_
     if (gemm_ms) *gemm_ms = c.gemm_ms;
     if (qr_ms) *qr_ms = c.qr_ms;
     if (qr_launches) *qr_launches = c.qr_launches;
+    if (qr_gemm_flops) *qr_gemm_flops = c.qr_gemm_flops;
     return TN_OK;
 }
 

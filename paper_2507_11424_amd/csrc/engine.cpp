@@ -552,7 +552,9 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         g.part = part;
     }
     // inside the QR the enclosing event pair already times the launch
-    EvPair *ev = (timing && !in_qr_) ? &next_pair(0) : nullptr;
+    // contractions inside the orthonormalisation are timed too (their QR-level
+    // pair also covers them); their flops are booked separately
+    EvPair *ev = timing ? &next_pair(0) : nullptr;
     if (ev) {
         ev->plan = P;
         TN_HIP(hipEventRecord(ev->a, s));
@@ -560,7 +562,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     TN_HIP(tnk::launch_gett(g, prec, P->cfg, s));
     if (ev) TN_HIP(hipEventRecord(ev->b, s));
     if (part) pool_.put(part);
-    if (in_qr_) return;
+    if (in_qr_) ctr.qr_gemm_flops += P->flops;
     ctr.gemm_flops += P->flops;
     ctr.gemm_launches += 1;
 }

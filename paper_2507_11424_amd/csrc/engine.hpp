@@ -96,6 +96,7 @@ struct Counters {
     double gemm_ms = 0;
     double qr_ms = 0;
     int64_t qr_launches = 0;
+    double qr_gemm_flops = 0;  // part of gemm_flops issued inside orthonormalisations
     void reset() { *this = Counters(); }
 };
 
@@ -158,7 +159,7 @@ class Engine {
     struct EvPair { hipEvent_t a, b; int kind; Plan *plan; };
     std::vector<EvPair> ev_;
     size_t ev_used_ = 0;
-    bool in_qr_ = false;  // contractions issued by the QR are booked as QR work
+    bool in_qr_ = false;  // contractions issued by the QR: flops booked as qr_gemm_flops
     bool autotune_ = false;
     std::string tune_path_;
     std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)
