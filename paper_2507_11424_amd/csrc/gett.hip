@@ -63,6 +63,7 @@ __device__ inline int xcd_remap(int t, int ntiles) {
 // loads of a stage issue back to back.  k offsets are affine (k * ks, kept in
 // registers) or come from the k table, staged into LDS once per block.
 constexpr uint32_t OOB = 0x80000000u;
+constexpr bool GAUSS3M = true;  // 64x64 and 64x16 FP64 / FP32 tiles; 128x64 keeps 4M (3M would spill)
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
     // the base is the same for the whole workgroup (batch item); say so, so
@@ -105,10 +106,14 @@ __device__ inline void stage_ktab(int *dst, const int32_t *tab, int kbeg, int kl
 }
 
 // --------------------------------------------------------------------------
-// FP64 / FP32: one MFMA 16x16x4 per real product, 4 per complex product.
+// FP64 / FP32: one MFMA 16x16x4 per real product; 4 per complex product (4M)
+// or 3 with the Gauss form (3M): aR bR, aI bI and (aR + aI)(bR + bI), the
+// sums formed in registers after the LDS reads.  3M saves a quarter of the
+// MFMA work; its imaginary part, P3 - P1 - P2, carries about twice the
+// rounding error of 4M relative to sum |a||b|.
 // Two LDS stages: the tile for step k+1 is loaded from HBM into registers while
 // step k computes, then stored to the other stage; one barrier per step.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool G3>
 __global__ void __launch_bounds__(64 * WGM * WGN, 2)
 gett_mfma(GettArgs p) {
     using C2 = typename Tr<T>::C2;
@@ -169,13 +174,23 @@ gett_mfma(GettArgs p) {
         const __amdgpu_buffer_rsrc_t rB = make_rsrc(reinterpret_cast<const C2 *>(p.B) + p.b_boff[b], p.b_bytes);
         C2 *Cb = reinterpret_cast<C2 *>(p.C) + p.c_boff[b];
 
-        Acc accR[FM][FN], accI[FM][FN];
+        // 4M: accR, accI.  3M (G3): accR = sum aR bR, accI = sum aI bI,
+        // acc3 = sum (aR + aI)(bR + bI); Re = accR - accI, Im = acc3 - accR - accI.
+        Acc accR[FM][FN], accI[FM][FN], acc3[G3 ? FM : 1][G3 ? FN : 1];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = T(0); accI[i][j][r] = T(0); }
+        if constexpr (G3) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc3[i][j][r] = T(0);
+        }
 
         C2 ra[LA], rb[LB];
         auto gload = [&](int k0) {
@@ -227,20 +242,36 @@ gett_mfma(GettArgs p) {
                     brv[j] = sB[st][0][kr][nn];
                     biv[j] = sB[st][1][kr][nn];
                 }
+                if constexpr (G3) {
+                    T asv[FM], bsv[FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                    for (int i = 0; i < FM; ++i) asv[i] = arv[i] + aiv[i];
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        accR[i][j] = Tr<T>::mma(arv[i], brv[j], accR[i][j]);
-                        accI[i][j] = Tr<T>::mma(arv[i], biv[j], accI[i][j]);
-                    }
+                    for (int j = 0; j < FN; ++j) bsv[j] = brv[j] + biv[j];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                    for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        accR[i][j] = Tr<T>::mma(-aiv[i], biv[j], accR[i][j]);
-                        accI[i][j] = Tr<T>::mma(aiv[i], brv[j], accI[i][j]);
-                    }
+                        for (int j = 0; j < FN; ++j) {
+                            accR[i][j] = Tr<T>::mma(arv[i], brv[j], accR[i][j]);
+                            accI[i][j] = Tr<T>::mma(aiv[i], biv[j], accI[i][j]);
+                            acc3[i][j] = Tr<T>::mma(asv[i], bsv[j], acc3[i][j]);
+                        }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            accR[i][j] = Tr<T>::mma(arv[i], brv[j], accR[i][j]);
+                            accI[i][j] = Tr<T>::mma(arv[i], biv[j], accI[i][j]);
+                        }
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            accR[i][j] = Tr<T>::mma(-aiv[i], biv[j], accR[i][j]);
+                            accI[i][j] = Tr<T>::mma(aiv[i], brv[j], accI[i][j]);
+                        }
+                }
             }
             if (more) {
                 // the other stage was last read in the previous step, before the
@@ -265,8 +296,13 @@ gett_mfma(GettArgs p) {
                     const int m = m0 + wm * WTM + i * 16 + Tr<T>::row(lane, r);
                     if (m >= p.M) continue;
                     C2 v;
-                    v.x = accR[i][j][r];
-                    v.y = accI[i][j][r];
+                    if constexpr (G3) {
+                        v.x = accR[i][j][r] - accI[i][j][r];
+                        v.y = acc3[i][j][r] - accR[i][j][r] - accI[i][j][r];
+                    } else {
+                        v.x = accR[i][j][r];
+                        v.y = accI[i][j][r];
+                    }
                     if (Pb) {
                         Pb[(int64_t)m * p.N + n] = v;
                         continue;
@@ -560,17 +596,17 @@ hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s) {
 static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t s) {
     if (prec == P_FP64) {
         switch (cfg) {
-            case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
-            case CFG_128x64: return launch_k(gett_mfma<double, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
-            case CFG_64x16: return launch_k(gett_mfma<double, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
+            case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2, GAUSS3M>, a, 64, 64, 256, s);
+            case CFG_128x64: return launch_k(gett_mfma<double, 128, 64, 16, 2, 2, false>, a, 128, 64, 256, s);
+            case CFG_64x16: return launch_k(gett_mfma<double, 64, 16, 16, 4, 1, GAUSS3M>, a, 64, 16, 256, s);
             default: return hipErrorInvalidValue;
         }
     }
     if (prec == P_FP32) {
         switch (cfg) {
-            case CFG_64x64: return launch_k(gett_mfma<float, 64, 64, 16, 2, 2>, a, 64, 64, 256, s);
-            case CFG_128x64: return launch_k(gett_mfma<float, 128, 64, 16, 2, 2>, a, 128, 64, 256, s);
-            case CFG_64x16: return launch_k(gett_mfma<float, 64, 16, 16, 4, 1>, a, 64, 16, 256, s);
+            case CFG_64x64: return launch_k(gett_mfma<float, 64, 64, 16, 2, 2, GAUSS3M>, a, 64, 64, 256, s);
+            case CFG_128x64: return launch_k(gett_mfma<float, 128, 64, 16, 2, 2, false>, a, 128, 64, 256, s);
+            case CFG_64x16: return launch_k(gett_mfma<float, 64, 16, 16, 4, 1, GAUSS3M>, a, 64, 16, 256, s);
             default: return hipErrorInvalidValue;
         }
     }
