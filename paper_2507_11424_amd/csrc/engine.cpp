@@ -615,7 +615,7 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
             const double shift = pass == 0 ? 11.0 * ((double)m * n + (double)n * (n + 1)) * u * n : 0.0;
             const double clamp = pass == 0 ? 1e-300 : 1e-14;
             TN_HIP(tnk::launch_chol_inv(reinterpret_cast<const double *>(G.p), n, Z, shift, clamp,
-                                        reinterpret_cast<double *>(Ri.p), nullptr, s));
+                                        reinterpret_cast<double *>(Ri.p), nullptr, nullptr, s));
             contract(op(X, "bij"), op(Ri, "bjk"), op(Y, "bik"));
             std::swap(X, Y);
         }

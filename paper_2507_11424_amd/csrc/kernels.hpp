@@ -70,10 +70,11 @@ size_t qr_workspace_bytes(int m, int n, int batch);
 hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
 
 // Cholesky of Hermitian G (batch x n x n, complex128, only the upper triangle is
-// read) as G + shift * tr(G)/n * I = R^H R, and Rinv = R^{-1} (upper triangular,
-// complex128, batch x n x n).  A pivot below clamp * tr(G)/n is raised to it
-// (flags[b] |= 4 when that happens).  One workgroup per matrix; n <= 128.
-hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv,
+// read) as G + shift * tr(G)/n * I = R^H R, Rinv = R^{-1} (upper triangular,
+// complex128, batch x n x n) and, if Rf is not null, R itself.  A pivot below
+// clamp * tr(G)/n is raised to it (flags[b] |= 4 when that happens).  One
+// workgroup per matrix; n <= 64.
+hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
                            int *flags, hipStream_t s);
 // out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element
 // strides (bs, rs, cs) on both sides, element sizes ie / oe, conjugation if conj.

@@ -369,92 +369,124 @@ size_t global_qr_bytes(int m, int n, size_t *w, size_t *y, size_t *t, size_t *b)
 }
 
 // ---------------------------------------------------------------- Cholesky + inverse
-// One workgroup per matrix, n <= 64, matrix in LDS.  Right-looking upper
-// Cholesky G + sI = R^H R, then R^{-1} by back substitution, one column per thread.
-__global__ void __launch_bounds__(256) k_chol_inv(const double2 *G, int n, double shift, double clamp, double2 *Rinv,
-                                                 int *flags) {
-    __shared__ double2 R[64][65];
-    __shared__ double2 Ri[64][65];
-    __shared__ double scale;
+// One workgroup of CT threads per matrix, n <= 64.  Right-looking elimination on
+// the augmented pair [W | E] = [G + sI | I]: at pivot k every lower row i takes
+//   row_i -= conj(W[k][i]) / W[k][k] * row_k
+// on both halves, and row k is scaled by 1 / sqrt(W[k][k]).  With G + sI =
+// L D L^H this leaves W = D^{1/2} L^H = R (upper) and E = D^{-1/2} L^{-1} =
+// R^{-H} (lower), so R^{-1} = E^H comes out of the same sweep, with no
+// back substitution.  Thread (row i, lane q of CL per row) keeps its part of the
+// row in registers: W[i][j] for j = i + q + CL m >= i and E[i][j] for
+// j = q + CL m <= i (m < 64 / CL); the owners of row k + 1 publish it to LDS
+// (two buffers) for the next pivot: one barrier per pivot.  Sixteen lanes per
+// row (1024 threads, four waves per SIMD) hide the latency of the short
+// dependent chains.  Rf (optional) receives R.
+constexpr int CL = 16;          // lanes per row
+constexpr int CT = 64 * CL;     // threads per matrix
+constexpr int CM = 64 / CL;     // row elements per lane
+
+__device__ inline void csub_conj_mul(double2 &w, double ax, double ay, double2 c) {
+    // w -= (ax - i ay) * c, i.e. w -= conj(a) c / d with (ax, ay) = a / d
+    w.x = fma(-ax, c.x, w.x);
+    w.x = fma(-ay, c.y, w.x);
+    w.y = fma(-ax, c.y, w.y);
+    w.y = fma(ay, c.x, w.y);
+}
+
+__global__ void __launch_bounds__(CT) k_chol_inv(const double2 *G, int n, double shift, double clamp, double2 *Rinv,
+                                                double2 *Rf, int *flags) {
+    __shared__ double2 PW[2][64];
+    __shared__ double2 PE[2][64];
+    __shared__ double red[CT / 64];
     const int b = blockIdx.x, t = threadIdx.x;
     const double2 *Gb = G + (int64_t)b * n * n;
-    for (int e = t; e < n * n; e += 256) {
-        const int i = e / n, j = e % n;
-        const double2 g = j >= i ? Gb[i * n + j] : Gb[j * n + i];
-        R[i][j] = j >= i ? g : make_double2(g.x, -g.y);
+    const int ti = t / CL, tq = t % CL;
+    const bool row = ti < n;
+    double2 w[CM], e[CM];
+#pragma unroll
+    for (int m = 0; m < CM; ++m) {
+        const int j = ti + tq + CL * m;
+        w[m] = (row && j < n) ? Gb[ti * n + j] : make_double2(0.0, 0.0);
+        const int je = tq + CL * m;
+        e[m] = make_double2(row && je == ti ? 1.0 : 0.0, 0.0);
+    }
+    // tr(G) / n
+    {
+        double v = (row && tq == 0) ? w[0].x : 0.0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((t & 63) == 0) red[t >> 6] = v;
     }
     __syncthreads();
-    if (t == 0) {
-        double tr = 0.0;
-        for (int i = 0; i < n; ++i) tr += R[i][i].x;
-        scale = tr / n;
-    }
-    __syncthreads();
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < CT / 64; ++i) tr += red[i];
+    const double scale = tr / n;
     const double sh = shift * scale, cl = clamp * scale;
-    if (t < n) R[t][t].x += sh;
+    if (row && tq == 0) w[0].x += sh;
+    if (ti == 0) {
+#pragma unroll
+        for (int m = 0; m < CM; ++m) {
+            const int j = tq + CL * m;
+            if (j < n) { PW[0][j] = w[m]; PE[0][j] = e[m]; }
+        }
+    }
     __syncthreads();
+    double myrk = 1.0;  // 1 / sqrt of this row's pivot
     for (int k = 0; k < n; ++k) {
-        double d = R[k][k].x;
+        const int pb = k & 1;
+        double d = PW[pb][k].x;
         if (!(d >= cl)) {
             if (t == 0 && flags) flags[b] |= 4;
             d = cl > 0.0 ? cl : 1e-300;
         }
-        const double rkk = sqrt(d);
-        __syncthreads();
-        for (int j = k + t; j < n; j += 256) {
-            if (j == k) R[k][k] = make_double2(rkk, 0.0);
-            else { R[k][j].x /= rkk; R[k][j].y /= rkk; }
-        }
-        __syncthreads();
-        const int w = n - k - 1;
-        for (int e = t; e < w * w; e += 256) {
-            const int i = k + 1 + e / w, j = k + 1 + e % w;
-            if (j < i) continue;
-            const double2 a = R[k][i], c = R[k][j];  // conj(a) * c
-            R[i][j].x -= a.x * c.x + a.y * c.y;
-            R[i][j].y -= a.x * c.y - a.y * c.x;
-        }
-        __syncthreads();
-    }
-    // R^{-1} column j by back substitution, four lanes per column (the lanes of
-    // a column are adjacent in one wave): each sums every fourth term of
-    // sum_{k>i} R[i][k] Ri[k][j], a butterfly adds the four, every lane writes
-    // the (identical) result; the wave's LDS accesses are ordered, so later
-    // steps of the column read it.
-    {
-        const int j = t >> 2, q = t & 3;
-        if (j < n) {
-            if (q == 0) {
-                for (int i = j + 1; i < n; ++i) Ri[i][j] = make_double2(0.0, 0.0);
-                Ri[j][j] = make_double2(1.0 / R[j][j].x, 0.0);
+        if (ti == k) {
+            myrk = 1.0 / sqrt(d);
+            if (tq == 0) w[0] = make_double2(d, 0.0);  // a raised pivot stays consistent
+        } else if (row && ti > k) {
+            const double inv = 1.0 / d;
+            const double2 a = PW[pb][ti];
+            const double ax = a.x * inv, ay = a.y * inv;
+            double2 cw[CM], ce[CM];
+#pragma unroll
+            for (int m = 0; m < CM; ++m) {
+                const int j = ti + tq + CL * m;
+                cw[m] = PW[pb][j < 64 ? j : 63];  // unconditional loads, then select
+                ce[m] = PE[pb][tq + CL * m];
             }
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int i = n - 2; i >= 0; --i) {
-            double sr = 0.0, si = 0.0;
-            if (j < n && i < j) {
-                for (int k = i + 1 + q; k <= j; k += 4) {
-                    const double2 a = R[i][k], c = Ri[k][j];
-                    sr += a.x * c.x - a.y * c.y;
-                    si += a.x * c.y + a.y * c.x;
+#pragma unroll
+            for (int m = 0; m < CM; ++m) {
+                if (ti + tq + CL * m < n) csub_conj_mul(w[m], ax, ay, cw[m]);
+                if (tq + CL * m <= k) csub_conj_mul(e[m], ax, ay, ce[m]);
+            }
+            if (ti == k + 1) {
+#pragma unroll
+                for (int m = 0; m < CM; ++m) {
+                    const int j = tq + CL * m;
+                    if (ti + j < n) PW[pb ^ 1][ti + j] = w[m];  // column ti + tq + CL m
+                    if (j < n) PE[pb ^ 1][j] = e[m];
                 }
             }
-            sr += __shfl_xor(sr, 1);
-            si += __shfl_xor(si, 1);
-            sr += __shfl_xor(sr, 2);
-            si += __shfl_xor(si, 2);
-            if (j < n && i < j) {
-                const double inv = 1.0 / R[i][i].x;
-                Ri[i][j] = make_double2(-sr * inv, -si * inv);
-            }
-            __builtin_amdgcn_wave_barrier();
         }
+        __syncthreads();
     }
-    __syncthreads();
+    if (!row) return;
+    // R[i][j] = W[i][j] / sqrt(d_i) (j >= i), R^{-1}[j][i] = conj(E[i][j]) / sqrt(d_i) (j <= i)
     double2 *Ob = Rinv + (int64_t)b * n * n;
-    for (int e = t; e < n * n; e += 256) {
-        const int i = e / n, j = e % n;
-        Ob[e] = i <= j ? Ri[i][j] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < CM; ++m) {
+        const int j = tq + CL * m;
+        if (j < n) Ob[j * n + ti] = j <= ti ? make_double2(e[m].x * myrk, -e[m].y * myrk) : make_double2(0.0, 0.0);
+    }
+    if (Rf) {
+        double2 *Fb = Rf + (int64_t)b * n * n;
+#pragma unroll
+        for (int m = 0; m < CM; ++m) {
+            const int j = ti + tq + CL * m;
+            if (j < n) Fb[ti * n + j] = j == ti ? make_double2(w[m].x * myrk, 0.0)
+                                                : make_double2(w[m].x * myrk, w[m].y * myrk);
+            const int jl = tq + CL * m;
+            if (jl < ti) Fb[ti * n + jl] = make_double2(0.0, 0.0);
+        }
     }
 }
 
@@ -473,11 +505,11 @@ __global__ void __launch_bounds__(256) k_strided_copy(const char *in, int ie, in
 
 }  // namespace
 
-hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, int *flags,
-                           hipStream_t s) {
+hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
+                           int *flags, hipStream_t s) {
     if (n > 64 || n < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(256), 0, s, reinterpret_cast<const double2 *>(G), n, shift, clamp,
-                       reinterpret_cast<double2 *>(Rinv), flags);
+    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(CT), 0, s, reinterpret_cast<const double2 *>(G), n, shift, clamp,
+                       reinterpret_cast<double2 *>(Rinv), reinterpret_cast<double2 *>(Rf), flags);
     return hipGetLastError();
 }
 
