@@ -221,16 +221,17 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  *   complex128 for FP64, complex64 otherwise); dims are host arrays of
  *   strlen(letters) entries; conjA/conjB conjugate an operand; accumulate adds.
  *   Enqueued on the handle's stream.
- * tn_test_qr: reduced Householder QR (FP64 arithmetic) of `batch` row-major
- *   m x n DEVICE matrices of element size esz (16 or 8 bytes): Q is m x k,
- *   R is k x n, k = min(m, n).  With R == NULL, only an orthonormal basis Q of
- *   the column space is formed, by the fit's shifted CholeskyQR3 (m >= n,
- *   n <= 64; Householder otherwise).  Enqueued on the handle's stream.
+ * tn_test_qr: reduced QR (FP64 arithmetic) of `batch` row-major m x n DEVICE
+ *   matrices of element size esz (16 or 8 bytes): Q is m x k, R (optional,
+ *   NULL = not formed) is k x n, k = min(m, n).  method 0: Householder;
+ *   method 1: the fit's shifted CholeskyQR3 (m >= n, n <= 64; Householder
+ *   otherwise), R = R_3 R_2 R_1.  Enqueued on the handle's stream.
  */
 tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims,
                            int conjA, const char *ib, const void *B, const int32_t *bdims, int conjB,
                            const char *ic, void *C, const int32_t *cdims, int accumulate);
-tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R);
+tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R,
+                     int method);
 
 #ifdef __cplusplus
 }

@@ -85,7 +85,7 @@ def lib(path: Optional[str] = None):
     L.tn_test_contract.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int]
-    L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
               "tn_test_qr", "tn_amplitude", "tn_sample_stats"):
@@ -302,10 +302,15 @@ class Handle:
                                            _i32(B.shape), int(conjB), ic.encode(), ctypes.c_void_p(C.data_ptr()),
                                            _i32(C.shape), int(accumulate)))
 
-    def test_qr(self, A, Q, R):
+    def test_qr(self, A, Q, R, method: str | None = None):
+        """method "householder" or "cholesky" (default: Householder when R is
+        given, CholeskyQR3 otherwise)."""
         m, n = A.shape[-2], A.shape[-1]
         batch = int(np.prod(A.shape[:-2])) if A.dim() > 2 else 1
         esz = 16 if A.element_size() == 16 else 8
+        if method is None:
+            method = "householder" if R is not None else "cholesky"
         self._check(lib().tn_test_qr(self.h, m, n, batch, esz, ctypes.c_void_p(A.data_ptr()),
                                      ctypes.c_void_p(Q.data_ptr()),
-                                     ctypes.c_void_p(R.data_ptr()) if R is not None else None))
+                                     ctypes.c_void_p(R.data_ptr()) if R is not None else None,
+                                     0 if method == "householder" else 1))

@@ -409,7 +409,7 @@ tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A
     }
 }
 
-tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R) {
+tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R, int method) {
     try {
         if (!h) throw TnError(ST_INVALID, "null handle");
         h->err.clear();
@@ -420,7 +420,7 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
         a.A = A; a.a_esz = esz; a.a_bs = (int64_t)m * n; a.a_rs = n; a.a_cs = 1;
         a.Q = Q; a.q_esz = esz; a.q_bs = (int64_t)m * k; a.q_rs = k; a.q_cs = 1;
         a.R = R; a.r_esz = esz; a.r_bs = (int64_t)k * n; a.r_rs = n; a.r_cs = 1;
-        if (R) h->E->qr(a);
+        if (method == 0) h->E->qr(a);
         else h->E->orthonormalise(a);
         return TN_OK;
     } catch (const TnError &e) {

@@ -96,7 +96,8 @@ static int64_t prod(const std::vector<int> &d, int a, int b) {
 }
 
 // QR of T seen as batch x m x n (batch = first nb dims, n = last dim).
-void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R) {
+// well_conditioned: R may come from CholeskyQR3 (see Engine::orthonormalise).
+void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R, bool well_conditioned) {
     const int rk = (int)T.d.size();
     const int64_t batch = prod(T.d, 0, nb);
     const int64_t n = T.d[rk - 1];
@@ -117,12 +118,12 @@ void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R) {
     a.Q = Q.p; a.q_esz = Q.esz; a.q_bs = m * k; a.q_rs = k; a.q_cs = 1; a.q_conj = 0;
     a.R = R ? R->p : nullptr; a.r_esz = T.esz; a.r_bs = k * n; a.r_rs = n; a.r_cs = 1; a.r_conj = 0;
     // the fit needs only an orthonormal basis of the column space
-    if (R) E.qr(a);
+    if (R && !well_conditioned) E.qr(a);
     else E.orthonormalise(a);
 }
 
 // LQ of T seen as batch x m x n (m = dim nb, n = the rest): T = L Q, Q rows orthonormal.
-void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *Lf) {
+void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *Lf, bool well_conditioned) {
     const int rk = (int)T.d.size();
     const int64_t batch = prod(T.d, 0, nb);
     const int64_t m = T.d[nb];
@@ -143,7 +144,7 @@ void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *Lf) {
     a.A = T.p; a.a_esz = T.esz; a.a_bs = m * n; a.a_rs = 1; a.a_cs = n; a.a_conj = 1;
     a.Q = Q.p; a.q_esz = Q.esz; a.q_bs = k * n; a.q_rs = 1; a.q_cs = n; a.q_conj = 1;
     a.R = Lf ? Lf->p : nullptr; a.r_esz = T.esz; a.r_bs = m * k; a.r_rs = 1; a.r_cs = k; a.r_conj = 1;
-    if (Lf) E.qr(a);
+    if (Lf && !well_conditioned) E.qr(a);
     else E.orthonormalise(a);
 }
 
@@ -217,12 +218,13 @@ void canonicalise(Engine &E, std::vector<Ten> &Y, int nb, double *logscale, bool
     E.normalise(Y[0].p, Y[0].esz, per, batch, per, logscale, acc, nullptr);
 }
 
-// Right-canonicalise a (batched) MPS by LQ sweeps from the right.
+// Right-canonicalise a (batched) MPS by LQ sweeps from the right.  Used on the
+// fits' random initial guesses, whose factors are well conditioned.
 void right_canonicalise(Engine &E, std::vector<Ten> &Y, int nb) {
     const int L = (int)Y.size();
     for (int c = L - 1; c >= 1; --c) {
         Ten Q, Lm;
-        lq_right(E, Y[c], nb, Q, &Lm);
+        lq_right(E, Y[c], nb, Q, &Lm, true);
         E.drop(Y[c]);
         Y[c] = Q;
         Ten N = nb ? E.contract_new(op(Y[c - 1], "zabc"), op(Lm, "zcd"), "zabd")

@@ -145,6 +145,11 @@ std::string Engine::plan_report(int top) const {
         os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << " cfg=" << p->cfg
            << " split=" << p->base.ksplit << (p->tuned ? " tuned" : "") << '\n';
     }
+    os << "calls\tfactorisation\n";
+    std::vector<std::pair<int64_t, std::string>> q;
+    for (auto &kv : qr_shapes_) q.push_back({kv.second, kv.first});
+    std::sort(q.rbegin(), q.rend());
+    for (int i = 0; i < (int)q.size() && i < top; ++i) os << q[i].first << '\t' << q[i].second << '\n';
     return os.str();
 }
 
@@ -584,6 +589,11 @@ Ten Engine::contract_new(const Op &A, const Op &B, const std::string &ic) {
 void Engine::qr(const tnk::QrArgs &a) {
     const size_t ws = tnk::qr_workspace_bytes(a.m, a.n, a.batch);
     void *w = pool_.get(ws);
+    {
+        std::ostringstream k;
+        k << "householder m=" << a.m << " n=" << a.n << " batch=" << a.batch << (a.R ? " R" : "");
+        qr_shapes_[k.str()] += 1;
+    }
     EvPair *ev = timing ? &next_pair(1) : nullptr;
     if (ev) TN_HIP(hipEventRecord(ev->a, s));
     TN_HIP(tnk::launch_qr(a, w, s));
@@ -594,6 +604,11 @@ void Engine::qr(const tnk::QrArgs &a) {
 
 void Engine::orthonormalise(const tnk::QrArgs &a) {
     const int m = a.m, n = a.n, Z = a.batch;
+    {
+        std::ostringstream k;
+        k << "orthonormalise m=" << m << " n=" << n << " batch=" << Z;
+        qr_shapes_[k.str()] += 1;
+    }
     if (n > 64 || m < n) {
         qr(a);
         return;
@@ -603,6 +618,10 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
     in_qr_ = true;
     Ten X = make({Z, m, n}, 16), Y = make({Z, m, n}, 16);
     Ten G = make({Z, n, n}, 16), Ri = make({Z, n, n}, 16);
+    // with R requested: the pass factors R_1, R_2, R_3 (A = Q R_3 R_2 R_1)
+    Ten Rp[3];
+    if (a.R)
+        for (auto &r : Rp) r = make({Z, n, n}, 16);
     EvPair *ev = timing ? &next_pair(1) : nullptr;
     try {
         if (ev) TN_HIP(hipEventRecord(ev->a, s));
@@ -615,12 +634,19 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
             const double shift = pass == 0 ? 11.0 * ((double)m * n + (double)n * (n + 1)) * u * n : 0.0;
             const double clamp = pass == 0 ? 1e-300 : 1e-14;
             TN_HIP(tnk::launch_chol_inv(reinterpret_cast<const double *>(G.p), n, Z, shift, clamp,
-                                        reinterpret_cast<double *>(Ri.p), nullptr, nullptr, s));
+                                        reinterpret_cast<double *>(Ri.p),
+                                        a.R ? reinterpret_cast<double *>(Rp[pass].p) : nullptr, nullptr, s));
             contract(op(X, "bij"), op(Ri, "bjk"), op(Y, "bik"));
             std::swap(X, Y);
         }
         TN_HIP(tnk::launch_strided_copy(X.p, 16, (int64_t)m * n, n, 1, a.Q, a.q_esz, a.q_bs, a.q_rs, a.q_cs, m, n, Z,
                                         a.q_conj, s));
+        if (a.R) {
+            contract(op(Rp[2], "bij"), op(Rp[1], "bjk"), op(G, "bik"));
+            contract(op(G, "bij"), op(Rp[0], "bjk"), op(Ri, "bik"));
+            TN_HIP(tnk::launch_strided_copy(Ri.p, 16, (int64_t)n * n, n, 1, a.R, a.r_esz, a.r_bs, a.r_rs, a.r_cs, n, n,
+                                            Z, a.r_conj, s));
+        }
         if (ev) TN_HIP(hipEventRecord(ev->b, s));
     } catch (...) {
         in_qr_ = false;
@@ -633,6 +659,8 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
     drop(Y);
     drop(G);
     drop(Ri);
+    for (auto &r : Rp)
+        if (r.p) drop(r);
     ctr.qr_launches += 1;
 }
 

@@ -124,10 +124,12 @@ class Engine {
 
     // Reduced QR (FP64) of `batch` matrices; see tnk::QrArgs.
     void qr(const tnk::QrArgs &a);
-    // Q factor only (R is not formed), m >= n, n <= 64: shifted CholeskyQR3 in
+    // Orthonormal Q for m >= n, n <= 64 (else Householder): shifted CholeskyQR3 in
     // FP64 -- three passes of Gram matrix (MFMA), Cholesky and R^{-1} (one
     // workgroup), Q <- Q R^{-1} (MFMA); the first pass adds the shift
-    // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots.
+    // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots.  If
+    // a.R is set, R = R_3 R_2 R_1 (A = Q R to about u cond(A); meant for
+    // well-conditioned A such as random initial guesses).
     void orthonormalise(const tnk::QrArgs &a);
     // norm2 per batch item into dev[batch]; normalise in place; logscale +=.
     void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
@@ -163,6 +165,7 @@ class Engine {
     bool autotune_ = false;
     std::string tune_path_;
     std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)
+    std::map<std::string, int64_t> qr_shapes_;               // factorisation calls by shape
     void set_split(Plan *P, int cfg, int ksplit_hint);
     void tune(Plan *P, tnk::GettArgs g);
     EvPair &next_pair(int kind);

@@ -56,9 +56,9 @@ struct BoundarySet {
 void free_mps(Engine &E, DMps &m);
 Ten ones(Engine &E, const std::vector<int> &dims);
 // QR of T as batch x m x n (first nb dims batch, n = last dim); R optional.
-void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R);
+void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R, bool well_conditioned = false);
 // LQ of T as batch x m x n (m = dim nb, n = the rest); L optional.
-void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *L);
+void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *L, bool well_conditioned = false);
 // Canonical form by QR then LQ sweeps, centre (site 0) normalised into logscale.
 void canonicalise(Engine &E, std::vector<Ten> &Y, int nb, double *logscale, bool acc);
 void right_canonicalise(Engine &E, std::vector<Ten> &Y, int nb);

@@ -171,6 +171,25 @@ def test_orthonormalise(handle, m, n, batch, esz, cond):
         assert np.abs(proj - A[b]).max() < tol * 10 * np.abs(A[b]).max()
 
 
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (512, 8, 4), (700, 33, 2)])
+def test_cholesky_qr_with_r(handle, m, n, batch):
+    """CholeskyQR3 with R = R_3 R_2 R_1, as used to right-canonicalise the fits'
+    random initial guesses: Q orthonormal, R upper triangular, QR = A."""
+    import torch
+    rng = np.random.default_rng(m * 7 + n)
+    A = (2 * rng.random((batch, m, n)) - 1) + 1j * (2 * rng.random((batch, m, n)) - 1)
+    dA = torch.from_numpy(A).cuda()
+    dQ = torch.zeros((batch, m, n), dtype=torch.complex128, device="cuda")
+    dR = torch.full((batch, n, n), 7.0 + 0j, dtype=torch.complex128, device="cuda")
+    handle.test_qr(dA, dQ, dR, method="cholesky")
+    torch.cuda.synchronize()
+    Q, R = dQ.cpu().numpy(), dR.cpu().numpy()
+    for b in range(batch):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(n)).max() < 1e-12
+        assert np.abs(np.tril(R[b], -1)).max() == 0.0
+        assert np.abs(Q[b] @ R[b] - A[b]).max() < 1e-12 * np.abs(A[b]).max() * np.sqrt(m)
+
+
 def test_qr_rank_deficient(handle):
     import torch
     rng = np.random.default_rng(3)
