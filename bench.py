@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--prec", default="fp64", choices=list(PEAK_TFLOPS))
-    ap.add_argument("--samples", type=int, default=4, help="samples per step")
+    ap.add_argument("--samples", type=int, default=16, help="samples per step")
     ap.add_argument("--chi", type=int, default=None)
     ap.add_argument("--chi-x", type=int, default=None)
     ap.add_argument("--no-env", action="store_true", help="leave the density matrices out of the step")

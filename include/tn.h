@@ -219,8 +219,10 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  * tn_test_contract: C[ic] (+)= sum A[ia] * B[ib] (einsum letters, one char per
  *   index, row-major dense DEVICE tensors of the precision's storage type:
  *   complex128 for FP64, complex64 otherwise); dims are host arrays of
- *   strlen(letters) entries; conjA/conjB conjugate an operand; accumulate adds.
- *   Enqueued on the handle's stream.
+ *   strlen(letters) entries; conjA/conjB conjugate an operand; accumulate adds;
+ *   cfg >= 0 forces a tile configuration (0: 64x64, 1: 128x64, 2: 64x16,
+ *   3: 128x64 on 8 waves) and ksplit > 0 a number of K slices, -1 / 0 = the
+ *   planner's choice.  Enqueued on the handle's stream.
  * tn_test_qr: reduced QR (FP64 arithmetic) of `batch` row-major m x n DEVICE
  *   matrices of element size esz (16 or 8 bytes): Q is m x k, R (optional,
  *   NULL = not formed) is k x n, k = min(m, n).  method 0: Householder;
@@ -229,7 +231,8 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  */
 tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims,
                            int conjA, const char *ib, const void *B, const int32_t *bdims, int conjB,
-                           const char *ic, void *C, const int32_t *cdims, int accumulate);
+                           const char *ic, void *C, const int32_t *cdims, int accumulate,
+                           int cfg, int ksplit);
 tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R,
                      int method);
 

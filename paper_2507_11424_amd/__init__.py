@@ -84,7 +84,8 @@ def lib(path: Optional[str] = None):
     L.tn_plan_report.restype = ctypes.c_int
     L.tn_test_contract.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
-                                   ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int]
+                                   ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int]
     L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
@@ -296,11 +297,11 @@ class Handle:
 
     # ---------------------------------------------------------------- test hooks
     def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
-                      accumulate=False):
+                      accumulate=False, cfg: int = -1, ksplit: int = 0):
         self._check(lib().tn_test_contract(self.h, PREC[prec], ia.encode(), ctypes.c_void_p(A.data_ptr()),
                                            _i32(A.shape), int(conjA), ib.encode(), ctypes.c_void_p(B.data_ptr()),
                                            _i32(B.shape), int(conjB), ic.encode(), ctypes.c_void_p(C.data_ptr()),
-                                           _i32(C.shape), int(accumulate)))
+                                           _i32(C.shape), int(accumulate), int(cfg), int(ksplit)))
 
     def test_qr(self, A, Q, R, method: str | None = None):
         """method "householder" or "cholesky" (default: Householder when R is

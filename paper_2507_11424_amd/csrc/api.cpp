@@ -388,7 +388,7 @@ tn_status tn_set_autotune(tn_handle *h, int enable, const char *cache_path) {
 
 tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims, int conjA,
                            const char *ib, const void *B, const int32_t *bdims, int conjB, const char *ic,
-                           void *C, const int32_t *cdims, int accumulate) {
+                           void *C, const int32_t *cdims, int accumulate, int cfg, int ksplit) {
     try {
         if (!h) throw TnError(ST_INVALID, "null handle");
         h->err.clear();
@@ -402,7 +402,15 @@ tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A
             return t;
         };
         Ten a = mk(A, adims, ia), b = mk(B, bdims, ib), c = mk(C, cdims, ic);
-        h->E->contract(op(a, ia, conjA != 0), op(b, ib, conjB != 0), op(c, ic), accumulate != 0);
+        h->E->force_cfg = cfg;
+        h->E->force_ksplit = ksplit;
+        try {
+            h->E->contract(op(a, ia, conjA != 0), op(b, ib, conjB != 0), op(c, ic), accumulate != 0);
+        } catch (...) {
+            h->E->force_cfg = -1;
+            throw;
+        }
+        h->E->force_cfg = -1;
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);

@@ -416,7 +416,7 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
     std::string k;
     int cfg, ks;
     while (f >> k >> cfg >> ks)
-        if (cfg >= 0 && cfg < tnk::CFG_COUNT && cfg != tnk::CFG_128x128 && ks >= 1) tune_cache_[k] = {cfg, ks};
+        if (cfg >= 0 && cfg < tnk::CFG_COUNT && ks >= 1) tune_cache_[k] = {cfg, ks};
 }
 
 // Times every candidate (tile configuration x split-K choice) on the call's own
@@ -425,9 +425,9 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
 void Engine::tune(Plan *P, tnk::GettArgs g) {
     struct Cand { int cfg, ks; };
     std::vector<Cand> cands;
-    const int cfgs[3] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64};
+    const int cfgs[4] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64, tnk::CFG_128x64W};
     for (int c : cfgs) {
-        if (c == tnk::CFG_128x64 && P->kM < 128) continue;
+        if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W) && P->kM < 128) continue;
         if (c == tnk::CFG_64x16 && P->kN > 64) continue;
         int bm = 64, bn = 64;
         tnk::gett_tile(c, prec, &bm, &bn);
@@ -546,10 +546,19 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     g.conjA = (P->swapped ? B.conj : A.conj) ? 1 : 0;
     g.conjB = (P->swapped ? A.conj : B.conj) ? 1 : 0;
     g.accumulate = accumulate ? 1 : 0;
-    if (autotune_ && !P->tuned && !accumulate) {
+    int cfg = P->cfg;
+    if (force_cfg >= 0) {
+        Plan tmp = *P;  // shares the tables, owns nothing
+        set_split(&tmp, force_cfg, force_ksplit);
+        tmp.dev = nullptr;
+        g.ksplit = tmp.base.ksplit;
+        g.kchunk = tmp.base.kchunk;
+        cfg = force_cfg;
+    } else if (autotune_ && !P->tuned && !accumulate) {
         tune(P, g);
         g.ksplit = P->base.ksplit;
         g.kchunk = P->base.kchunk;
+        cfg = P->cfg;
     }
     void *part = nullptr;
     if (g.ksplit > 1) {
@@ -564,7 +573,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         ev->plan = P;
         TN_HIP(hipEventRecord(ev->a, s));
     }
-    TN_HIP(tnk::launch_gett(g, prec, P->cfg, s));
+    TN_HIP(tnk::launch_gett(g, prec, cfg, s));
     if (ev) TN_HIP(hipEventRecord(ev->b, s));
     if (part) pool_.put(part);
     if (in_qr_) ctr.qr_gemm_flops += P->flops;

@@ -109,6 +109,9 @@ class Engine {
     int device;
     int prec = tnk::P_FP64;
     int esz = 16;  // element size of compute tensors
+    // test hook: run contractions with this tile configuration / K-slice count
+    // instead of the plan's (-1: the plan's choice)
+    int force_cfg = -1, force_ksplit = 0;
     Counters ctr;
     bool timing = false;
 

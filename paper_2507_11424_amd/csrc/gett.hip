@@ -579,7 +579,8 @@ void gett_tile(int cfg, int prec, int *bm, int *bn) {
         case CFG_64x64: *bm = 64; *bn = 64; break;
         case CFG_128x64: *bm = 128; *bn = 64; break;
         case CFG_64x16: *bm = 64; *bn = 16; break;
-        default: *bm = 128; *bn = 128; break;
+        case CFG_128x64W: *bm = 128; *bn = 64; break;
+        default: *bm = 64; *bn = 64; break;
     }
     (void)prec;
 }
@@ -599,6 +600,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_mfma<double, 64, 64, 16, 2, 2, GAUSS3M>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_mfma<double, 128, 64, 16, 2, 2, false>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_mfma<double, 64, 16, 16, 4, 1, GAUSS3M>, a, 64, 16, 256, s);
+            case CFG_128x64W: return launch_k(gett_mfma<double, 128, 64, 16, 4, 2, GAUSS3M>, a, 128, 64, 512, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -607,6 +609,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_mfma<float, 64, 64, 16, 2, 2, GAUSS3M>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_mfma<float, 128, 64, 16, 2, 2, false>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_mfma<float, 64, 16, 16, 4, 1, GAUSS3M>, a, 64, 16, 256, s);
+            case CFG_128x64W: return launch_k(gett_mfma<float, 128, 64, 16, 4, 2, GAUSS3M>, a, 128, 64, 512, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -615,6 +618,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
             case CFG_64x64: return launch_k(gett_bf16<2, 64, 64, 2, 2>, a, 64, 64, 256, s);
             case CFG_128x64: return launch_k(gett_bf16<2, 128, 64, 2, 2>, a, 128, 64, 256, s);
             case CFG_64x16: return launch_k(gett_bf16<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
+            case CFG_128x64W: return launch_k(gett_bf16<2, 128, 64, 4, 2>, a, 128, 64, 512, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -622,6 +626,7 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
         case CFG_64x64: return launch_k(gett_bf16<3, 64, 64, 2, 2>, a, 64, 64, 256, s);
         case CFG_128x64: return launch_k(gett_bf16<3, 128, 64, 2, 2>, a, 128, 64, 256, s);
         case CFG_64x16: return launch_k(gett_bf16<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
+        case CFG_128x64W: return launch_k(gett_bf16<3, 128, 64, 4, 2>, a, 128, 64, 512, s);
         default: return hipErrorInvalidValue;
     }
 }

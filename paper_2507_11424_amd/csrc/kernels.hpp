@@ -47,7 +47,7 @@ enum GettCfg : int {
     CFG_64x64 = 0,    // 4 waves, 32x32 per wave
     CFG_128x64 = 1,   // 4 waves, 64x32 per wave
     CFG_64x16 = 2,    // skinny N
-    CFG_128x128 = 3,  // 4 waves, 64x64 per wave
+    CFG_128x64W = 3,  // 8 waves, 32x32 per wave
     CFG_COUNT = 4
 };
 

@@ -63,6 +63,34 @@ def test_contract_matches_einsum(handle, prec, case, conj):
     assert err < TOL[prec], err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("ksplit", [1, 3])
+def test_every_tile_configuration(handle, prec, case, cfg, ksplit):
+    """Each kernel variant (tile configuration x K slicing) against einsum, with
+    conjugated A; the autotuner may pick any of them."""
+    import torch
+    ia, ib, ic, dims = CASES[case]
+    rng = np.random.default_rng(500 + case)
+    A = _rand(rng, [dims[c] for c in ia])
+    B = _rand(rng, [dims[c] for c in ib])
+    td = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+    ref = np.einsum(f"{ia},{ib}->{ic}", A.conj(), B)
+    scale = np.einsum(f"{ia},{ib}->{ic}", np.abs(A), np.abs(B))
+    dA = torch.from_numpy(A).to("cuda", td)
+    dB = torch.from_numpy(B).to("cuda", td)
+    dC = torch.full([dims[c] for c in ic], 3.0 + 1j, dtype=td, device="cuda")
+    handle.test_contract(prec, ia, dA, ib, dB, ic, dC, conjA=True, cfg=cfg, ksplit=ksplit)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(got - ref) / np.maximum(scale, 1e-300))
+    assert err < TOL[prec], err
+
+
 @pytest.fixture(scope="module")
 def tuned_handle(tmp_path_factory):
     import paper_2507_11424_amd as tnb
