@@ -108,14 +108,18 @@ def brick_lattice(rows: int, cols: int, D: int) -> Lattice:
     return Lattice(f"brick{rows}x{cols}_D{D}", rows, cols, phys, dim_h, dim_v, _index_sites(phys))
 
 
-def rotated_square_lattice(D: int) -> Lattice:
-    """105 qubits: chip rows r = 0..9, x = 0,2,..,20 (r even) or 1,3,..,19 (r odd);
-    neighbours (r +- 1, x +- 1). Grid position (u, v) = ((r + x)/2, (x - r)/2 + 4)."""
-    occ = set()
-    for r in range(10):
-        xs = range(0, 21, 2) if r % 2 == 0 else range(1, 20, 2)
+def rotated_square_lattice(D: int, chip_rows: int = 10, xmax: int = 20) -> Lattice:
+    """Rotated square lattice: chip rows r = 0..chip_rows-1 with x = 0,2,..,xmax
+    (r even) or 1,3,..,xmax-1 (r odd); neighbours (r +- 1, x +- 1).  Grid
+    position (u, v) = ((r + x)/2, (x - r)/2 + offset), offset making v >= 0.
+    The defaults give the 105-qubit chip in a 15x15 embedding."""
+    sites = []
+    for r in range(chip_rows):
+        xs = range(0, xmax + 1, 2) if r % 2 == 0 else range(1, xmax, 2)
         for x in xs:
-            occ.add(((r + x) // 2, (x - r) // 2 + 4))
+            sites.append((r, x))
+    off = -min((x - r) // 2 for r, x in sites)
+    occ = set(((r + x) // 2, (x - r) // 2 + off) for r, x in sites)
     rows = 1 + max(u for u, _ in occ)
     cols = 1 + max(v for _, v in occ)
     phys = np.ones((rows, cols), dtype=np.int32)
@@ -128,8 +132,9 @@ def rotated_square_lattice(D: int) -> Lattice:
             dim_h[u, v] = D
         if (u + 1, v) in occ:
             dim_v[u, v] = D
-    lat = Lattice(f"rotsq105_D{D}", rows, cols, phys, dim_h, dim_v, _index_sites(phys))
-    assert lat.n_qubits == 105
+    lat = Lattice(f"rotsq{len(occ)}_D{D}", rows, cols, phys, dim_h, dim_v, _index_sites(phys))
+    if (chip_rows, xmax) == (10, 20):
+        assert lat.n_qubits == 105
     return lat
 
 

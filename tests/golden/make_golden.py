@@ -5,6 +5,7 @@ Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
 
     python tests/golden/make_golden.py c3_norm       # ~10 min on 8 cores
     python tests/golden/make_golden.py c3_samples    # a few samples at chi_x = 8
+    python tests/golden/make_golden.py c2_env        # 8x8 D=4 environments at chi = 32
 """
 import json
 import math
@@ -49,5 +50,19 @@ def c3_samples(n=2, chi_x=8):
     print({k: v for k, v in out.items() if k != "bits"})
 
 
+def c2_env(chi=32):
+    lat, T, cfg = make_config("c2")
+    t0 = time.time()
+    e = oracle.environments(T, chi)
+    enc = lambda a: [[float(v.real), float(v.imag)] for v in a.reshape(-1)]  # noqa: E731
+    out = dict(config="c2", chi=chi, sweeps=2, init_seed=0,
+               rho1=enc(e["rho1"]), rho1_shape=list(e["rho1"].shape),
+               zz_h=[float(v) for v in e["zz_h"].reshape(-1)], zz_h_shape=list(e["zz_h"].shape),
+               zz_v=[float(v) for v in e["zz_v"].reshape(-1)], zz_v_shape=list(e["zz_v"].shape),
+               oracle_seconds=time.time() - t0, command="python tests/golden/make_golden.py c2_env")
+    json.dump(out, open(os.path.join(HERE, "c2_env_chi32.json"), "w"))
+    print({k: v for k, v in out.items() if k in ("config", "chi", "oracle_seconds")})
+
+
 if __name__ == "__main__":
-    {"c3_norm": c3_norm, "c3_samples": c3_samples}[sys.argv[1]]()
+    {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env}[sys.argv[1]]()

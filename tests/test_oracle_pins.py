@@ -119,6 +119,8 @@ EXACT_CASES = [
     ("square3x4D3", lambda: square_lattice(3, 4, 3), "haar", 0.5, 22, 4096),
     ("brick4x4D2", lambda: brick_lattice(4, 4, 2), "haar", 0.4, 23, 64),
     ("c1", None, None, None, None, 16),
+    # rotated square patch: 10 qubits in a 4x4 embedding with dummy sites
+    ("rotsq10D2", lambda: rotated_square_lattice(2, 4, 4), "haar", 0.5, 24, 64),
 ]
 
 
@@ -154,7 +156,7 @@ def test_c1_bond_16_is_exact():
     assert any(i["mode"] == "fit" for i in info8[:-1])
 
 
-@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2"])
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2"])
 def test_environments_exact(name):
     lat, T, chi = _case(name)
     psi = statevector(T, lat.site_index)
@@ -166,22 +168,25 @@ def test_environments_exact(name):
     for r in range(lat.rows):
         for c in range(lat.cols):
             q = lat.site_index[r, c]
+            if q < 0:  # dummy grid position: no qubit, NaN by definition
+                assert np.all(np.isnan(env["rho1"][r, c]))
+                continue
             ps = np.moveaxis(psi, q, 0).reshape(2, -1)
             rho = ps @ ps.conj().T / Z
             assert np.abs(rho - env["rho1"][r, c]).max() < 1e-12
-            if c + 1 < lat.cols:
+            if c + 1 < lat.cols and lat.site_index[r, c + 1] >= 0:
                 q2 = lat.site_index[r, c + 1]
                 zz = np.sum(P * (1 - 2 * idx[q]) * (1 - 2 * idx[q2]))
                 assert abs(zz - env["zz_h"][r, c]) < 1e-12
                 p2 = [np.sum(P * (idx[q] == s) * (idx[q2] == t)) for s in (0, 1) for t in (0, 1)]
                 assert np.abs(np.array(p2) - env["p2_h"][r, c]).max() < 1e-12
-            if r + 1 < lat.rows:
+            if r + 1 < lat.rows and lat.site_index[r + 1, c] >= 0:
                 q2 = lat.site_index[r + 1, c]
                 zz = np.sum(P * (1 - 2 * idx[q]) * (1 - 2 * idx[q2]))
                 assert abs(zz - env["zz_v"][r, c]) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1"])
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1", "rotsq10D2"])
 @pytest.mark.parametrize("force_fit", [False, True])
 def test_sampler_exact_q_equals_p_over_Z(name, force_fit):
     lat, T, chi = _case(name)
