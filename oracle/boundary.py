@@ -66,15 +66,18 @@ def plan_bonds(phys: List[int], bond_in: List[int], chi: int):
     phys[c]    : product of the output physical dims at site c;
     bond_in[c] : bond of the exactly applied MPS-MPO product at cut c|c+1.
     Returns (exact_ok, targets): exact_ok is True when chi reaches the exact
-    bound at every cut; targets are min(chi, bound) made consistent so that a
-    reduced QR/LQ never shrinks them (t[c] <= t[c-1] phys[c], t[c] <= phys[c+1] t[c+1])."""
+    bound at every cut and the exact product itself is small (bond_in[c] <=
+    max(chi, 64) everywhere; rows with few sites can have a small bound but a
+    huge product bond, which is then fitted with the bound as target instead);
+    targets are min(chi, bound) made consistent so that a reduced QR/LQ never
+    shrinks them (t[c] <= t[c-1] phys[c], t[c] <= phys[c+1] t[c+1])."""
     L = len(phys)
     ex = []
     for c in range(L - 1):
         pl = math.prod(phys[: c + 1])
         pr = math.prod(phys[c + 1:])
         ex.append(min(pl, pr, bond_in[c]))
-    exact_ok = all(chi >= e for e in ex)
+    exact_ok = all(chi >= e for e in ex) and all(b <= max(chi, 64) for b in bond_in)
     t = [min(chi, e) for e in ex]
     for c in range(L - 1):
         left = t[c - 1] if c > 0 else 1

@@ -159,9 +159,14 @@ void plan_bonds(const std::vector<int> &phys, const std::vector<int64_t> &bond_i
         for (int i = c + 1; i < L; ++i) pr = std::min<int64_t>(pr * phys[i], (int64_t)1 << 40);
         ex[c] = std::min(std::min(pl, pr), bond_in[c]);
     }
+    // exact when chi reaches the bound at every cut and the exact product is
+    // small (its bond <= max(chi, 64)); a row with few sites can have a small
+    // bound but a huge product bond, which is fitted to the bound instead
     exact_ok = true;
     for (int64_t e : ex)
         if ((int64_t)chi < e) exact_ok = false;
+    for (int64_t b : bond_in)
+        if (b > std::max<int64_t>(chi, 64)) exact_ok = false;
     t.assign(std::max(L - 1, 0), 0);
     for (int c = 0; c + 1 < L; ++c) t[c] = (int)std::min<int64_t>(chi, ex[c]);
     for (int c = 0; c + 1 < L; ++c) {

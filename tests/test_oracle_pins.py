@@ -239,8 +239,12 @@ def test_brick_is_degree_three():
 def test_plan_bonds_consistency():
     ok, t = plan_bonds([4, 4, 4, 4], [16, 16, 16], 16)
     assert ok and t == [4, 16, 4]
-    ok, _ = plan_bonds([64, 1, 64, 1], [4096, 4096, 4096], 64)
-    assert ok  # every cut has one side with a physical space of at most 64
+    # every cut has a side with a physical space of at most 64, but the exact
+    # product's bond (4096) is far above max(chi, 64): fitted to the bound instead
+    ok, t = plan_bonds([64, 1, 64, 1], [4096, 4096, 4096], 64)
+    assert not ok and t == [64, 64, 1]
+    ok, t = plan_bonds([64, 1, 64, 1], [64, 64, 64], 64)
+    assert ok and t == [64, 64, 1]
     phys = [64, 64, 1, 64, 64, 1]
     ok, t = plan_bonds(phys, [4096, 512, 4096, 4096, 512], 64)
     assert not ok and t == [64, 64, 64, 64, 1]
