@@ -161,12 +161,14 @@ def main():
         t0 = time.perf_counter()
         lz, _ = h.boundary_contract(P, o)
         rec["contract"] = (time.perf_counter() - t0, h.counters())
+        print(f"  contract done ({rec['contract'][0]:.1f} s)", file=sys.stderr, flush=True)
         if not a.no_env:
             # one-site marginals of every qubit (pairs are left out at this size)
             t0 = time.perf_counter()
             h.environments(P, o, want_zz=False, want_p2=False)
             torch.cuda.synchronize()
             rec["environments"] = (time.perf_counter() - t0, h.counters())
+            print(f"  environments done ({rec['environments'][0]:.1f} s)", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         h.sample(P, o, a.samples, seed=17)
         torch.cuda.synchronize()

@@ -127,12 +127,14 @@ class Engine {
 
     // Reduced QR (FP64) of `batch` matrices; see tnk::QrArgs.
     void qr(const tnk::QrArgs &a);
-    // Orthonormal Q for m >= n, n <= 64 (else Householder): shifted CholeskyQR3 in
+    // Orthonormal Q for m >= n (else Householder): shifted CholeskyQR3 in
     // FP64 -- three passes of Gram matrix (MFMA), Cholesky and R^{-1} (one
     // workgroup), Q <- Q R^{-1} (MFMA); the first pass adds the shift
     // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots.  If
     // a.R is set, R = R_3 R_2 R_1 (A = Q R to about u cond(A); meant for
-    // well-conditioned A such as random initial guesses).
+    // well-conditioned A such as random initial guesses).  n > 64: blocks of 64
+    // columns, each orthogonalised against the previous ones by three passes of
+    // block Gram-Schmidt before its CholeskyQR3.
     void orthonormalise(const tnk::QrArgs &a);
     // norm2 per batch item into dev[batch]; normalise in place; logscale +=.
     void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
@@ -171,7 +173,8 @@ class Engine {
     std::map<std::string, int64_t> qr_shapes_;               // factorisation calls by shape
     void set_split(Plan *P, int cfg, int ksplit_hint);
     void tune(Plan *P, tnk::GettArgs g);
-    EvPair &next_pair(int kind);
+    static constexpr size_t NOEV = ~size_t(0);
+    size_t next_pair(int kind);
 };
 
 }  // namespace tnb

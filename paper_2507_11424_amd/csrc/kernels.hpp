@@ -76,6 +76,8 @@ hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
 // workgroup per matrix; n <= 64.
 hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
                            int *flags, hipStream_t s);
+// x *= (re + i im) over n complex128 elements.
+hipError_t launch_scale(void *x, int64_t n, double re, double im, hipStream_t s);
 // out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element
 // strides (bs, rs, cs) on both sides, element sizes ie / oe, conjugation if conj.
 hipError_t launch_strided_copy(const void *in, int ie, int64_t ibs, int64_t irs, int64_t ics, void *out, int oe,

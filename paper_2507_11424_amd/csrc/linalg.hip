@@ -369,7 +369,7 @@ size_t global_qr_bytes(int m, int n, size_t *w, size_t *y, size_t *t, size_t *b)
 }
 
 // ---------------------------------------------------------------- Cholesky + inverse
-// One workgroup of CT threads per matrix, n <= 64.  Right-looking elimination on
+// One workgroup of 1024 threads per matrix, n <= 64.  Right-looking elimination on
 // the augmented pair [W | E] = [G + sI | I]: at pivot k every lower row i takes
 //   row_i -= conj(W[k][i]) / W[k][k] * row_k
 // on both halves, and row k is scaled by 1 / sqrt(W[k][k]).  With G + sI =
@@ -377,14 +377,10 @@ size_t global_qr_bytes(int m, int n, size_t *w, size_t *y, size_t *t, size_t *b)
 // R^{-H} (lower), so R^{-1} = E^H comes out of the same sweep, with no
 // back substitution.  Thread (row i, lane q of CL per row) keeps its part of the
 // row in registers: W[i][j] for j = i + q + CL m >= i and E[i][j] for
-// j = q + CL m <= i (m < 64 / CL); the owners of row k + 1 publish it to LDS
+// j = q + CL m <= i (m < NMAX / CL); the owners of row k + 1 publish it to LDS
 // (two buffers) for the next pivot: one barrier per pivot.  Sixteen lanes per
 // row (1024 threads, four waves per SIMD) hide the latency of the short
 // dependent chains.  Rf (optional) receives R.
-constexpr int CL = 16;          // lanes per row
-constexpr int CT = 64 * CL;     // threads per matrix
-constexpr int CM = 64 / CL;     // row elements per lane
-
 __device__ inline void csub_conj_mul(double2 &w, double ax, double ay, double2 c) {
     // w -= (ax - i ay) * c, i.e. w -= conj(a) c / d with (ax, ay) = a / d
     w.x = fma(-ax, c.x, w.x);
@@ -393,10 +389,14 @@ __device__ inline void csub_conj_mul(double2 &w, double ax, double ay, double2 c
     w.y = fma(ay, c.x, w.y);
 }
 
-__global__ void __launch_bounds__(CT) k_chol_inv(const double2 *G, int n, double shift, double clamp, double2 *Rinv,
-                                                double2 *Rf, int *flags) {
-    __shared__ double2 PW[2][64];
-    __shared__ double2 PE[2][64];
+// NMAX rows of CL lanes each (64 x 16 = 1024 threads).
+template <int NMAX, int CL>
+__global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int n, double shift, double clamp,
+                                                       double2 *Rinv, double2 *Rf, int *flags) {
+    constexpr int CT = NMAX * CL;   // threads per matrix
+    constexpr int CM = NMAX / CL;   // row elements per lane
+    __shared__ double2 PW[2][NMAX];
+    __shared__ double2 PE[2][NMAX];
     __shared__ double red[CT / 64];
     const int b = blockIdx.x, t = threadIdx.x;
     const double2 *Gb = G + (int64_t)b * n * n;
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(CT) k_chol_inv(const double2 *G, int n, double
 #pragma unroll
             for (int m = 0; m < CM; ++m) {
                 const int j = ti + tq + CL * m;
-                cw[m] = PW[pb][j < 64 ? j : 63];  // unconditional loads, then select
+                cw[m] = PW[pb][j < NMAX ? j : NMAX - 1];  // unconditional loads, then select
                 ce[m] = PE[pb][tq + CL * m];
             }
 #pragma unroll
@@ -490,6 +490,14 @@ __global__ void __launch_bounds__(CT) k_chol_inv(const double2 *G, int n, double
     }
 }
 
+// x[i] *= (re + i im), complex128.
+__global__ void __launch_bounds__(256) k_scale(double2 *x, int64_t n, double re, double im) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double2 v = x[i];
+        x[i] = make_double2(v.x * re - v.y * im, v.x * im + v.y * re);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_strided_copy(const char *in, int ie, int64_t ibs, int64_t irs, int64_t ics,
                                                      char *out, int oe, int64_t obs, int64_t ors, int64_t ocs, int m,
                                                      int n, int batch, int conj) {
@@ -508,8 +516,17 @@ __global__ void __launch_bounds__(256) k_strided_copy(const char *in, int ie, in
 hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
                            int *flags, hipStream_t s) {
     if (n > 64 || n < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_inv, dim3(batch), dim3(CT), 0, s, reinterpret_cast<const double2 *>(G), n, shift, clamp,
-                       reinterpret_cast<double2 *>(Rinv), reinterpret_cast<double2 *>(Rf), flags);
+    const double2 *g = reinterpret_cast<const double2 *>(G);
+    double2 *ri = reinterpret_cast<double2 *>(Rinv), *rf = reinterpret_cast<double2 *>(Rf);
+    hipLaunchKernelGGL((k_chol_inv<64, 16>), dim3(batch), dim3(1024), 0, s, g, n, shift, clamp, ri, rf, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(void *x, int64_t n, double re, double im, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)g), dim3(256), 0, s, reinterpret_cast<double2 *>(x), n, re, im);
     return hipGetLastError();
 }
 

@@ -73,3 +73,89 @@ def test_c3_samples_match_oracle(state, prec, tol):
     assert np.array_equal(got_bits, ref_bits)
     assert np.max(np.abs(lq.cpu().numpy() - np.array(SAMP["log_q"]))) < tol
     assert np.max(np.abs(lp.cpu().numpy() - np.array(SAMP["log_p"]))) < tol
+
+
+C2ENV = json.load(open(os.path.join(HERE, "golden", "c2_env_chi32.json")))
+
+
+def _c2_ref():
+    rho = np.array([complex(a, b) for a, b in C2ENV["rho1"]]).reshape(C2ENV["rho1_shape"])
+    zzh = np.array(C2ENV["zz_h"]).reshape(C2ENV["zz_h_shape"])
+    zzv = np.array(C2ENV["zz_v"]).reshape(C2ENV["zz_v_shape"])
+    return rho, zzh, zzv
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_c2_environments_match_oracle(prec, tol):
+    """8x8 square lattice, D=4, chi=32: one-site density matrices and
+    nearest-neighbour <ZZ> (horizontal and vertical pairs) against the stored
+    FP64 oracle values; FP32 runs on the complex64-rounded tensors (the oracle
+    ran on complex128, so the tolerance covers that rounding too)."""
+    import paper_2507_11424_amd as tnb
+    lat, T, cfg = make_config("c2")
+    h = tnb.Handle(0)
+    try:
+        P = tnb.Peps.from_numpy(lat, T, dtype="c128" if prec == "fp64" else "c64")
+        got = h.environments(P, tnb.make_opts(chi=C2ENV["chi"], sweeps=C2ENV["sweeps"],
+                                              init_seed=C2ENV["init_seed"], prec=prec), want_p2=False)
+    finally:
+        h.close()
+    rho, zzh, zzv = _c2_ref()
+    e_rho = np.max(np.abs(got["rho1"].cpu().numpy() - rho))
+    e_h = np.max(np.abs(got["zz_h"].cpu().numpy() - zzh))
+    e_v = np.max(np.abs(got["zz_v"].cpu().numpy() - zzv))
+    print(f"{prec}: rho {e_rho:.2e}, zz_h {e_h:.2e}, zz_v {e_v:.2e}")
+    assert e_rho < tol and e_h < tol and e_v < tol
+
+
+def test_c2_sample_histograms_within_shot_noise():
+    """2048 samples at chi = chi_x = 32: every qubit's frequency of 0 against
+    the environments' P(0), within the total-variation bound
+    tau = 1/2 sqrt((k-1)/n) + sqrt(ln(1/delta) / (2n)), k = 2, delta = 1e-3 / 64."""
+    import math
+    import paper_2507_11424_amd as tnb
+    lat, T, cfg = make_config("c2")
+    n = 2048
+    h = tnb.Handle(0)
+    try:
+        P = tnb.Peps.from_numpy(lat, T)
+        bits, lq, _ = h.sample(P, tnb.make_opts(chi=32, chi_x=32), n, seed=2024)
+        bits = bits.cpu().numpy()
+    finally:
+        h.close()
+    rho, _, _ = _c2_ref()
+    tau = 0.5 * math.sqrt(1.0 / n) + math.sqrt(math.log(64 / 1e-3) / (2 * n))
+    worst = 0.0
+    for r in range(lat.rows):
+        for c in range(lat.cols):
+            q = lat.site_index[r, c]
+            p0 = rho[r, c, 0, 0].real
+            f0 = np.mean(bits[:, q] == 0)
+            worst = max(worst, abs(f0 - p0))
+    print(f"largest |freq - P(0)| = {worst:.4f}, bound {tau:.4f}")
+    assert worst < tau
+
+
+def test_c4_full_lattice_small_bond():
+    """The 105-qubit rotated-square chip in its 15x15 embedding (D=8, complex64
+    data widened to complex128) at chi = 8, chi_x = 4: the norm and two samples
+    against the FP64 oracle run in the test (a few seconds)."""
+    import torch
+    import oracle
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import sample_uniforms
+    lat, T, cfg = make_config("c4")
+    ref_lz, ref_arg = oracle.norm(T, 8)
+    u = sample_uniforms(41, 2, lat.n_qubits)
+    rb, rq, rp = oracle.sample(T, lat.site_index, 8, 4, 2, seed=3, uniforms=u)
+    h = tnb.Handle(0)
+    try:
+        P = tnb.Peps.from_numpy(lat, T)
+        lz, arg = h.boundary_contract(P, tnb.make_opts(chi=8))
+        bits, lq, lp = h.sample(P, tnb.make_opts(chi=8, chi_x=4), 2, seed=3, uniforms=torch.from_numpy(u))
+    finally:
+        h.close()
+    assert abs(lz - ref_lz) < 1e-10 and abs(arg - ref_arg) < 1e-9
+    assert np.array_equal(bits.cpu().numpy(), rb)
+    assert np.abs(lq.cpu().numpy() - rq).max() < 1e-9
+    assert np.abs(lp.cpu().numpy() - rp).max() < 1e-9

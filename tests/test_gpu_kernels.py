@@ -172,7 +172,8 @@ def test_qr(handle, m, n, batch, esz):
         assert np.abs(np.tril(R[b], -1)).max() == 0.0
 
 
-@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (700, 33, 2), (512, 8, 5)])
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (700, 33, 2), (512, 8, 5), (8192, 128, 1),
+                                       (300, 200, 2), (1024, 65, 1)])
 @pytest.mark.parametrize("esz", [16, 8])
 @pytest.mark.parametrize("cond", [1.0, 1e6, 1e12])
 def test_orthonormalise(handle, m, n, batch, esz, cond):
@@ -199,7 +200,8 @@ def test_orthonormalise(handle, m, n, batch, esz, cond):
         assert np.abs(proj - A[b]).max() < tol * 10 * np.abs(A[b]).max()
 
 
-@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (512, 8, 4), (700, 33, 2)])
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (512, 8, 4), (700, 33, 2), (8192, 128, 1),
+                                       (300, 200, 2)])
 def test_cholesky_qr_with_r(handle, m, n, batch):
     """CholeskyQR3 with R = R_3 R_2 R_1, as used to right-canonicalise the fits'
     random initial guesses: Q orthonormal, R upper triangular, QR = A."""
@@ -268,3 +270,28 @@ def test_contract_operand_over_2gib(handle, layout):
     del A, B
     torch.cuda.empty_cache()
     assert np.max(np.abs(got - ref) / scale) < 1e-12
+
+
+def test_timing_mode_with_nested_contractions():
+    """Event timing on a fresh handle while a blocked (n > 64) orthonormalisation
+    issues nested contractions: the event-pair store grows inside the outer
+    pair (this once invalidated the outer pair), and the counters collect."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    h = tnb.Handle(0)
+    try:
+        h.set_timing(True)
+        rng = np.random.default_rng(12)
+        for n in (128, 200):
+            A = torch.from_numpy(_rand(rng, (2, 1024, n))).cuda()
+            Q = torch.zeros_like(A)
+            R = torch.zeros((2, n, n), dtype=A.dtype, device="cuda")
+            h.test_qr(A, Q, R, method="cholesky")
+        c = h.counters()
+        torch.cuda.synchronize()
+        q = Q.cpu().numpy()
+        assert np.abs(q[0].conj().T @ q[0] - np.eye(200)).max() < 1e-11
+        assert c["gemm_launches"] > 0 and c["gemm_ms"] > 0 and c["qr_ms"] > 0
+    finally:
+        h.set_timing(False)
+        h.close()

@@ -7,7 +7,8 @@ import math
 import numpy as np
 import pytest
 
-from peps_inputs import square_lattice, brick_lattice, random_peps, make_config, sample_uniforms
+from peps_inputs import (square_lattice, brick_lattice, rotated_square_lattice, random_peps, make_config,
+                         sample_uniforms)
 import oracle
 
 pytestmark = pytest.mark.gpu
@@ -36,11 +37,14 @@ STATES = {
     "sq4x4D3": lambda: (lambda l: (l, random_peps(l, "haar", 0.6, 51)))(square_lattice(4, 4, 3)),
     "brick5x4D2": lambda: (lambda l: (l, random_peps(l, "haar", 0.5, 52)))(brick_lattice(5, 4, 2)),
     "sq3x5D2": lambda: (lambda l: (l, random_peps(l, "product0", 0.4, 53)))(square_lattice(3, 5, 2)),
+    # rotated-square patches: dummy grid positions and staggered rows, as in the 105-qubit chip
+    "rotsq10D2": lambda: (lambda l: (l, random_peps(l, "haar", 0.5, 54)))(rotated_square_lattice(2, 4, 4)),
+    "rotsq18D3": lambda: (lambda l: (l, random_peps(l, "haar", 0.4, 55)))(rotated_square_lattice(3, 4, 8)),
 }
 
 
 @pytest.mark.parametrize("name,chi", [("c1", 16), ("sq4x4D3", 4), ("sq4x4D3", 9), ("brick5x4D2", 3),
-                                      ("sq3x5D2", 2), ("sq4x4D3", 81)])
+                                      ("sq3x5D2", 2), ("sq4x4D3", 81), ("rotsq10D2", 64), ("rotsq18D3", 5)])
 @pytest.mark.parametrize("direction", [0, 1, 2, 3])
 @pytest.mark.parametrize("force_fit", [False, True])
 def test_norm_fp64(handle, name, chi, direction, force_fit):
@@ -75,7 +79,8 @@ def test_norm_c2_chi32(handle):
     assert abs(got[0] - ref[0]) < 1e-10, (got, ref)
 
 
-@pytest.mark.parametrize("name,chi", [("c1", 16), ("sq4x4D3", 4), ("brick5x4D2", 3)])
+@pytest.mark.parametrize("name,chi", [("c1", 16), ("sq4x4D3", 4), ("brick5x4D2", 3), ("rotsq10D2", 64),
+                                      ("rotsq18D3", 5)])
 def test_environments_fp64(handle, name, chi):
     lat, T = STATES[name]()
     ref = oracle.environments(T, chi)
@@ -90,7 +95,8 @@ def test_environments_fp64(handle, name, chi):
 
 @pytest.mark.parametrize("name,chi,chi_x,force", [("c1", 16, 16, False), ("c1", 16, 16, True),
                                                    ("sq4x4D3", 4, 3, False), ("brick5x4D2", 3, 2, False),
-                                                   ("sq3x5D2", 2, 2, True)])
+                                                   ("sq3x5D2", 2, 2, True), ("rotsq10D2", 64, 64, False),
+                                                   ("rotsq18D3", 5, 3, False)])
 @pytest.mark.parametrize("given_uniforms", [True, False])
 def test_sample_fp64(handle, name, chi, chi_x, force, given_uniforms):
     import torch
