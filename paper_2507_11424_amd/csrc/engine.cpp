@@ -181,6 +181,23 @@ static Op squeeze(const Op &o) {
     return r;
 }
 
+// Rows of o as a matrix against the other input x: the product of the letters
+// x does not carry (batch letters, shared by all three operands, are excluded).
+static int64_t op_rows(const Op &o, const Op &x) {
+    int64_t rows = 1;
+    for (size_t i = 0; i < o.idx.size(); ++i)
+        if (x.idx.find(o.idx[i]) == std::string::npos) rows *= o.dims[i];
+    return rows;
+}
+
+// Split-BF16 packs both operands into bf16 part planes once when each is
+// re-read by several output tiles (both matrix sides above 128); otherwise the
+// kernel splits the gathered elements while staging, which reads each operand
+// once instead of three times.
+static bool pack_pays(const Op &A, const Op &B) {
+    return op_rows(A, B) > 128 && op_rows(B, A) > 128;
+}
+
 Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     const Op A = squeeze(A0), B = squeeze(B0), C = squeeze(C0);
     std::ostringstream ks;
@@ -358,12 +375,14 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     g.b_bytes = (uint32_t)wb;
     (void)kml; (void)knl;
     P->kM = kM; P->kN = kN; P->K = K; P->Z = Z;
+    P->pack = (prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B);
     P->key = key;
     P->flops = 8.0 * (double)M * (double)N * (double)K * (double)Z;
     {
         std::ostringstream d;
         d << A.idx << ',' << B.idx << "->" << C.idx << " M=" << M << " N=" << N << " K=" << K << " batch=" << Z
-          << (swap ? " swapped" : "");
+          << (swap ? " swapped" : "")
+          << ((prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B) ? " packed" : "");
         P->desc = d.str();
     }
     auto tc = tune_cache_.find(P->key);
@@ -397,8 +416,9 @@ void Engine::set_split(Plan *P, int cfg, int ksplit_hint) {
         const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
         if (tiles < 512 && K >= 256) ks = std::min<int64_t>((1024 + tiles - 1) / tiles, K / 128);
     }
-    // a k table staged in LDS bounds the K slice of a block
-    if (!g.a_kaff || !g.b_kaff) ks = std::max<int64_t>(ks, (K + tnk::GETT_KTAB - 1) / tnk::GETT_KTAB);
+    // a k table staged in LDS bounds the K slice of a block (the packed
+    // split-BF16 kernel reads no tables)
+    if (!P->pack && (!g.a_kaff || !g.b_kaff)) ks = std::max<int64_t>(ks, (K + tnk::GETT_KTAB - 1) / tnk::GETT_KTAB);
     g.ksplit = 1;
     g.kchunk = (int)K;
     if (ks > 1) {
@@ -505,6 +525,21 @@ static int64_t op_window(const Op &o, const Op &x, const Op &y) {
     return (w + 1) * (int64_t)o.esz;
 }
 
+// Elements of the dense rows x kpad matrix a packed operand becomes (kpad = K
+// rounded up to 32; letters shared by all three operands index the batch).
+// x is the other input, y the output.
+static int64_t op_dense(const Op &o, const Op &x, const Op &y) {
+    int64_t rows = 1, k = 1;
+    for (size_t i = 0; i < o.idx.size(); ++i) {
+        const char c = o.idx[i];
+        const bool in_x = x.idx.find(c) != std::string::npos, in_y = y.idx.find(c) != std::string::npos;
+        if (in_x && in_y) continue;
+        if (in_x) k *= o.dims[i];
+        else rows *= o.dims[i];
+    }
+    return rows * ((k + 31) / 32 * 32);
+}
+
 // Restricts letter c of o (if present) to [i0, i0 + n).
 static Op slice(const Op &o, char c, int i0, int n) {
     Op r = o;
@@ -515,18 +550,53 @@ static Op slice(const Op &o, char c, int i0, int n) {
     return r;
 }
 
+// Split-BF16: packs A and B into bf16 part planes (see tnk::launch_pack_bf16)
+// and points g at them.  The buffers come from the pool; the caller returns them.
+void Engine::pack_bf16(tnk::GettArgs &g, void **pa, void **pb) {
+    const int np = prec == tnk::P_BF16X3 ? 2 : 3;
+    const int kpad = (std::max(g.K, 1) + 31) / 32 * 32;
+    const int64_t ba = (int64_t)np * 4 * g.M * kpad, bb = (int64_t)np * 4 * g.N * kpad;
+    if (ba > (int64_t)tnk::GETT_MAX_WINDOW || bb > (int64_t)tnk::GETT_MAX_WINDOW)
+        throw TnError(ST_UNSUPPORTED, "packed split-BF16 operand above 2 GiB per batch item");
+    *pa = pool_.get((size_t)ba * g.batch);
+    *pb = pool_.get((size_t)bb * g.batch);
+    TN_HIP(tnk::launch_pack_bf16(np, g.A, g.a_boff, g.a_moff, g.a_koff, g.a_kaff, g.a_ks, g.M, g.K, kpad, g.batch,
+                                 g.conjA, *pa, s));
+    TN_HIP(tnk::launch_pack_bf16(np, g.B, g.b_boff, g.b_noff, g.b_koff, g.b_kaff, g.b_ks, g.N, g.K, kpad, g.batch,
+                                 g.conjB, *pb, s));
+    g.A = *pa;
+    g.B = *pb;
+    g.kpad = kpad;
+    g.a_bytes = (uint32_t)ba;
+    g.b_bytes = (uint32_t)bb;
+    g.conjA = g.conjB = 0;
+    g.a_kaff = g.b_kaff = 1;  // no tables in the packed kernel
+}
+
 void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     if (A.esz != esz || B.esz != esz || C.esz != esz)
         throw TnError(ST_INVALID, "operand element size does not match the compute precision");
     // The kernel addresses A and B through buffer resources of < 2 GiB per
     // batch item; a larger operand is cut along its widest-stride letter into
     // slices that fit (a summed letter accumulates over its slices).
+    const bool bf16 = prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6;
     const int64_t lim = (int64_t)tnk::GETT_MAX_WINDOW;
-    const int64_t wa = op_window(A, B, C), wb = op_window(B, A, C);
+    const int64_t wina = op_window(A, B, C), winb = op_window(B, A, C);
+    int64_t wa = wina, wb = winb;
+    if (bf16 && pack_pays(A, B)) {
+        // packed split-BF16 reads packed operands: dense rows x K planes, 4 * parts bytes
+        // per complex element (the window of a strided or broadcast operand can
+        // be smaller than that)
+        const int64_t per = prec == tnk::P_BF16X3 ? 8 : 12;
+        wa = std::max(wa, op_dense(A, B, C) * per);
+        wb = std::max(wb, op_dense(B, A, C) * per);
+    }
     if (wa > lim || wb > lim) {
         const Op &X = wa > lim ? A : B;
         const Op &Y = wa > lim ? B : A;
         const int64_t w = wa > lim ? wa : wb;
+        const int64_t win = wa > lim ? wina : winb;
+        // widest-stride letter
         int best = -1;
         int64_t span = 0;
         for (size_t i = 0; i < X.idx.size(); ++i) {
@@ -539,9 +609,14 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         if (best < 0) throw TnError(ST_UNSUPPORTED, "contraction operand cannot be cut below 2 GiB");
         const char c = X.idx[best];
         const int dim = X.dims[best];
-        const int64_t step = X.str[best] * (int64_t)X.esz;
-        const int64_t rest = w - (int64_t)(dim - 1) * step;
-        const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, (lim - rest) / step + 1));
+        int chunk;
+        if (win >= w) {  // the strided window is the binding limit
+            const int64_t step = X.str[best] * (int64_t)X.esz;
+            const int64_t rest = w - (int64_t)(dim - 1) * step;
+            chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, (lim - rest) / step + 1));
+        } else {         // the packed size is: it shrinks in proportion to the letter
+            chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, dim * lim / w));
+        }
         const bool summed = C.idx.find(c) == std::string::npos;
         for (int i0 = 0; i0 < dim; i0 += chunk) {
             const int n = std::min(chunk, dim - i0);
@@ -567,7 +642,18 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         g.kchunk = tmp.base.kchunk;
         cfg = force_cfg;
     } else if (autotune_ && !P->tuned && !accumulate) {
-        tune(P, g);
+        void *ta = nullptr, *tb = nullptr;
+        tnk::GettArgs gt = g;
+        if (P->pack) pack_bf16(gt, &ta, &tb);
+        try {
+            tune(P, gt);
+        } catch (...) {
+            if (ta) pool_.put(ta);
+            if (tb) pool_.put(tb);
+            throw;
+        }
+        if (ta) pool_.put(ta);
+        if (tb) pool_.put(tb);
         g.ksplit = P->base.ksplit;
         g.kchunk = P->base.kchunk;
         cfg = P->cfg;
@@ -577,17 +663,21 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         part = pool_.get((size_t)g.ksplit * g.batch * (size_t)g.M * g.N * esz);
         g.part = part;
     }
-    // inside the QR the enclosing event pair already times the launch
     // contractions inside the orthonormalisation are timed too (their QR-level
-    // pair also covers them); their flops are booked separately
+    // pair also covers them); their flops are booked separately.  The pair
+    // covers the split-BF16 packing of the operands.
     const size_t ev = timing ? next_pair(0) : NOEV;
     if (ev != NOEV) {
         ev_[ev].plan = P;
         TN_HIP(hipEventRecord(ev_[ev].a, s));
     }
+    void *pka = nullptr, *pkb = nullptr;
+    if (P->pack) pack_bf16(g, &pka, &pkb);
     TN_HIP(tnk::launch_gett(g, prec, cfg, s));
     if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
     if (part) pool_.put(part);
+    if (pka) pool_.put(pka);
+    if (pkb) pool_.put(pkb);
     if (in_qr_) ctr.qr_gemm_flops += P->flops;
     ctr.gemm_flops += P->flops;
     ctr.gemm_launches += 1;

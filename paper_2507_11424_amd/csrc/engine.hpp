@@ -88,6 +88,7 @@ struct Plan {
     int64_t calls = 0;
     bool tuned = false;   // tile configuration chosen by measurement
     int64_t kM = 0, kN = 0, K = 0, Z = 0;
+    bool pack = false;    // split-BF16 on packed operand planes (else split while staging)
 };
 
 struct Counters {
@@ -172,6 +173,7 @@ class Engine {
     std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)
     std::map<std::string, int64_t> qr_shapes_;               // factorisation calls by shape
     void set_split(Plan *P, int cfg, int ksplit_hint);
+    void pack_bf16(tnk::GettArgs &g, void **pa, void **pb);
     void tune(Plan *P, tnk::GettArgs g);
     static constexpr size_t NOEV = ~size_t(0);
     size_t next_pair(int kind);

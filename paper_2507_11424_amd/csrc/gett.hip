@@ -362,9 +362,12 @@ __device__ inline void split_bf16(float x, unsigned short *out) {
     }
 }
 
+// Split-BF16 on unpacked operands: elements gathered through the tables and
+// split into bf16 parts while staging.  Used when one operand is read at most
+// twice (M or N <= 128), where packing would cost more traffic than it saves.
 template <int NP, int BM, int BN, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-gett_bf16(GettArgs p) {
+gett_bf16_direct(GettArgs p) {
     constexpr int BK = 32;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -542,6 +545,211 @@ gett_bf16(GettArgs p) {
     }
 }
 
+// Packs one operand for the split-BF16 kernel: element (row, k) of batch item b
+// (gathered through the plan's tables, conjugated if asked) is split into NP
+// bf16 parts, stored as planes out[b][part][re/im][row][kpad], K contiguous and
+// zero past K.  Done once per contraction, so the GEMM's inner loop reads ready
+// bf16 fragments with 16-byte loads instead of splitting every tile it stages.
+template <int NP>
+__global__ void __launch_bounds__(256) k_pack_bf16(const float2 *X, const int64_t *boff, const int32_t *roff,
+                                                   const int32_t *koff, int kaff, int ks, int rows, int K, int kpad,
+                                                   int conj, unsigned short *out) {
+    const int b = blockIdx.y;
+    const int kc = kpad / 8;
+    const int64_t plane = (int64_t)rows * kpad;
+    const float2 *Xb = X + boff[b];
+    unsigned short *Ob = out + (int64_t)b * NP * 2 * plane;
+    const float sg = conj ? -1.f : 1.f;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)rows * kc; e += (int64_t)gridDim.x * 256) {
+        const int row = (int)(e / kc), k8 = (int)(e - (int64_t)row * kc) * 8;
+        const float2 *xr = Xb + roff[row];
+        v8s pr[NP], pi[NP];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k8 + j;
+            float2 v = make_float2(0.f, 0.f);
+            if (k < K) v = xr[kaff ? (int64_t)k * ks : (int64_t)koff[k]];
+            unsigned short hr[NP], hi[NP];
+            split_bf16<NP>(v.x, hr);
+            split_bf16<NP>(sg * v.y, hi);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) { pr[q][j] = (short)hr[q]; pi[q][j] = (short)hi[q]; }
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            *reinterpret_cast<v8s *>(Ob + (int64_t)(2 * q) * plane + (int64_t)row * kpad + k8) = pr[q];
+            *reinterpret_cast<v8s *>(Ob + (int64_t)(2 * q + 1) * plane + (int64_t)row * kpad + k8) = pi[q];
+        }
+    }
+}
+
+// Split-BF16 GEMM on packed operands (see k_pack_bf16): p.A / p.B are the
+// packed planes (rows M / N, p.kpad columns), p.a_bytes / p.b_bytes one batch
+// item's planes.  Each stage copies 16-byte chunks (8 k values of one plane
+// row) through LDS; rows past M / N read as zero (buffer range check).
+template <int NP, int BM, int BN, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+gett_bf16(GettArgs p) {
+    constexpr int BK = 32;
+    constexpr int CH = BK / 8;  // 16-byte chunks per plane row and stage
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int CA = NP * 2 * BM * CH, CB = NP * 2 * BN * CH;  // chunks per stage
+    constexpr int LA = (CA + NT - 1) / NT, LB = (CB + NT - 1) / NT;
+    constexpr int KP = BK + 8;  // padded k extent (bf16 elements), keeps 16-byte alignment
+    // two LDS stages when they fit in the 160 KiB of a CU, else one
+    constexpr int S = (2 * 2 * NP * (BM + BN) * KP * 2 <= 160 * 1024) ? 2 : 1;
+    // planes: [stage][re/im][part][row][k]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[S][2][NP][BM][KP];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[S][2][NP][BN][KP];
+
+    const int tid = threadIdx.x;
+    const int tiles_n = (p.N + BN - 1) / BN;
+    const int tiles_m = (p.M + BM - 1) / BM;
+    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    const int m0 = (tile / tiles_n) * BM;
+    const int n0 = (tile % tiles_n) * BN;
+    const int kbeg = blockIdx.z * p.kchunk;
+    const int kend = min(p.K, kbeg + p.kchunk);
+    const int64_t planeA = (int64_t)p.M * p.kpad, planeB = (int64_t)p.N * p.kpad;
+
+    // chunk e = (plane q*2+c, row in a tile of tr rows, ch) -> byte offset in one
+    // batch item's planes, or OOB past the matrix
+    auto chunk_off = [&](int e, int tr, int rows, int r0, int64_t plane, int k0) {
+        const int ch = e % CH, row = (e / CH) % tr, pl = e / (CH * tr);
+        if (r0 + row >= rows) return OOB;
+        return (uint32_t)(((int64_t)pl * plane + (int64_t)(r0 + row) * p.kpad + k0 + ch * 8) * 2);
+    };
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+
+    for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        const __amdgpu_buffer_rsrc_t rA =
+            make_rsrc(reinterpret_cast<const unsigned short *>(p.A) + (int64_t)b * NP * 2 * planeA, p.a_bytes);
+        const __amdgpu_buffer_rsrc_t rB =
+            make_rsrc(reinterpret_cast<const unsigned short *>(p.B) + (int64_t)b * NP * 2 * planeB, p.b_bytes);
+        float2 *Cb = reinterpret_cast<float2 *>(p.C) + p.c_boff[b];
+        v4f accR[FM][FN], accI[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
+        v8s ra[LA], rb[LB];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int e = tid + NT * i;
+                const uint32_t o = e < CA ? chunk_off(e, BM, p.M, m0, planeA, k0) : OOB;
+                ra[i] = __builtin_bit_cast(v8s, __builtin_amdgcn_raw_buffer_load_b128(rA, (int)o, 0, 0));
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int e = tid + NT * i;
+                const uint32_t o = e < CB ? chunk_off(e, BN, p.N, n0, planeB, k0) : OOB;
+                rb[i] = __builtin_bit_cast(v8s, __builtin_amdgcn_raw_buffer_load_b128(rB, (int)o, 0, 0));
+            }
+        };
+        auto lstore = [&](int st) {
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int e = tid + NT * i;
+                if (e >= CA) continue;
+                const int ch = e % CH, row = (e / CH) % BM, pl = e / (CH * BM);
+                *reinterpret_cast<v8s *>(&sA[st][pl & 1][pl >> 1][row][ch * 8]) = ra[i];
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int e = tid + NT * i;
+                if (e >= CB) continue;
+                const int ch = e % CH, row = (e / CH) % BN, pl = e / (CH * BN);
+                *reinterpret_cast<v8s *>(&sB[st][pl & 1][pl >> 1][row][ch * 8]) = rb[i];
+            }
+        };
+        // the previous batch item's last step may still read stage 0
+        __syncthreads();
+        gload(kbeg);
+        lstore(0);
+        __syncthreads();
+        int st = 0;
+        for (int k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) gload(k0 + BK);
+            const int kc = (lane >> 4) * 8;
+            v8s a[2][NP][FM], bfr[2][NP][FN];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+                        a[c][q][i] = *reinterpret_cast<const v8s *>(&sA[st][c][q][wm * WTM + i * 16 + (lane & 15)][kc]);
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        bfr[c][q][j] = *reinterpret_cast<const v8s *>(&sB[st][c][q][wn * WTN + j * 16 + (lane & 15)][kc]);
+                }
+            // negated imaginary parts of A for the Re C term (sign bit flip is exact)
+            v8s an[NP][FM];
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                for (int i = 0; i < FM; ++i) an[q][i] = a[1][q][i] ^ (short)0x8000;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+#pragma unroll
+                    for (int qa = 0; qa < NP; ++qa)
+#pragma unroll
+                        for (int qb = 0; qb < NP; ++qb) {
+                            if (qa + qb >= NP) continue;  // keep products of total order < NP
+                            accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[0][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accR[i][j], 0, 0, 0);
+                            accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, an[qa][i]), __builtin_bit_cast(v8bf, bfr[1][qb][j]), accR[i][j], 0, 0, 0);
+                            accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[0][qa][i]), __builtin_bit_cast(v8bf, bfr[1][qb][j]), accI[i][j], 0, 0, 0);
+                            accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(v8bf, a[1][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accI[i][j], 0, 0, 0);
+                        }
+                }
+            if (more) {
+                if (S == 1) __syncthreads();  // single stage: every wave has read it
+                const int nx = (S == 2) ? (st ^ 1) : 0;
+                lstore(nx);
+                __syncthreads();
+                st = nx;
+            }
+        }
+        float2 *Pb = p.ksplit > 1
+                         ? reinterpret_cast<float2 *>(p.part) + ((int64_t)blockIdx.z * p.batch + b) * (int64_t)p.M * p.N
+                         : nullptr;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+            if (n >= p.N) continue;
+            const int64_t cn = Pb ? 0 : p.c_noff[n];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * WTM + i * 16 + (lane >> 4) * 4 + r;
+                    if (m >= p.M) continue;
+                    float2 v = make_float2(accR[i][j][r], accI[i][j][r]);
+                    if (Pb) {
+                        Pb[(int64_t)m * p.N + n] = v;
+                        continue;
+                    }
+                    float2 *dst = Cb + p.c_moff[m] + cn;
+                    if (p.accumulate) { const float2 o = *dst; v.x += o.x; v.y += o.y; }
+                    *dst = v;
+                }
+        }
+    }
+}
+
 template <typename K>
 hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStream_t s) {
     const int tiles = ((a.M + bm - 1) / bm) * ((a.N + bn - 1) / bn);
@@ -573,6 +781,26 @@ hipError_t launch_reduce(const GettArgs &a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_pack_bf16(int np, const void *X, const int64_t *boff, const int32_t *roff, const int32_t *koff,
+                            int kaff, int ks, int rows, int K, int kpad, int batch, int conj, void *out,
+                            hipStream_t s) {
+    if (rows <= 0 || batch <= 0) return hipSuccess;
+    const int64_t work = (int64_t)rows * (kpad / 8);
+    int64_t g = (work + 255) / 256;
+    if (g > 8192) g = 8192;
+    const int gy = batch < 65535 ? batch : 65535;
+    if (batch > gy) return hipErrorInvalidValue;
+    auto x = reinterpret_cast<const float2 *>(X);
+    auto o = reinterpret_cast<unsigned short *>(out);
+    if (np == 2)
+        hipLaunchKernelGGL(k_pack_bf16<2>, dim3((unsigned)g, gy), dim3(256), 0, s, x, boff, roff, koff, kaff, ks, rows,
+                           K, kpad, conj, o);
+    else
+        hipLaunchKernelGGL(k_pack_bf16<3>, dim3((unsigned)g, gy), dim3(256), 0, s, x, boff, roff, koff, kaff, ks, rows,
+                           K, kpad, conj, o);
+    return hipGetLastError();
+}
 
 void gett_tile(int cfg, int prec, int *bm, int *bn) {
     switch (cfg) {
@@ -615,18 +843,26 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
     }
     if (prec == P_BF16X3) {
         switch (cfg) {
-            case CFG_64x64: return launch_k(gett_bf16<2, 64, 64, 2, 2>, a, 64, 64, 256, s);
-            case CFG_128x64: return launch_k(gett_bf16<2, 128, 64, 2, 2>, a, 128, 64, 256, s);
-            case CFG_64x16: return launch_k(gett_bf16<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
-            case CFG_128x64W: return launch_k(gett_bf16<2, 128, 64, 4, 2>, a, 128, 64, 512, s);
+            case CFG_64x64: return a.kpad ? launch_k(gett_bf16<2, 64, 64, 2, 2>, a, 64, 64, 256, s)
+                                          : launch_k(gett_bf16_direct<2, 64, 64, 2, 2>, a, 64, 64, 256, s);
+            case CFG_128x64: return a.kpad ? launch_k(gett_bf16<2, 128, 64, 2, 2>, a, 128, 64, 256, s)
+                                           : launch_k(gett_bf16_direct<2, 128, 64, 2, 2>, a, 128, 64, 256, s);
+            case CFG_64x16: return a.kpad ? launch_k(gett_bf16<2, 64, 16, 4, 1>, a, 64, 16, 256, s)
+                                          : launch_k(gett_bf16_direct<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
+            case CFG_128x64W: return a.kpad ? launch_k(gett_bf16<2, 128, 64, 4, 2>, a, 128, 64, 512, s)
+                                            : launch_k(gett_bf16_direct<2, 128, 64, 4, 2>, a, 128, 64, 512, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (cfg) {
-        case CFG_64x64: return launch_k(gett_bf16<3, 64, 64, 2, 2>, a, 64, 64, 256, s);
-        case CFG_128x64: return launch_k(gett_bf16<3, 128, 64, 2, 2>, a, 128, 64, 256, s);
-        case CFG_64x16: return launch_k(gett_bf16<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
-        case CFG_128x64W: return launch_k(gett_bf16<3, 128, 64, 4, 2>, a, 128, 64, 512, s);
+        case CFG_64x64: return a.kpad ? launch_k(gett_bf16<3, 64, 64, 2, 2>, a, 64, 64, 256, s)
+                                      : launch_k(gett_bf16_direct<3, 64, 64, 2, 2>, a, 64, 64, 256, s);
+        case CFG_128x64: return a.kpad ? launch_k(gett_bf16<3, 128, 64, 2, 2>, a, 128, 64, 256, s)
+                                       : launch_k(gett_bf16_direct<3, 128, 64, 2, 2>, a, 128, 64, 256, s);
+        case CFG_64x16: return a.kpad ? launch_k(gett_bf16<3, 64, 16, 4, 1>, a, 64, 16, 256, s)
+                                      : launch_k(gett_bf16_direct<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
+        case CFG_128x64W: return a.kpad ? launch_k(gett_bf16<3, 128, 64, 4, 2>, a, 128, 64, 512, s)
+                                        : launch_k(gett_bf16_direct<3, 128, 64, 4, 2>, a, 128, 64, 512, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -37,6 +37,10 @@ struct GettArgs {
     // reachable through the tables); operands are read with buffer loads whose
     // range check returns zero for padding, so a window must stay below 2^31.
     uint32_t a_bytes, b_bytes;
+    // split-BF16 modes: A and B are packed bf16 planes (launch_pack_bf16) with
+    // kpad columns (K rounded up to 32); a_bytes / b_bytes are one batch item's
+    // planes
+    int kpad;
 };
 // Largest K slice a block handles when a k table is not affine (LDS table).
 constexpr int GETT_KTAB = 1024;
@@ -52,6 +56,12 @@ enum GettCfg : int {
 };
 
 hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s);
+// Split-BF16 operand packing: element (row, k) of batch item b at
+// X + boff[b] + roff[row] + (kaff ? k * ks : koff[k]) (complex64), conjugated if
+// conj, split into np bf16 parts -> out[b][part][re/im][row][kpad] (zero past K).
+hipError_t launch_pack_bf16(int np, const void *X, const int64_t *boff, const int32_t *roff, const int32_t *koff,
+                            int kaff, int ks, int rows, int K, int kpad, int batch, int conj, void *out,
+                            hipStream_t s);
 void gett_tile(int cfg, int prec, int *bm, int *bn);
 
 // ---------------------------------------------------------------- linear algebra

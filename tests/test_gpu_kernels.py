@@ -33,6 +33,10 @@ CASES = [
     ("ik", "kj", "ij", dict(i=2000, k=5, j=16)),          # skinny N
     ("ik", "kj", "ij", dict(i=70, k=4100, j=50)),         # split-K with a ragged last slice
     ("zki", "zkj", "zij", dict(z=3, k=1000, i=64, j=64)),  # batched split-K, K-contiguous A and B
+    # both matrix sides above 128: split-BF16 packs its operands
+    ("ik", "kj", "ij", dict(i=300, k=70, j=200)),
+    ("yghk", "gdeG", "yhkdeG", dict(y=20, g=7, h=3, k=3, d=4, e=4, G=11)),
+    ("iab", "baj", "ij", dict(i=150, a=40, b=37, j=140)),  # k table longer than one LDS slice
 ]
 
 
