@@ -16,6 +16,15 @@ sampling paragraphs of Methods:
 * q(x) is the product of the drawn conditionals; p(x) is taken from the last
   amplitude boundary contracted with the last projected row.
 
+Optional adaptive bond (the per-sample SVD cutoff of the batched workloads,
+not part of the paper's fixed-R_x sampler): after each fit, a left-to-right
+SVD sweep over the canonical m keeps at every cut the fewest singular values
+whose discarded weight sum_{j>=k} s_j^2 / sum_j s_j^2 is at most the cutoff
+(the error measure of the paper's Eq. error_per_gate), clamped to
+[chi_x_min, bond width] and to the numerical rank (s_j > 1e-12 s_0).  The
+dropped directions stay as zero padding, so tensor shapes (and the next fit's
+target bonds) do not depend on the cutoff.
+
 Readings (listed in the design notes): P(s) = max(Re rho_ss, 0) / sum; x = 0
 iff u < P(0); environments are divided by their Frobenius norm to stay in
 range (probabilities are ratios, so this changes nothing); a non-finite or
@@ -126,6 +135,56 @@ def fit_single(m, X, chi_x: int, sweeps: int, seed: int, row_id: int, sample: in
 
 
 # ---------------------------------------------------------------------------
+# adaptive bond: SVD truncation by discarded weight
+
+RANK_RTOL = 1e-12
+
+
+def keep_count(sv, cutoff: float, chi_min: int) -> int:
+    """Number of singular values kept from ``sv`` (any order): the smallest k
+    with sum of the squares beyond the k largest <= cutoff * total, at most the
+    numerical rank (s > RANK_RTOL * s_max), at least min(chi_min, rank)."""
+    s = np.sort(np.asarray(sv, dtype=np.float64))[::-1]
+    if s.size == 0 or s[0] <= 0.0:
+        return 0
+    rank = int(np.count_nonzero(s > RANK_RTOL * s[0]))
+    w = s * s
+    total = float(np.sum(w))
+    k = rank
+    tail = 0.0
+    # grow the discarded tail from the smallest kept value while it stays
+    # within the cutoff
+    for j in range(rank - 1, 0, -1):
+        if tail + w[j] > cutoff * total:
+            break
+        tail += w[j]
+        k = j
+    return max(k, min(chi_min, rank))
+
+
+def truncate_cutoff(m, cutoff: float, chi_min: int):
+    """Left-to-right SVD truncation of an MPS m[c][a, u, A] whose sites 1..L-1
+    are right-canonical (the gauge the fit and the exact product leave).  At
+    cut c the site matrix (a u) x A is factorised M = U S V^H; U's first k
+    columns replace site c and S V^H (first k rows) moves into site c+1; the
+    other columns and rows become zeros.  Returns (m', k per cut)."""
+    m = [x.copy() for x in m]
+    ks = []
+    for c in range(len(m) - 1):
+        a, u, A = m[c].shape
+        U, S, Vh = np.linalg.svd(m[c].reshape(a * u, A), full_matrices=False)
+        k = keep_count(S, cutoff, chi_min)
+        ks.append(k)
+        Up = np.zeros((a * u, A), dtype=np.complex128)
+        Up[:, :k] = U[:, :k]
+        SV = np.zeros((A, A), dtype=np.complex128)
+        SV[:k, :] = S[:k, None] * Vh[:k, :]
+        m[c] = Up.reshape(a, u, A)
+        m[c + 1] = np.tensordot(SV, m[c + 1], axes=(1, 0))
+    return m, ks
+
+
+# ---------------------------------------------------------------------------
 # sampler environments (ket boundary m, its conjugate, norm boundary below)
 
 def env_left(Lenv, mc, A, Bc, s: Optional[int]):
@@ -160,9 +219,13 @@ def _unit(x):
 
 
 def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: int,
-               sample: int, uniforms=None, forced_bits=None, force_fit: bool = False):
+               sample: int, uniforms=None, forced_bits=None, force_fit: bool = False,
+               svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None):
     """One sample. ``uniforms[q]`` is the uniform for qubit q; ``forced_bits``
     (optional) replaces the draw by a given bitstring (for enumerating q(x)).
+    ``svd_cutoff`` > 0 adds the SVD truncation after every fit; ``chi_used``
+    (optional, length rows) receives the largest kept bond of the amplitude
+    boundary that conditions each row (1 for the first row).
     Returns (bits, log_q, log_p_from_final_m)."""
     rows, cols = len(tensors), len(tensors[0])
     n_q = int(np.max(site_index)) + 1
@@ -171,6 +234,8 @@ def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: i
     m = [np.ones((1, 1, 1), dtype=np.complex128) for _ in range(cols)]
     mlog = 0.0
     logp = float("nan")
+    if chi_used is not None:
+        chi_used[0] = 1
     for r in range(rows):
         row = tensors[r]
         B = below[r]
@@ -208,6 +273,12 @@ def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: i
         if r < rows - 1:
             m, lg = fit_single(m, X, chi_x, sweeps, init_seed, r, sample, force_fit)
             mlog += lg
+            if svd_cutoff > 0.0:
+                m, ks = truncate_cutoff(m, svd_cutoff, chi_x_min)
+            else:
+                ks = [mc.shape[2] for mc in m[:-1]]
+            if chi_used is not None:
+                chi_used[r + 1] = max(ks) if ks else 1
         else:
             # the last row has no down legs (dimension 1): m . X_last is the amplitude
             v = np.ones((1, 1), dtype=np.complex128)
@@ -219,9 +290,12 @@ def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: i
 
 
 def sample(tensors, site_index, chi: int, chi_x: int, n: int, seed: int, first: int = 0,
-           sweeps: int = 2, init_seed: int = 0, uniforms=None, below=None, force_fit=False):
+           sweeps: int = 2, init_seed: int = 0, uniforms=None, below=None, force_fit=False,
+           svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None):
     """n samples (indices first..first+n-1). ``uniforms`` [n][N] overrides the
-    Philox draws. Returns (bits [n][N] uint8, log_q [n], log_p [n])."""
+    Philox draws; ``chi_used`` (optional int array [n][rows]) receives the
+    per-row bonds (see sample_one). Returns (bits [n][N] uint8, log_q [n],
+    log_p [n])."""
     if below is None:
         below, _, _ = boundary_set(tensors, chi, sweeps, init_seed, TAG_INIT_DOWN, force_fit)
     n_q = int(np.max(site_index)) + 1
@@ -232,6 +306,8 @@ def sample(tensors, site_index, chi: int, chi_x: int, n: int, seed: int, first: 
     lp = np.zeros(n)
     for i in range(n):
         b, q, p = sample_one(tensors, site_index, below, chi_x, sweeps, init_seed, first + i,
-                             uniforms[i], force_fit=force_fit)
+                             uniforms[i], force_fit=force_fit, svd_cutoff=svd_cutoff,
+                             chi_x_min=chi_x_min,
+                             chi_used=None if chi_used is None else chi_used[i])
         bits[i], lq[i], lp[i] = b, q, p
     return bits, lq, lp
