@@ -94,10 +94,17 @@ typedef struct {
     tn_prec prec;
     uint64_t init_seed;   /* Philox key of the random initial guesses                  */
     size_t workspace_cap; /* bytes of device workspace the library may hold; 0 = no cap */
+    double svd_cutoff;    /* sampler only: > 0 truncates every fitted amplitude boundary
+                             by an SVD sweep keeping, per cut, the fewest singular values
+                             whose discarded weight sum_{j>=k} s_j^2 / sum_j s_j^2 is
+                             <= svd_cutoff (the error measure of Eq. error_per_gate);
+                             0 = fixed bond chi_x (the paper's sampler)                 */
+    int32_t chi_x_min;    /* lower clamp of that truncation (never above the numerical
+                             rank, s_j > 1e-12 s_0); the upper clamp is chi_x <= 128    */
 } tn_opts;
 
 /* Fills opts with defaults: chi = chi_x = 16, sweeps = 2, direction 0, init 0,
- * FP64, seed 0, no cap. */
+ * FP64, seed 0, no cap, svd_cutoff 0, chi_x_min 1. */
 void tn_default_opts(tn_opts *opts);
 
 /* Creates a handle bound to HIP device `device` and stream `hip_stream`
@@ -136,14 +143,18 @@ tn_status tn_environments(tn_handle *h, const tn_peps *peps, const tn_opts *opts
  *   bits     : device [n][N] uint8, bit of qubit q at position site_index;
  *   log_q    : device [n] doubles, log of the product of drawn conditionals;
  *   log_p    : optional device [n] doubles, 2 log|<x|psi>| from the last
- *              amplitude boundary (accurate only when chi_x is large).
+ *              amplitude boundary (accurate only when chi_x is large);
+ *   chi_x_used : optional device [n][rows] int32, the largest bond kept by the
+ *              amplitude boundary that conditions each row (1 for the first
+ *              row; with svd_cutoff > 0 it varies per sample).
  * Computes (and caches) the norm boundary set if the cached one does not match
  * the state and options.  A sample is a function of (state, options, seed,
  * sample index) only, so split runs reproduce one run.
  * Synchronises the stream (marginal checks). */
 tn_status tn_sample(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
                     uint64_t seed, uint64_t first_sample, int64_t n,
-                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
+                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p,
+                    int32_t *chi_x_used);
 
 /* Independent check of given bitstrings (Methods, sampling paragraphs: p(x)
  * recomputed by a separate contraction of <x|psi> rather than taken from the
@@ -228,6 +239,12 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  *   NULL = not formed) is k x n, k = min(m, n).  method 0: Householder;
  *   method 1: the fit's shifted CholeskyQR3 (m >= n, n <= 64; Householder
  *   otherwise), R = R_3 R_2 R_1.  Enqueued on the handle's stream.
+ * tn_test_svd: the sampler's SVD truncation step on `batch` row-major n x n
+ *   complex128 DEVICE matrices R (n <= 128): U (n x n) and SV (n x n), element
+ *   size esz (16 or 8), with R ~ U SV; columns of U and rows of SV past the
+ *   kept count are zero; k (device int32 [batch]) receives the kept counts
+ *   (rule as for tn_opts.svd_cutoff with the lower clamp chi_min).  Enqueued
+ *   on the handle's stream.
  */
 tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A, const int32_t *adims,
                            int conjA, const char *ib, const void *B, const int32_t *bdims, int conjB,
@@ -235,6 +252,8 @@ tn_status tn_test_contract(tn_handle *h, int prec, const char *ia, const void *A
                            int cfg, int ksplit);
 tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void *A, void *Q, void *R,
                      int method);
+tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cutoff, int chi_min, void *U, void *SV,
+                      int esz, int32_t *k);
 
 #ifdef __cplusplus
 }

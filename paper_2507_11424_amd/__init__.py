@@ -30,8 +30,8 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 
 # every symbol declared in include/tn.h
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
-           "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing", "tn_set_autotune",
-           "tn_plan_report", "tn_test_contract", "tn_test_qr"]
+           "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
+           "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd"]
 
 
 class TnError(RuntimeError):
@@ -50,7 +50,8 @@ class c_peps(ctypes.Structure):
 class c_opts(ctypes.Structure):
     _fields_ = [("chi", ctypes.c_int32), ("chi_x", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("direction", ctypes.c_int32), ("init", ctypes.c_int32), ("prec", ctypes.c_int),
-                ("init_seed", ctypes.c_uint64), ("workspace_cap", ctypes.c_size_t)]
+                ("init_seed", ctypes.c_uint64), ("workspace_cap", ctypes.c_size_t),
+                ("svd_cutoff", ctypes.c_double), ("chi_x_min", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,7 +73,7 @@ def lib(path: Optional[str] = None):
     L.tn_destroy.argtypes = [vp]
     L.tn_boundary_contract.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), dp, dp]
     L.tn_environments.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), vp, vp, vp, vp, vp]
-    L.tn_sample.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, u64, i64, vp, vp, vp, vp]
+    L.tn_sample.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, u64, i64, vp, vp, vp, vp, vp]
     L.tn_amplitude.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, i64, vp, vp, vp]
     L.tn_sample_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
     L.tn_last_error.argtypes = [vp]
@@ -87,9 +88,11 @@ def lib(path: Optional[str] = None):
                                    ctypes.c_char_p, vp, ctypes.POINTER(i32), ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int]
     L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int]
+    L.tn_test_svd.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, ctypes.c_int, vp, vp,
+                              ctypes.c_int, vp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
-              "tn_test_qr", "tn_amplitude", "tn_sample_stats"):
+              "tn_test_qr", "tn_test_svd", "tn_amplitude", "tn_sample_stats"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -102,7 +105,7 @@ def _i32(a) -> ctypes.Array:
 
 
 def make_opts(chi=16, chi_x=None, sweeps=2, direction=0, force_fit=False, prec="fp64", init_seed=0,
-              workspace_cap=0) -> c_opts:
+              workspace_cap=0, svd_cutoff=0.0, chi_x_min=1) -> c_opts:
     o = c_opts()
     lib().tn_default_opts(ctypes.byref(o))
     o.chi = int(chi)
@@ -113,6 +116,8 @@ def make_opts(chi=16, chi_x=None, sweeps=2, direction=0, force_fit=False, prec="
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.init_seed = int(init_seed)
     o.workspace_cap = int(workspace_cap)
+    o.svd_cutoff = float(svd_cutoff)
+    o.chi_x_min = int(chi_x_min)
     return o
 
 
@@ -211,7 +216,9 @@ class Handle:
         return dict(rho1=rho1, zz_h=zzh, zz_v=zzv, p2_h=p2h, p2_v=p2v)
 
     def sample(self, peps: Peps, opts: c_opts, n: int, seed: int = 0, first: int = 0, uniforms=None,
-               want_logp: bool = True):
+               want_logp: bool = True, want_chi: bool = False):
+        """bits [n][N] uint8, log q [n], log p [n] (or None); with want_chi also
+        the per-row amplitude-boundary bonds [n][rows] int32 (see tn_sample)."""
         import torch
         dev = peps.tensors[0].device
         nq = peps.n_qubits
@@ -223,10 +230,12 @@ class Handle:
             if tuple(uniforms.shape) != (n, nq):
                 raise ValueError("uniforms must have shape [n][N]")
         up = ctypes.c_void_p(uniforms.data_ptr()) if uniforms is not None else None
+        cu = torch.empty((n, peps.c.rows), dtype=torch.int32, device=dev) if want_chi else None
         self._check(lib().tn_sample(self.h, ctypes.byref(peps.c), ctypes.byref(opts), seed, first, n, up,
                                     ctypes.c_void_p(bits.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
-                                    ctypes.c_void_p(lp.data_ptr()) if lp is not None else None))
-        return bits, lq, lp
+                                    ctypes.c_void_p(lp.data_ptr()) if lp is not None else None,
+                                    ctypes.c_void_p(cu.data_ptr()) if cu is not None else None))
+        return (bits, lq, lp, cu) if want_chi else (bits, lq, lp)
 
     def amplitude(self, peps: Peps, opts: c_opts, bits, first: int = 0, want_arg: bool = False):
         """log p(x) = 2 log|<x|psi>| (and arg <x|psi>) for bitstrings bits [n][N]
@@ -302,6 +311,22 @@ class Handle:
                                            _i32(A.shape), int(conjA), ib.encode(), ctypes.c_void_p(B.data_ptr()),
                                            _i32(B.shape), int(conjB), ic.encode(), ctypes.c_void_p(C.data_ptr()),
                                            _i32(C.shape), int(accumulate), int(cfg), int(ksplit)))
+
+    def test_svd(self, R, cutoff: float, chi_min: int = 1, esz: int = 16):
+        """The sampler's SVD truncation on complex128 matrices R [batch][n][n]:
+        returns (U, SV, k) with R ~ U @ SV (see tn_test_svd)."""
+        import torch
+        R = R.to(torch.complex128).contiguous()
+        n = R.shape[-1]
+        batch = R.shape[0]
+        dt = torch.complex128 if esz == 16 else torch.complex64
+        U = torch.empty((batch, n, n), dtype=dt, device=R.device)
+        SV = torch.empty((batch, n, n), dtype=dt, device=R.device)
+        k = torch.empty((batch,), dtype=torch.int32, device=R.device)
+        self._check(lib().tn_test_svd(self.h, n, batch, ctypes.c_void_p(R.data_ptr()), float(cutoff), int(chi_min),
+                                      ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(SV.data_ptr()), esz,
+                                      ctypes.c_void_p(k.data_ptr())))
+        return U, SV, k
 
     def test_qr(self, A, Q, R, method: str | None = None):
         """method "householder" or "cholesky" (default: Householder when R is

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtnbmps.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["gett.hip", "linalg.hip", "small.hip", "engine.cpp", "boundary.cpp", "sampler.cpp",
+SOURCES = ["gett.hip", "linalg.hip", "svd.hip", "small.hip", "engine.cpp", "boundary.cpp", "sampler.cpp",
            "environments.cpp", "api.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

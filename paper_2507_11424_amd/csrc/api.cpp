@@ -8,6 +8,7 @@
 
 #include "../../include/tn.h"
 #include "tn_core.hpp"
+#include "kernels.hpp"
 
 using namespace tnb;
 
@@ -51,6 +52,8 @@ void validate(const tn_peps *p, const tn_opts *o) {
     if (o->direction < 0 || o->direction > 3) throw TnError(ST_INVALID, "direction must be 0..3");
     if (o->init != 0 && o->init != 1) throw TnError(ST_INVALID, "init must be 0 or 1");
     if (o->prec < TN_PREC_FP64 || o->prec > TN_PREC_BF16X6) throw TnError(ST_INVALID, "bad precision");
+    if (!(o->svd_cutoff >= 0.0 && o->svd_cutoff <= 1.0)) throw TnError(ST_INVALID, "svd_cutoff must be in [0, 1]");
+    if (o->chi_x_min < 1) throw TnError(ST_INVALID, "chi_x_min must be >= 1");
     const int n = p->rows * p->cols;
     int nq = 0;
     std::vector<int> seen(n, 0);
@@ -158,6 +161,8 @@ void tn_default_opts(tn_opts *o) {
     o->prec = TN_PREC_FP64;
     o->init_seed = 0;
     o->workspace_cap = 0;
+    o->svd_cutoff = 0.0;
+    o->chi_x_min = 1;
 }
 
 tn_status tn_create(tn_handle **out, int device, void *stream) {
@@ -248,7 +253,7 @@ tn_status tn_environments(tn_handle *h, const tn_peps *p, const tn_opts *o, doub
 }
 
 tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t seed, uint64_t first, int64_t n,
-                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p) {
+                    const double *uniforms, uint8_t *bits, double *log_q, double *log_p, int32_t *chi_x_used) {
     try {
         begin(h, o);
         validate(p, o);
@@ -262,7 +267,11 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
         so.force_fit = o->init == 1;
         so.init_seed = o->init_seed;
         so.seed = seed;
-        sample(*h->E, h->cache_peps, S, so, first, n, uniforms, bits, log_q, log_p);
+        so.svd_cutoff = o->svd_cutoff;
+        so.chi_x_min = o->chi_x_min;
+        if (so.svd_cutoff > 0 && o->chi_x > tnk::SVD_NMAX)
+            throw TnError(ST_UNSUPPORTED, "svd_cutoff needs chi_x <= " + std::to_string(tnk::SVD_NMAX));
+        sample(*h->E, h->cache_peps, S, so, first, n, uniforms, bits, log_q, log_p, chi_x_used);
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);
@@ -430,6 +439,27 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
         a.R = R; a.r_esz = esz; a.r_bs = (int64_t)k * n; a.r_rs = n; a.r_cs = 1;
         if (method == 0) h->E->qr(a);
         else h->E->orthonormalise(a);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    }
+}
+
+tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cutoff, int chi_min, void *U, void *SV,
+                      int esz, int32_t *k) {
+    try {
+        if (!h) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        if (n < 1 || n > tnk::SVD_NMAX || batch < 0 || (esz != 8 && esz != 16))
+            throw TnError(ST_INVALID, "tn_test_svd: bad n, batch or esz");
+        if (!R || !U || !SV || !k) throw TnError(ST_INVALID, "tn_test_svd: null pointer");
+        const size_t wsb = tnk::svd_trunc_workspace_bytes(n, batch);
+        void *ws = wsb ? h->E->raw(wsb) : nullptr;
+        const hipError_t e = tnk::launch_svd_trunc(static_cast<const double *>(R), n, batch, cutoff, chi_min, U, SV,
+                                                   esz, k, ws, h->E->s);
+        if (ws) h->E->unraw(ws);
+        TN_HIP(e);
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);

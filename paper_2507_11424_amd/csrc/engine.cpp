@@ -732,7 +732,7 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
         k << "orthonormalise m=" << m << " n=" << n << " batch=" << Z;
         qr_shapes_[k.str()] += 1;
     }
-    if (m < n) {
+    if (m < n || householder_only) {
         qr(a);
         return;
     }

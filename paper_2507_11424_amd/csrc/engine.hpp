@@ -115,6 +115,10 @@ class Engine {
     int force_cfg = -1, force_ksplit = 0;
     Counters ctr;
     bool timing = false;
+    // orthonormalise() by Householder QR instead of CholeskyQR: set while the
+    // sampler truncates its amplitude boundaries, whose zero-padded bonds make
+    // the fit's matrices rank-deficient (CholeskyQR needs full column rank)
+    bool householder_only = false;
 
     void set_prec(int p) { prec = p; esz = (p == tnk::P_FP64) ? 16 : 8; }
 

@@ -86,6 +86,17 @@ hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
 // workgroup per matrix; n <= 64.
 hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
                            int *flags, hipStream_t s);
+// Batched SVD truncation (one-sided Jacobi, FP64): R [batch][n][n] complex128
+// (row-major) = U diag(sigma) V^H with sigma descending; keeps the fewest k
+// values whose discarded weight sum_{j>=k} sigma_j^2 is at most cutoff times
+// the total, capped by the numerical rank (sigma > 1e-12 sigma_max), at least
+// min(chi_min, rank).  Writes U[b](i, c) = u_c(i) and SV[b](c, l) = sigma_c
+// conj(v_c(l)) for c < k, zero for c >= k (element size esz, 8 or 16), and
+// kout[b] = k.  n <= SVD_NMAX; n > 64 needs svd_trunc_workspace_bytes.
+constexpr int SVD_NMAX = 128;
+size_t svd_trunc_workspace_bytes(int n, int batch);
+hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, int chi_min, void *U, void *SV, int esz,
+                            int *kout, void *workspace, hipStream_t s);
 // x *= (re + i im) over n complex128 elements.
 hipError_t launch_scale(void *x, int64_t n, double re, double im, hipStream_t s);
 // out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element
@@ -157,6 +168,10 @@ hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row
 // z_is[n_qubits] (optional) = importance-weighted <Z_q> from bits [n][n_qubits].
 hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t n, double log_Z,
                                const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s);
+// out[z * stride] = max_c k[c * batch + z] over c < cuts, or `constant` when
+// k is null or cuts == 0.
+hipError_t launch_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride,
+                           hipStream_t s);
 hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
                        hipStream_t s);
 

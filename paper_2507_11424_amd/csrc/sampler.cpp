@@ -11,7 +11,12 @@
 //    closed against the right environment to give P~(s), the bit is drawn, and
 //    the environment projected on the drawn bit is kept;
 //  * the product of m with the projected row x_b . psi_b is fitted to a new m of
-//    bond <= chi_x by the one-site fit (single layer).
+//    bond <= chi_x by the one-site fit (single layer);
+//  * optionally (svd_cutoff > 0) the fitted m is truncated per sample by a
+//    left-to-right SVD sweep that keeps the fewest singular values whose
+//    discarded weight is within the cutoff (clamped to [chi_x_min, width]);
+//    the dropped directions stay as zeros, so every sample of a wave keeps the
+//    same tensor shapes while its effective bond varies.
 // q(x) accumulates the drawn conditionals; p(x) is the last amplitude boundary
 // contracted with the last projected row.  Probabilities are FP64; P(s) =
 // max(Re P~(s), 0) / sum, x = 0 iff u < P(0).
@@ -216,6 +221,48 @@ std::vector<Ten> fit_single(Engine &E, const std::vector<Ten> &m, const std::vec
     return Y;
 }
 
+// Left-to-right SVD truncation of the fitted amplitude boundary m (sites 1..L-1
+// right-canonical, the gauge the fit and the exact product leave).  At cut c:
+// Householder QR of site c as (a u) x A (FP64, rank-deficient input allowed),
+// Jacobi SVD of R with the keep rule, site c <- Q U_k and site c+1 <- S_k V_k^H
+// site c+1, zero past k.  kbuf [cuts][Z] receives the kept counts.
+void truncate_cutoff(Engine &E, std::vector<Ten> &m, const SampleOpts &o, int *kbuf) {
+    const int L = (int)m.size();
+    const int Z = m[0].d[0];
+    for (int c = 0; c + 1 < L; ++c) {
+        const int a = m[c].d[1], u = m[c].d[2], A = m[c].d[3];
+        const int64_t rows = (int64_t)a * u;
+        if (A > tnk::SVD_NMAX)
+            throw TnError(ST_UNSUPPORTED, "SVD truncation supports bonds up to " + std::to_string(tnk::SVD_NMAX));
+        if (rows < A) throw TnError(ST_SHAPE, "amplitude boundary site narrower than its right bond");
+        Ten Q = E.make({Z, a, u, A});
+        Ten R = E.make({Z, A, A}, 16);
+        tnk::QrArgs q{};
+        q.m = (int)rows; q.n = A; q.batch = Z;
+        q.A = m[c].p; q.a_esz = m[c].esz; q.a_bs = rows * A; q.a_rs = A; q.a_cs = 1; q.a_conj = 0;
+        q.Q = Q.p; q.q_esz = Q.esz; q.q_bs = rows * A; q.q_rs = A; q.q_cs = 1; q.q_conj = 0;
+        q.R = R.p; q.r_esz = 16; q.r_bs = (int64_t)A * A; q.r_rs = A; q.r_cs = 1; q.r_conj = 0;
+        E.qr(q);
+        Ten U = E.make({Z, A, A}), SV = E.make({Z, A, A});
+        const size_t wsb = tnk::svd_trunc_workspace_bytes(A, Z);
+        void *ws = wsb ? E.raw(wsb) : nullptr;
+        const hipError_t err = tnk::launch_svd_trunc(static_cast<const double *>(R.p), A, Z, o.svd_cutoff, o.chi_x_min,
+                                                     U.p, SV.p, U.esz, kbuf + (size_t)c * Z, ws, E.s);
+        if (ws) E.unraw(ws);
+        TN_HIP(err);
+        E.drop(R);
+        Ten mc = E.contract_new(op(Q, "zauk"), op(U, "zkA"), "zauA");
+        E.drop(Q);
+        E.drop(U);
+        Ten mn = E.contract_new(op(SV, "zAk"), op(m[c + 1], "zkvB"), "zAvB");
+        E.drop(SV);
+        E.drop(m[c]);
+        E.drop(m[c + 1]);
+        m[c] = mc;
+        m[c + 1] = mn;
+    }
+}
+
 // <x|psi> from the last amplitude boundary and the last projected row (whose
 // down legs have dimension 1): log_p[z] = 2 (mlog[z] + log|v_z|), arg[z] =
 // arg v_z (optional); amp is [Z] complex128 scratch.
@@ -263,7 +310,7 @@ double bytes_per_sample(const LView &V, const BoundarySet &B, int chi_x, int esz
 }  // namespace
 
 void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts &o, uint64_t first, int64_t n,
-            const double *uniforms, uint8_t *bits, double *log_q, double *log_p) {
+            const double *uniforms, uint8_t *bits, double *log_q, double *log_p, int *chi_used) {
     const LView V = make_view(P, 0);
     const int rows = V.rows, cols = V.cols;
     int Zw = o.wave;
@@ -282,8 +329,16 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     int *flags = reinterpret_cast<int *>(E.raw((size_t)Zw * 4));
     int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
     double *amp = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    int *kbuf = o.svd_cutoff > 0 ? reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * std::max(cols - 1, 1))) : nullptr;
     std::vector<uint64_t> hidx(Zw);
     std::vector<int> hflags(Zw);
+    // truncated (zero-padded) boundaries make the fit's QR inputs rank-deficient
+    struct HouseholderScope {
+        Engine &E;
+        bool saved;
+        HouseholderScope(Engine &e, bool on) : E(e), saved(e.householder_only) { E.householder_only = saved || on; }
+        ~HouseholderScope() { E.householder_only = saved; }
+    } hh(E, o.svd_cutoff > 0);
     try {
         for (int64_t w0 = 0; w0 < n; w0 += Zw) {
             const int Z = (int)std::min<int64_t>(Zw, n - w0);
@@ -294,6 +349,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
             TN_HIP(hipMemsetAsync(log_q + w0, 0, (size_t)Z * 8, E.s));
             std::vector<Ten> m(cols);
             for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
+            if (chi_used) TN_HIP(tnk::launch_chi_used(nullptr, 0, Z, 1, chi_used + w0 * rows, rows, E.s));
             for (int r = 0; r < rows; ++r) {
                 const DMps &Bb = B.below[r];
                 // sites that take the transfer-matrix route, and their matrices
@@ -382,6 +438,13 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
                     for (auto &x : m) E.drop(x);
                     m = mn;
+                    if (o.svd_cutoff > 0) truncate_cutoff(E, m, o, kbuf);
+                    if (chi_used) {
+                        int width = 1;
+                        for (int c = 0; c + 1 < cols; ++c) width = std::max(width, m[c].d[3]);
+                        TN_HIP(tnk::launch_chi_used(o.svd_cutoff > 0 ? kbuf : nullptr, cols - 1, Z, width,
+                                                    chi_used + w0 * rows + r + 1, rows, E.s));
+                    }
                 } else if (log_p) {
                     last_row_amplitude(E, m, X, mlog, amp, log_p + w0, nullptr);
                 }
@@ -398,9 +461,11 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
         }
     } catch (...) {
         E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+        if (kbuf) E.unraw(kbuf);
         throw;
     }
     E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+    if (kbuf) E.unraw(kbuf);
 }
 
 void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first, int64_t n, const uint8_t *bits,

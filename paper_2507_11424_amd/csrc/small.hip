@@ -229,6 +229,18 @@ __global__ void k_logp(const double *amp, const double *mlog, int batch, double 
     if (arg) arg[b] = atan2(amp[2 * b + 1], amp[2 * b]);
 }
 
+// Per-sample bond of the amplitude boundary: the largest kept value over the cuts.
+__global__ void k_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= batch) return;
+    int v = constant;
+    if (k && cuts > 0) {
+        v = 0;
+        for (int c = 0; c < cuts; ++c) v = max(v, k[(int64_t)c * batch + z]);
+    }
+    out[(int64_t)z * stride] = v;
+}
+
 // xs[z] = bits[(row0 + z) * n_qubits + qubit]: the given bit of every sample of
 // a wave, as the selector of the projected row tensor.
 __global__ void k_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs) {
@@ -409,6 +421,13 @@ hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t
                                const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sample_stats, dim3(1), dim3(SN), 0, s, log_q, log_p, n, log_Z, bits, n_qubits, out, z_is);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride,
+                           hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chi_used, dim3((batch + 63) / 64), dim3(64), 0, s, k, cuts, batch, constant, out, stride);
     return hipGetLastError();
 }
 

@@ -83,10 +83,14 @@ struct SampleOpts {
     uint64_t seed = 0;
     int wave = 0;  // samples per wave (0 = automatic)
     int init_tag = 2;  // Philox stream of the fit's random initial guesses
+    double svd_cutoff = 0;  // > 0: SVD truncation of every fitted amplitude boundary
+    int chi_x_min = 1;      // lower clamp of the truncation
 };
 
+// chi_used (optional, device [n][rows] int32): largest kept bond of the
+// amplitude boundary conditioning each row (1 for the first row).
 void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts &o, uint64_t first,
-            int64_t n, const double *uniforms, uint8_t *bits, double *log_q, double *log_p);
+            int64_t n, const double *uniforms, uint8_t *bits, double *log_q, double *log_p, int *chi_used);
 
 // <x|psi> for given bitstrings bits [n][nq] (device) by single-layer boundary
 // MPSs of bond <= o.chi_x from the top row down; log_p [n] = 2 log|<x|psi>|,

@@ -299,3 +299,52 @@ def test_timing_mode_with_nested_contractions():
     finally:
         h.set_timing(False)
         h.close()
+
+
+# ---------------------------------------------------------------- SVD truncation
+
+def _svd_cases():
+    rng = np.random.default_rng(31)
+    out = []
+    for n in (1, 2, 7, 16, 33, 64, 65, 128):
+        R = _rand(rng, (5, n, n)) * np.exp(-0.35 * np.arange(n))[None, None, :]
+        R[1] = np.triu(R[1])                      # QR-shaped
+        if n > 2:
+            R[2][:, n // 2:] = 0                  # rank-deficient (zero columns)
+        if n > 1:
+            R[3] = R[3][:, :1] @ _rand(rng, (1, n))  # rank one
+        # Householder R of a rank-deficient matrix: zero rows below the rank,
+        # small nonzero columns past it (the Jacobi residue of such columns must
+        # not be rotated down into underflow)
+        r = max(1, n // 2)
+        R[4] = np.triu(R[4])
+        R[4][r:] = 0
+        R[4][:r, r:] *= 1e-4
+        out.append(R)
+    return out
+
+
+@pytest.mark.parametrize("case", range(8))
+@pytest.mark.parametrize("cutoff,chi_min", [(1e-2, 1), (1e-6, 1), (1e-2, 5), (1e-300, 1)])
+@pytest.mark.parametrize("esz", [16, 8])
+def test_svd_truncation(handle, case, cutoff, chi_min, esz):
+    import torch
+    from oracle.sampler import keep_count
+    R = _svd_cases()[case]
+    n = R.shape[-1]
+    U, SV, k = handle.test_svd(torch.from_numpy(R).cuda(), cutoff, chi_min, esz)
+    U = U.cpu().numpy().astype(np.complex128)
+    SV = SV.cpu().numpy().astype(np.complex128)
+    k = k.cpu().numpy()
+    tol = 1e-12 if esz == 16 else 2e-6
+    for b in range(R.shape[0]):
+        u, s, vh = np.linalg.svd(R[b])
+        kk = keep_count(s, cutoff, chi_min)
+        assert k[b] == kk, (n, b, k[b], kk)
+        best = (u[:, :kk] * s[:kk]) @ vh[:kk]
+        assert np.linalg.norm(U[b] @ SV[b] - best) <= tol * np.linalg.norm(R[b]) * max(1, n / 16)
+        assert np.all(U[b][:, kk:] == 0) and np.all(SV[b][kk:] == 0)
+        G = U[b][:, :kk].conj().T @ U[b][:, :kk]
+        assert np.abs(G - np.eye(kk)).max() <= (1e-11 if esz == 16 else 1e-5)
+        # rows of SV carry the singular values, in descending order
+        assert np.allclose(np.linalg.norm(SV[b][:kk], axis=1), s[:kk], rtol=tol * 10, atol=tol * s[0])

@@ -138,3 +138,46 @@ def test_sample_exact_matches_statevector(handle):
         x = tuple(int(v) for v in b)
         assert abs(q - math.log(p[x] / Z)) < 1e-10
         assert abs(pp - math.log(p[x])) < 1e-10
+
+
+@pytest.mark.parametrize("name,chi,chi_x,cutoff,chi_min", [("sq4x4D3", 9, 9, 1e-2, 1), ("sq4x4D3", 9, 9, 1e-4, 2),
+                                                           ("brick5x4D2", 3, 4, 1e-3, 2),
+                                                           ("rotsq18D3", 5, 6, 5e-3, 1), ("c1", 16, 16, 1e-2, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sample_svd_cutoff(handle, name, chi, chi_x, cutoff, chi_min, prec):
+    """Adaptive amplitude-boundary bond: bits, log q, log p and the per-row
+    kept bonds against the oracle's SVD sweep."""
+    lat, T = STATES[name]()
+    n = 16
+    rows = len(T)
+    used = np.zeros((n, rows), dtype=np.int64)
+    rb, rq, rp = oracle.sample(T, lat.site_index, chi, chi_x, n, seed=77, first=3, svd_cutoff=cutoff,
+                               chi_x_min=chi_min, chi_used=used)
+    dtype = "c128" if prec == "fp64" else "c64"
+    if dtype == "c64":
+        T = [[t.astype(np.complex64).astype(np.complex128) for t in row] for row in T]
+        rb, rq, rp = oracle.sample(T, lat.site_index, chi, chi_x, n, seed=77, first=3, svd_cutoff=cutoff,
+                                   chi_x_min=chi_min, chi_used=used)
+    o = opts(chi=chi, chi_x=chi_x, svd_cutoff=cutoff, chi_x_min=chi_min, prec=prec)
+    bits, lq, lp, cu = handle.sample(dev_peps(lat, T, dtype), o, n, seed=77, first=3, want_chi=True)
+    bits, lq, lp, cu = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy(), cu.cpu().numpy()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert np.array_equal(bits, rb)
+    assert np.array_equal(cu, used)
+    assert np.abs(lq - rq).max() < tol
+    assert np.abs(lp - rp).max() < tol
+
+
+def test_sample_svd_cutoff_truncates_and_reports(handle):
+    """With the cutoff the kept bonds vary per sample and stay within
+    [chi_x_min, chi_x]; without it they equal the fixed widths."""
+    lat, T = STATES["sq4x4D3"]()
+    P = dev_peps(lat, T)
+    _, _, _, cu0 = handle.sample(P, opts(chi=9, chi_x=9), 32, seed=4, want_chi=True)
+    _, _, _, cu1 = handle.sample(P, opts(chi=9, chi_x=9, svd_cutoff=3e-2, chi_x_min=2), 32, seed=4, want_chi=True)
+    cu0, cu1 = cu0.cpu().numpy(), cu1.cpu().numpy()
+    assert np.all(cu0[:, 0] == 1) and np.all(cu1[:, 0] == 1)
+    assert np.all(cu0 == cu0[0])
+    assert np.all(cu1 <= cu0) and np.all(cu1[:, 1:] >= 2)
+    assert (cu1 < cu0).any()
+    assert len({tuple(r) for r in cu1}) > 1
