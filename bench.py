@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--samples", type=int, default=16, help="samples per step")
     ap.add_argument("--chi", type=int, default=None)
     ap.add_argument("--chi-x", type=int, default=None)
+    ap.add_argument("--svd-cutoff", type=float, default=None,
+                    help="adaptive amplitude-boundary bond: discarded-weight cutoff (0 = fixed chi_x)")
+    ap.add_argument("--chi-x-min", type=int, default=None)
     ap.add_argument("--no-env", action="store_true", help="leave the density matrices out of the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -150,7 +153,10 @@ def main():
     h.set_autotune(not a.no_autotune, a.tune_cache or None)
     # inputs resident in HBM before timing (stored as the configured type, computed in the mode's type)
     P = tnb.Peps.from_numpy(lat, T, dtype=dev_dtype, device="cuda:0")
-    o = tnb.make_opts(chi=chi, chi_x=chi_x, prec=a.prec)
+    cutoff = a.svd_cutoff if a.svd_cutoff is not None else cfg.get("svd_cutoff", 0.0)
+    chi_x_min = a.chi_x_min or cfg.get("chi_x_min", 1)
+    o = tnb.make_opts(chi=chi, chi_x=chi_x, prec=a.prec, svd_cutoff=cutoff, chi_x_min=chi_x_min)
+    used = []
 
     phases = ("contract", "environments", "sample")
 
@@ -170,8 +176,10 @@ def main():
             rec["environments"] = (time.perf_counter() - t0, h.counters())
             print(f"  environments done ({rec['environments'][0]:.1f} s)", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        h.sample(P, o, a.samples, seed=17)
+        res = h.sample(P, o, a.samples, seed=17, want_chi=cutoff > 0)
         torch.cuda.synchronize()
+        if cutoff > 0:
+            used.append(res[3][:, 1:].float())
         rec["sample"] = (time.perf_counter() - t0, h.counters())
         return lz, rec
 
@@ -225,7 +233,8 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[a.prec],
         "data": "synthetic",
-        "config": {"workload": f"{a.config}: {lat.name}, {lat.n_qubits} qubits, chi={chi}, chi_x={chi_x}, "
+        "config": {"workload": f"{a.config}: {lat.name}, {lat.n_qubits} qubits, chi={chi}, "
+                               f"chi_x={chi_x}{' (max, SVD cutoff %g)' % cutoff if cutoff > 0 else ''}, "
                                f"{cfg['dtype']} input, {a.samples} samples per step",
                    "samples_per_step": a.samples, "prec": a.prec, "autotune": not a.no_autotune},
         "contraction_tflops": con_f / con_t / 1e12 if con_t > 0 else None,
@@ -243,6 +252,12 @@ def main():
                      "kernel_ms_per_step": gemm_ms,
                      "qr_ms_per_step": qr_ms},
     }
+    if cutoff > 0:
+        cu = torch.cat(used)
+        out["config"]["svd_cutoff"] = cutoff
+        out["config"]["chi_x_min"] = chi_x_min
+        out["chi_x_used"] = {"mean": float(cu.mean()), "min": int(cu.min()), "max": int(cu.max()),
+                             "note": "largest kept bond per row of each sample's amplitude boundary"}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, T, chi, chi_x, con_f / a.steps)
     print(json.dumps(out))

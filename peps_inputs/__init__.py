@@ -211,8 +211,9 @@ CONFIGS = {
     "c3": dict(lattice=("brick", 12, 12, 8), recipe="haar", eps=0.2, seed=1003,
                dtype="c64", chi=64, chi_x=64, n_samples=64),
     # 105-site rotated square in a 15x15 grid, D=8, complex64
+    # amplitude-boundary bond adaptive in [16, 128] by an SVD cutoff of 1e-8
     "c4": dict(lattice=("rotsq", 0, 0, 8), recipe="haar", eps=0.2, seed=1004,
-               dtype="c64", chi=128, chi_x=16, n_samples=16384),
+               dtype="c64", chi=128, chi_x=128, n_samples=16384, svd_cutoff=1e-8, chi_x_min=16),
     # 12x12 square, D=16, complex64
     "c5sq": dict(lattice=("square", 12, 12, 16), recipe="haar", eps=0.2, seed=1005,
                  dtype="c64", chi=256, chi_x=16, n_samples=8192),
