@@ -193,8 +193,8 @@ def main():
     # between launches; the events are read when each call returns)
     t0 = time.perf_counter()
     acc = {k: [0.0, 0.0] for k in phases}
-    gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = 0.0
-    launches = 0
+    gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = masked_ms = 0.0
+    launches = masked = 0
     for i in range(a.steps):
         lz, rec = step(timing=True)
         for k, (sec, c) in rec.items():
@@ -205,6 +205,8 @@ def main():
             qr_ms += c["qr_ms"]
             qr_gemm_flops += c["qr_gemm_flops"]
             launches += c["gemm_launches"]
+            masked += c["masked_launches"]
+            masked_ms += c["masked_ms"]
         print(f"timed step {i} done ({time.perf_counter() - t0:.1f} s so far)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -217,6 +219,8 @@ def main():
     qr_ms /= a.steps
     qr_gemm_flops /= a.steps
     launches //= a.steps
+    masked //= a.steps
+    masked_ms /= a.steps
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     samples = a.samples * a.steps
     con_t, con_f = acc["contract"]
@@ -250,7 +254,11 @@ def main():
                      "algorithmic_flops_per_step": gemm_flops,
                      "of_which_orthonormalisation_flops": qr_gemm_flops,
                      "kernel_ms_per_step": gemm_ms,
-                     "qr_ms_per_step": qr_ms},
+                     "qr_ms_per_step": qr_ms,
+                     "masked_launches_per_step": masked,
+                     "masked_ms_per_step": masked_ms,
+                     "masked_note": "launches that extend the s = 1 environment only for the samples that "
+                                    "drew 1 (other tiles skipped); excluded from achieved, flops and launches"},
     }
     if cutoff > 0:
         cu = torch.cat(used)

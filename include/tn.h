@@ -197,10 +197,13 @@ const char *tn_last_error(const tn_handle *h);
  * issues contractions of its own (Gram matrices, triangular solves): they are
  * included in gemm_* and in qr_ms, and their flops are also reported in
  * qr_gemm_flops, so gemm_flops - qr_gemm_flops is the method's own work.
+ * The sampler extends the environment of the rarer outcome only for the
+ * samples that drew it: those launches skip the other samples' tiles, and are
+ * counted apart (masked_launches, masked_ms), outside gemm_*.
  * Any pointer may be NULL. */
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
                           double *gemm_ms, double *qr_ms, int64_t *qr_launches,
-                          double *qr_gemm_flops);
+                          double *qr_gemm_flops, int64_t *masked_launches, double *masked_ms);
 
 /* Enables (1) or disables (0) per-launch HIP-event timing: an event pair is
  * recorded around every contraction and QR launch on the handle's stream and read

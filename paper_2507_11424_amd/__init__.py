@@ -78,7 +78,8 @@ def lib(path: Optional[str] = None):
     L.tn_sample_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
     L.tn_last_error.argtypes = [vp]
     L.tn_last_error.restype = ctypes.c_char_p
-    L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64), dp]
+    L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64), dp,
+                                  ctypes.POINTER(i64), dp]
     L.tn_set_timing.argtypes = [vp, ctypes.c_int]
     L.tn_set_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.tn_plan_report.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
@@ -283,12 +284,14 @@ class Handle:
         return res
 
     def counters(self):
-        f, ms, qms, qf = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        n, qn = ctypes.c_int64(), ctypes.c_int64()
+        f, ms, qms, qf, mms = (ctypes.c_double() for _ in range(5))
+        n, qn, mn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().tn_get_counters(self.h, ctypes.byref(f), ctypes.byref(n), ctypes.byref(ms),
-                                          ctypes.byref(qms), ctypes.byref(qn), ctypes.byref(qf)))
+                                          ctypes.byref(qms), ctypes.byref(qn), ctypes.byref(qf),
+                                          ctypes.byref(mn), ctypes.byref(mms)))
         return dict(gemm_flops=f.value, gemm_launches=n.value, gemm_ms=ms.value, qr_ms=qms.value,
-                    qr_launches=qn.value, qr_gemm_flops=qf.value)
+                    qr_launches=qn.value, qr_gemm_flops=qf.value, masked_launches=mn.value,
+                    masked_ms=mms.value)
 
     def set_timing(self, on: bool):
         self._check(lib().tn_set_timing(self.h, 1 if on else 0))

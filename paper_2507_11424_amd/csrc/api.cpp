@@ -341,7 +341,8 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
 const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "null handle"; }
 
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
-                          double *qr_ms, int64_t *qr_launches, double *qr_gemm_flops) {
+                          double *qr_ms, int64_t *qr_launches, double *qr_gemm_flops, int64_t *masked_launches,
+                          double *masked_ms) {
     if (!h || !h->E) return TN_ERR_INVALID;
     try {
         const_cast<Engine *>(h->E.get())->collect_timing();
@@ -355,6 +356,8 @@ tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_
     if (qr_ms) *qr_ms = c.qr_ms;
     if (qr_launches) *qr_launches = c.qr_launches;
     if (qr_gemm_flops) *qr_gemm_flops = c.qr_gemm_flops;
+    if (masked_launches) *masked_launches = c.masked_launches;
+    if (masked_ms) *masked_ms = c.masked_ms;
     return TN_OK;
 }
 

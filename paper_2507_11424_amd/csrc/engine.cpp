@@ -124,8 +124,9 @@ void Engine::collect_timing() {
         float ms = 0.f;
         TN_HIP(hipEventElapsedTime(&ms, ev_[i].a, ev_[i].b));
         if (ev_[i].kind == 0) ctr.gemm_ms += ms;
+        else if (ev_[i].kind == 2) ctr.masked_ms += ms;
         else ctr.qr_ms += ms;
-        if (ev_[i].plan) {
+        if (ev_[i].plan && ev_[i].kind != 2) {
             ev_[i].plan->ms += ms;
             ev_[i].plan->calls += 1;
         }
@@ -376,6 +377,10 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     (void)kml; (void)knl;
     P->kM = kM; P->kN = kN; P->K = K; P->Z = Z;
     P->pack = (prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B);
+    P->bl = bl;
+    P->kml = swap ? nl : ml;
+    P->knl = swap ? ml : nl;
+    P->ldim = dim;
     P->key = key;
     P->flops = 8.0 * (double)M * (double)N * (double)K * (double)Z;
     {
@@ -617,11 +622,18 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         } else {         // the packed size is: it shrinks in proportion to the letter
             chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, dim * lim / w));
         }
+        {   // equal slices (a short last slice wastes a launch on a thin GEMM)
+            const int nsl = (dim + chunk - 1) / chunk;
+            chunk = (dim + nsl - 1) / nsl;
+        }
         const bool summed = C.idx.find(c) == std::string::npos;
+        const int *mask = mask_;
         for (int i0 = 0; i0 < dim; i0 += chunk) {
             const int n = std::min(chunk, dim - i0);
+            if (mask && c == mask_letter_) mask_ = mask + i0;
             contract(slice(A, c, i0, n), slice(B, c, i0, n), slice(C, c, i0, n),
                      summed ? (accumulate || i0 > 0) : accumulate);
+            mask_ = mask;
         }
         return;
     }
@@ -658,6 +670,25 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         g.kchunk = P->base.kchunk;
         cfg = P->cfg;
     }
+    bool masked = false;
+    if (mask_) {
+        auto div = [&](const std::string &l) {
+            int64_t d = 1;
+            for (size_t i = 1; i < l.size(); ++i) d *= P->ldim.at(l[i]);
+            return d;
+        };
+        int mode = 0;
+        int64_t d = 0;
+        if (!P->bl.empty() && P->bl[0] == mask_letter_) { mode = 1; d = div(P->bl); }
+        else if (!P->kml.empty() && P->kml[0] == mask_letter_) { mode = 2; d = div(P->kml); }
+        else if (!P->knl.empty() && P->knl[0] == mask_letter_) { mode = 3; d = div(P->knl); }
+        if (mode && d <= INT32_MAX) {
+            g.mask = mask_;
+            g.mask_mode = mode;
+            g.mask_div = (int)d;
+            masked = true;
+        }
+    }
     void *part = nullptr;
     if (g.ksplit > 1) {
         part = pool_.get((size_t)g.ksplit * g.batch * (size_t)g.M * g.N * esz);
@@ -666,7 +697,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     // contractions inside the orthonormalisation are timed too (their QR-level
     // pair also covers them); their flops are booked separately.  The pair
     // covers the split-BF16 packing of the operands.
-    const size_t ev = timing ? next_pair(0) : NOEV;
+    const size_t ev = timing ? next_pair(masked ? 2 : 0) : NOEV;
     if (ev != NOEV) {
         ev_[ev].plan = P;
         TN_HIP(hipEventRecord(ev_[ev].a, s));
@@ -678,6 +709,10 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     if (part) pool_.put(part);
     if (pka) pool_.put(pka);
     if (pkb) pool_.put(pkb);
+    if (masked) {
+        ctr.masked_launches += 1;
+        return;
+    }
     if (in_qr_) ctr.qr_gemm_flops += P->flops;
     ctr.gemm_flops += P->flops;
     ctr.gemm_launches += 1;

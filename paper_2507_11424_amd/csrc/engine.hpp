@@ -89,6 +89,10 @@ struct Plan {
     bool tuned = false;   // tile configuration chosen by measurement
     int64_t kM = 0, kN = 0, K = 0, Z = 0;
     bool pack = false;    // split-BF16 on packed operand planes (else split while staging)
+    // letters of the batch, kernel-M and kernel-N index spaces, slowest first,
+    // and every letter's extent (for masked launches)
+    std::string bl, kml, knl;
+    std::map<char, int> ldim;
 };
 
 struct Counters {
@@ -98,6 +102,10 @@ struct Counters {
     double qr_ms = 0;
     int64_t qr_launches = 0;
     double qr_gemm_flops = 0;  // part of gemm_flops issued inside orthonormalisations
+    // masked launches (tiles of masked items skipped): neither their flops nor
+    // their time enter gemm_flops / gemm_ms
+    double masked_ms = 0;
+    int64_t masked_launches = 0;
     void reset() { *this = Counters(); }
 };
 
@@ -119,6 +127,13 @@ class Engine {
     // sampler truncates its amplitude boundaries, whose zero-padded bonds make
     // the fit's matrices rank-deficient (CholeskyQR needs full column rank)
     bool householder_only = false;
+    // Contractions issued while a mask is set skip the tiles of the items z of
+    // letter `letter` with mask[z] == 0 (device int array over that letter's
+    // extent) when the letter is the slowest of the batch, M or N index space;
+    // otherwise they compute everything.  Skipped parts of the output keep
+    // whatever they held.
+    void set_mask(const int *mask, char letter) { mask_ = mask; mask_letter_ = letter; }
+    void clear_mask() { mask_ = nullptr; }
 
     void set_prec(int p) { prec = p; esz = (p == tnk::P_FP64) ? 16 : 8; }
 
@@ -172,6 +187,8 @@ class Engine {
     std::vector<EvPair> ev_;
     size_t ev_used_ = 0;
     bool in_qr_ = false;  // contractions issued by the QR: flops booked as qr_gemm_flops
+    const int *mask_ = nullptr;
+    char mask_letter_ = 0;
     bool autotune_ = false;
     std::string tune_path_;
     std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)

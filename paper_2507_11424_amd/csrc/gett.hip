@@ -54,6 +54,13 @@ __device__ inline int xcd_remap(int t, int ntiles) {
     return (t & 7) * (ntiles >> 3) + (t >> 3);
 }
 
+// Tile skip of a masked launch (see GettArgs::mask); block-uniform.
+__device__ inline bool gett_skip(const GettArgs &p, int b, int m0, int n0) {
+    if (!p.mask) return false;
+    const int c = p.mask_mode == 1 ? b : (p.mask_mode == 2 ? m0 : n0);
+    return p.mask[c / p.mask_div] == 0;
+}
+
 // --------------------------------------------------------------------------
 // Operand staging shared by the kernels.
 //
@@ -170,6 +177,7 @@ gett_mfma(GettArgs p) {
     const T sgnB = p.conjB ? T(-1) : T(1);
 
     for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        if (gett_skip(p, b, m0, n0)) continue;
         const __amdgpu_buffer_rsrc_t rA = make_rsrc(reinterpret_cast<const C2 *>(p.A) + p.a_boff[b], p.a_bytes);
         const __amdgpu_buffer_rsrc_t rB = make_rsrc(reinterpret_cast<const C2 *>(p.B) + p.b_boff[b], p.b_bytes);
         C2 *Cb = reinterpret_cast<C2 *>(p.C) + p.c_boff[b];
@@ -422,6 +430,7 @@ gett_bf16_direct(GettArgs p) {
     const float sgnB = p.conjB ? -1.f : 1.f;
 
     for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        if (gett_skip(p, b, m0, n0)) continue;
         const __amdgpu_buffer_rsrc_t rA = make_rsrc(reinterpret_cast<const float2 *>(p.A) + p.a_boff[b], p.a_bytes);
         const __amdgpu_buffer_rsrc_t rB = make_rsrc(reinterpret_cast<const float2 *>(p.B) + p.b_boff[b], p.b_bytes);
         float2 *Cb = reinterpret_cast<float2 *>(p.C) + p.c_boff[b];
@@ -625,6 +634,7 @@ gett_bf16(GettArgs p) {
     const int wm = wave / WGN, wn = wave % WGN;
 
     for (int b = blockIdx.y; b < p.batch; b += gridDim.y) {
+        if (gett_skip(p, b, m0, n0)) continue;
         const __amdgpu_buffer_rsrc_t rA =
             make_rsrc(reinterpret_cast<const unsigned short *>(p.A) + (int64_t)b * NP * 2 * planeA, p.a_bytes);
         const __amdgpu_buffer_rsrc_t rB =
@@ -757,6 +767,12 @@ hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStre
     if (tiles <= 0 || a.batch <= 0) return hipSuccess;
     const int gz = a.ksplit > 1 ? a.ksplit : 1;
     if ((!a.a_kaff || !a.b_kaff) && a.kchunk > GETT_KTAB) return hipErrorInvalidValue;
+    if (a.mask && (a.mask_div <= 0 || (a.mask_mode == 2 && a.mask_div % bm) || (a.mask_mode == 3 && a.mask_div % bn) ||
+                   a.mask_mode < 1 || a.mask_mode > 3)) {
+        GettArgs u = a;  // tiles would straddle mask items: compute everything
+        u.mask = nullptr;
+        return launch_k(kernel, u, bm, bn, nt, s);
+    }
     const size_t dyn = (size_t)((a.a_kaff ? 0 : a.kchunk) + (a.b_kaff ? 0 : a.kchunk)) * sizeof(int);
     static bool attr = false;  // one per kernel instantiation
     if (!attr) {

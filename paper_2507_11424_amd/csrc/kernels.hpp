@@ -41,6 +41,13 @@ struct GettArgs {
     // kpad columns (K rounded up to 32); a_bytes / b_bytes are one batch item's
     // planes
     int kpad;
+    // optional tile skip: a tile whose item mask[coord / mask_div] is 0 is not
+    // computed (its part of C is left as it was); coord is the batch index
+    // (mask_mode 1), the tile's first row m0 (2) or first column n0 (3).  For
+    // modes 2 and 3 mask_div must be a multiple of the tile edge (else the
+    // launch ignores the mask).
+    const int *mask;
+    int mask_mode, mask_div;
 };
 // Largest K slice a block handles when a k table is not affine (LDS table).
 constexpr int GETT_KTAB = 1024;
@@ -160,6 +167,11 @@ hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t s);
 hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s);
 // dots [4][2] = complex P~(s, t) -> p2[4] = Re P / sum Re P (if p2), zz = sum (-1)^(s+t) Re P / sum Re P.
 hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t s);
+// pt1[z] = exp(lnr[z]) tot[z] - pt0[z] (complex, [batch][2] doubles): the other
+// projection's P~ from the traced total, whose right environment is stored
+// divided by exp(lnr).
+hipError_t launch_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch,
+                                hipStream_t s);
 // Final amplitude -> log p.
 // xs[z] = bits[(row0 + z) * n_qubits + qubit] (0/1) for z < batch.
 hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs,

@@ -56,6 +56,32 @@ Ten env_left(Engine &E, const Ten &L, const Ten &m, const SiteRef &a, const Ten 
     return out;
 }
 
+// First contraction of a left step, shared by both projections: L . m.
+// Direct route: [z,b,g,h,k,u,A]; transfer-matrix route (u = 1): [z,A,b,g,h,k].
+Ten left_t1(Engine &E, const Ten &L, const Ten &m, bool via_T) {
+    return E.contract_new(op(L, "zabghk"), op(m, "zauA"), via_T ? "zAbghk" : "zbghkuA");
+}
+
+// Rest of a left step with the site projected on s, from t1 (direct route).
+Ten left_rest(Engine &E, const Ten &t1, const Ten &m, const SiteRef &a, const Ten &B, int s) {
+    Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop_proj(a, s, "uhdH"), "zbgkAdH");
+    Ten t3 = E.contract_new(op(t2, "zbgkAdH"), op(B, "gdeG"), "zbkAHeG");
+    E.drop(t2);
+    Ten W = E.contract_new(op(m, "zbvB", true), sop_proj(a, s, "vkeK", true), "zbBkeK");
+    Ten out = E.contract_new(op(t3, "zbkAHeG"), op(W, "zbBkeK"), "zABGHK");
+    E.drop(t3);
+    E.drop(W);
+    return out;
+}
+
+// Rest of a left step through a u = 1 site with transfer matrix T_s, from t1.
+Ten left_rest_T(Engine &E, const Ten &t1, const Ten &m, const Ten &T) {
+    Ten t2 = E.contract_new(op(t1, "zAbghk"), op(T, "ghkGHK"), "zAbGHK");
+    Ten out = E.contract_new(op(t2, "zAbGHK"), op(m, "zbvB", true), "zABGHK");
+    E.drop(t2);
+    return out;
+}
+
 // [z,A,B,G,H,K] + column -> [z,a,b,g,h,k] (physical index summed).
 Ten env_right(Engine &E, const Ten &R, const Ten &m, const SiteRef &a, const Ten &B) {
     Ten t1 = E.contract_new(op(m, "zauA"), op(R, "zABGHK"), "zauBGHK");
@@ -326,6 +352,8 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     uint64_t *sidx = reinterpret_cast<uint64_t *>(E.raw((size_t)Zw * 8));
     double *mlog = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
     double *pt = reinterpret_cast<double *>(E.raw((size_t)Zw * 32));
+    double *ptot = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    double *lnR = reinterpret_cast<double *>(E.raw((size_t)Zw * 8 * (cols + 1)));
     int *flags = reinterpret_cast<int *>(E.raw((size_t)Zw * 4));
     int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
     double *amp = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
@@ -365,12 +393,14 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         T1[c] = transfer(E, a, Bb.site[c], 1);
                     }
                 }
+                // R[c] is stored divided by its norm; lnR[c][z] keeps the log of that norm
                 std::vector<Ten> R(cols + 1);
                 R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
                 for (int c = cols - 1; c >= 1; --c) {
                     R[c] = useT[c] ? env_right_T(E, R[c + 1], m[c], Ts[c])
                                    : env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
-                    unit(E, R[c], Z);
+                    const int64_t per = R[c].numel() / Z;
+                    E.normalise(R[c].p, R[c].esz, per, Z, per, lnR + (size_t)c * Zw, false, nullptr);
                 }
                 Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
                 for (int c = 0; c < cols; ++c) {
@@ -384,17 +414,25 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
                         continue;
                     }
-                    Ten L0, L1;
-                    if (useT[c]) {
-                        L0 = env_left_T(E, Lc, m[c], T0[c]);
-                        L1 = env_left_T(E, Lc, m[c], T1[c]);
-                    } else {
-                        L0 = env_left(E, Lc, m[c], a, Bb.site[c], 0);
-                        L1 = env_left(E, Lc, m[c], a, Bb.site[c], 1);
-                    }
+                    // P~(0) = <L_c . site(s=0), R_{c+1}>.  For c >= 1 the traced right
+                    // environment gives P~(0) + P~(1) = |R_c| <L_c, R_c>, so P~(1)
+                    // needs no second projected step; the step with s = 1 is then
+                    // extended only for the samples that drew 1 (the others' tiles
+                    // are skipped).  Site 0 computes both projections.
+                    Ten t1 = left_t1(E, Lc, m[c], useT[c] != 0);
+                    Ten L0 = useT[c] ? left_rest_T(E, t1, m[c], T0[c]) : left_rest(E, t1, m[c], a, Bb.site[c], 0);
                     const int64_t per = L0.numel() / Z;
                     E.dot(L0.p, R[c + 1].p, L0.esz, per, Z, per, pt);
-                    E.dot(L1.p, R[c + 1].p, L1.esz, per, Z, per, pt + 2 * Zw);
+                    Ten L1;
+                    const bool rest = c >= 1;
+                    if (rest) {
+                        const int64_t perc = Lc.numel() / Z;
+                        E.dot(Lc.p, R[c].p, Lc.esz, perc, Z, perc, ptot);
+                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, pt, pt + 2 * Zw, Z, E.s));
+                    } else {
+                        L1 = useT[c] ? left_rest_T(E, t1, m[c], T1[c]) : left_rest(E, t1, m[c], a, Bb.site[c], 1);
+                        E.dot(L1.p, R[c + 1].p, L1.esz, per, Z, per, pt + 2 * Zw);
+                    }
                     tnk::DrawArgs d{};
                     d.batch = Z;
                     d.pt0 = pt;
@@ -411,6 +449,18 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     d.xsel = xs;
                     d.flags = flags;
                     TN_HIP(tnk::launch_draw(d, E.s));
+                    if (rest) {
+                        E.set_mask(xs, 'z');
+                        try {
+                            L1 = useT[c] ? left_rest_T(E, t1, m[c], T1[c])
+                                         : left_rest(E, t1, m[c], a, Bb.site[c], 1);
+                        } catch (...) {
+                            E.clear_mask();
+                            throw;
+                        }
+                        E.clear_mask();
+                    }
+                    E.drop(t1);
                     // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
                     E.drop(Lc);
                     Lc = E.make(L0.d);
@@ -461,10 +511,12 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
         }
     } catch (...) {
         E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+        E.unraw(ptot); E.unraw(lnR);
         if (kbuf) E.unraw(kbuf);
         throw;
     }
     E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+    E.unraw(ptot); E.unraw(lnR);
     if (kbuf) E.unraw(kbuf);
 }
 

@@ -229,6 +229,14 @@ __global__ void k_logp(const double *amp, const double *mlog, int batch, double 
     if (arg) arg[b] = atan2(amp[2 * b + 1], amp[2 * b]);
 }
 
+__global__ void k_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= batch) return;
+    const double f = exp(lnr[z]);
+    pt1[2 * z] = f * tot[2 * z] - pt0[2 * z];
+    pt1[2 * z + 1] = f * tot[2 * z + 1] - pt0[2 * z + 1];
+}
+
 // Per-sample bond of the amplitude boundary: the largest kept value over the cuts.
 __global__ void k_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,6 +429,13 @@ hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t
                                const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sample_stats, dim3(1), dim3(SN), 0, s, log_q, log_p, n, log_Z, bits, n_qubits, out, z_is);
+    return hipGetLastError();
+}
+
+hipError_t launch_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch,
+                                hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_marginal_rest, dim3((batch + 63) / 64), dim3(64), 0, s, tot, lnr, pt0, pt1, batch);
     return hipGetLastError();
 }
 
