@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--tune-cache", default="",
                     help="text file of tile choices: loaded if present, new choices appended")
     ap.add_argument("--plan-report", default="", help="write the per-shape contraction timing table here")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="no HIP events around the launches (for counter runs; roofline.achieved is then null)")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -62,6 +64,38 @@ def copy_reference(nbytes: int):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gett_brick12x12_D8_chi64_fp64_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11424_amd", "csrc", f) for f in ("gett.hip", "kernels.hpp")]
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per contraction launch from the committed counter summary
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by the copy-kernel
+    calibration), if it was taken on this workload with the current kernel
+    sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("workload") != workload or kv.get("kernel_sources_sha256") != kernel_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(lat, T, chi, chi_x, contraction_flops):
@@ -193,10 +227,10 @@ def main():
     # between launches; the events are read when each call returns)
     t0 = time.perf_counter()
     acc = {k: [0.0, 0.0] for k in phases}
-    gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = masked_ms = 0.0
+    gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = masked_ms = gemm_bytes = 0.0
     launches = masked = 0
     for i in range(a.steps):
-        lz, rec = step(timing=True)
+        lz, rec = step(timing=not a.no_timing)
         for k, (sec, c) in rec.items():
             acc[k][0] += sec
             acc[k][1] += c["gemm_flops"] - c["qr_gemm_flops"]
@@ -207,6 +241,7 @@ def main():
             launches += c["gemm_launches"]
             masked += c["masked_launches"]
             masked_ms += c["masked_ms"]
+            gemm_bytes += c["gemm_bytes"]
         print(f"timed step {i} done ({time.perf_counter() - t0:.1f} s so far)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -221,9 +256,12 @@ def main():
     launches //= a.steps
     masked //= a.steps
     masked_ms /= a.steps
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    gemm_bytes /= a.steps
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None
     samples = a.samples * a.steps
     con_t, con_f = acc["contract"]
+    workload = (f"{a.config} {a.prec} samples={a.samples} chi={chi} chi_x={chi_x} cutoff={cutoff:g} "
+                f"env={'no' if a.no_env else 'yes'}")
     out = {
         "metric": METRIC,
         "value": samples / dt,
@@ -246,12 +284,17 @@ def main():
                        "tflops": v[1] / v[0] / 1e12 if v[0] > 0 else None} for k, v in acc.items()},
         "log_abs_Z": lz,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[a.prec], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS[a.prec] if achieved else None,
+                     "traffic": stored_traffic(workload),
+                     "traffic_unit": "HBM bytes per launch (all contraction launches, masked included)",
+                     "algorithmic_bytes_per_launch": gemm_bytes / launches if launches else None,
                      "kernel": "gett (complex contraction engine, all tile variants, with its split-K "
                                "reduction)",
                      "launches_per_step": launches,
-                     "kernel_avg_us": 1e3 * gemm_ms / launches if launches else None,
+                     "kernel_avg_us": 1e3 * gemm_ms / launches if launches and gemm_ms > 0 else None,
                      "algorithmic_flops_per_step": gemm_flops,
+                     "algorithmic_bytes_per_step": gemm_bytes,
+                     "counter_workload": workload,
                      "of_which_orthonormalisation_flops": qr_gemm_flops,
                      "kernel_ms_per_step": gemm_ms,
                      "qr_ms_per_step": qr_ms,

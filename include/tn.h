@@ -199,11 +199,14 @@ const char *tn_last_error(const tn_handle *h);
  * qr_gemm_flops, so gemm_flops - qr_gemm_flops is the method's own work.
  * The sampler extends the environment of the rarer outcome only for the
  * samples that drew it: those launches skip the other samples' tiles, and are
- * counted apart (masked_launches, masked_ms), outside gemm_*.
+ * counted apart (masked_launches, masked_ms), outside gemm_*.  gemm_bytes:
+ * algorithmic operand bytes of the counted launches (A and B read once, C
+ * written once, and read once more when accumulating).
  * Any pointer may be NULL. */
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
                           double *gemm_ms, double *qr_ms, int64_t *qr_launches,
-                          double *qr_gemm_flops, int64_t *masked_launches, double *masked_ms);
+                          double *qr_gemm_flops, int64_t *masked_launches, double *masked_ms,
+                          double *gemm_bytes);
 
 /* Enables (1) or disables (0) per-launch HIP-event timing: an event pair is
  * recorded around every contraction and QR launch on the handle's stream and read

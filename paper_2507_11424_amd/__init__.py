@@ -79,7 +79,7 @@ def lib(path: Optional[str] = None):
     L.tn_last_error.argtypes = [vp]
     L.tn_last_error.restype = ctypes.c_char_p
     L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64), dp,
-                                  ctypes.POINTER(i64), dp]
+                                  ctypes.POINTER(i64), dp, dp]
     L.tn_set_timing.argtypes = [vp, ctypes.c_int]
     L.tn_set_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.tn_plan_report.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
@@ -284,14 +284,14 @@ class Handle:
         return res
 
     def counters(self):
-        f, ms, qms, qf, mms = (ctypes.c_double() for _ in range(5))
+        f, ms, qms, qf, mms, gb = (ctypes.c_double() for _ in range(6))
         n, qn, mn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().tn_get_counters(self.h, ctypes.byref(f), ctypes.byref(n), ctypes.byref(ms),
                                           ctypes.byref(qms), ctypes.byref(qn), ctypes.byref(qf),
-                                          ctypes.byref(mn), ctypes.byref(mms)))
+                                          ctypes.byref(mn), ctypes.byref(mms), ctypes.byref(gb)))
         return dict(gemm_flops=f.value, gemm_launches=n.value, gemm_ms=ms.value, qr_ms=qms.value,
                     qr_launches=qn.value, qr_gemm_flops=qf.value, masked_launches=mn.value,
-                    masked_ms=mms.value)
+                    masked_ms=mms.value, gemm_bytes=gb.value)
 
     def set_timing(self, on: bool):
         self._check(lib().tn_set_timing(self.h, 1 if on else 0))

@@ -342,7 +342,7 @@ const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "nul
 
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
                           double *qr_ms, int64_t *qr_launches, double *qr_gemm_flops, int64_t *masked_launches,
-                          double *masked_ms) {
+                          double *masked_ms, double *gemm_bytes) {
     if (!h || !h->E) return TN_ERR_INVALID;
     try {
         const_cast<Engine *>(h->E.get())->collect_timing();
@@ -358,6 +358,7 @@ tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_
     if (qr_gemm_flops) *qr_gemm_flops = c.qr_gemm_flops;
     if (masked_launches) *masked_launches = c.masked_launches;
     if (masked_ms) *masked_ms = c.masked_ms;
+    if (gemm_bytes) *gemm_bytes = c.gemm_bytes;
     return TN_OK;
 }
 

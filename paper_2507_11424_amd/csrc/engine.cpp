@@ -716,6 +716,8 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     if (in_qr_) ctr.qr_gemm_flops += P->flops;
     ctr.gemm_flops += P->flops;
     ctr.gemm_launches += 1;
+    ctr.gemm_bytes += (double)P->Z * ((double)P->kM * P->K + (double)P->K * P->kN +
+                                      (double)P->kM * P->kN * (accumulate ? 2.0 : 1.0)) * esz;
 }
 
 Ten Engine::contract_new(const Op &A, const Op &B, const std::string &ic) {

@@ -106,6 +106,9 @@ struct Counters {
     // their time enter gemm_flops / gemm_ms
     double masked_ms = 0;
     int64_t masked_launches = 0;
+    // algorithmic operand bytes of the (unmasked) launches: every element of A
+    // and B read once, C written once (read too when accumulating)
+    double gemm_bytes = 0;
     void reset() { *this = Counters(); }
 };
 
