@@ -24,6 +24,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef short v8s __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Tr;
 // Accumulator layout of the 16x16 MFMA forms: lane l, register r holds row
@@ -647,22 +648,30 @@ gett_bf16(GettArgs p) {
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
-        v8s ra[LA], rb[LB];
-        auto gload = [&](int k0) {
+        // operand chunks are prefetched two k-steps ahead into alternating
+        // register sets: one k-step of MFMA work is shorter than a global load's
+        // latency, so a single step of lead leaves the CU waiting at the barrier
+        v8s ra0[LA], rb0[LB], ra1[LA], rb1[LB];
+        // loads are issued on every step (past kend they read the zero of an
+        // out-of-range offset): a branch around them would leave the count of
+        // loads in flight unknown at the LDS store, and the wait there would
+        // then also cover the loads just issued for the step after next
+        auto gload = [&](int k0, v8s (&ra)[LA], v8s (&rb)[LB]) {
+            const bool in = k0 < kend;
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 const int e = tid + NT * i;
-                const uint32_t o = e < CA ? chunk_off(e, BM, p.M, m0, planeA, k0) : OOB;
+                const uint32_t o = (in && e < CA) ? chunk_off(e, BM, p.M, m0, planeA, k0) : OOB;
                 ra[i] = __builtin_bit_cast(v8s, __builtin_amdgcn_raw_buffer_load_b128(rA, (int)o, 0, 0));
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
                 const int e = tid + NT * i;
-                const uint32_t o = e < CB ? chunk_off(e, BN, p.N, n0, planeB, k0) : OOB;
+                const uint32_t o = (in && e < CB) ? chunk_off(e, BN, p.N, n0, planeB, k0) : OOB;
                 rb[i] = __builtin_bit_cast(v8s, __builtin_amdgcn_raw_buffer_load_b128(rB, (int)o, 0, 0));
             }
         };
-        auto lstore = [&](int st) {
+        auto lstore = [&](int st, const v8s (&ra)[LA], const v8s (&rb)[LB]) {
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 const int e = tid + NT * i;
@@ -678,15 +687,7 @@ gett_bf16(GettArgs p) {
                 *reinterpret_cast<v8s *>(&sB[st][pl & 1][pl >> 1][row][ch * 8]) = rb[i];
             }
         };
-        // the previous batch item's last step may still read stage 0
-        __syncthreads();
-        gload(kbeg);
-        lstore(0);
-        __syncthreads();
-        int st = 0;
-        for (int k0 = kbeg; k0 < kend; k0 += BK) {
-            const bool more = k0 + BK < kend;
-            if (more) gload(k0 + BK);
+        auto compute = [&](int st) {
             const int kc = (lane >> 4) * 8;
             v8s a[2][NP][FM], bfr[2][NP][FN];
 #pragma unroll
@@ -705,7 +706,8 @@ gett_bf16(GettArgs p) {
 #pragma unroll
             for (int q = 0; q < NP; ++q)
 #pragma unroll
-                for (int i = 0; i < FM; ++i) an[q][i] = a[1][q][i] ^ (short)0x8000;
+                for (int i = 0; i < FM; ++i)
+                    an[q][i] = __builtin_bit_cast(v8s, __builtin_bit_cast(v4u, a[1][q][i]) ^ 0x80008000u);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -725,13 +727,32 @@ gett_bf16(GettArgs p) {
                                 __builtin_bit_cast(v8bf, a[1][qa][i]), __builtin_bit_cast(v8bf, bfr[0][qb][j]), accI[i][j], 0, 0, 0);
                         }
                 }
-            if (more) {
+        };
+        int st = 0;
+        // one k-step: `cur` holds step k0 + BK (loaded a step earlier), `nxt`
+        // receives step k0 + 2 BK
+        auto step = [&](int k0, v8s (&cur_a)[LA], v8s (&cur_b)[LB], v8s (&nxt_a)[LA], v8s (&nxt_b)[LB]) {
+            gload(k0 + 2 * BK, nxt_a, nxt_b);
+            if (k0 < kend) compute(st);
+            if (k0 + BK < kend) {
                 if (S == 1) __syncthreads();  // single stage: every wave has read it
                 const int nx = (S == 2) ? (st ^ 1) : 0;
-                lstore(nx);
+                lstore(nx, cur_a, cur_b);
                 __syncthreads();
                 st = nx;
             }
+        };
+        // the previous batch item's last step may still read stage 0
+        __syncthreads();
+        gload(kbeg, ra0, rb0);
+        lstore(0, ra0, rb0);
+        gload(kbeg + BK, ra0, rb0);
+        __syncthreads();
+        // both halves run on every trip (the second is idle past kend) so that
+        // every trip issues the same loads
+        for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+            step(k0, ra0, rb0, ra1, rb1);
+            step(k0 + BK, ra1, rb1, ra0, rb0);
         }
         float2 *Pb = p.ksplit > 1
                          ? reinterpret_cast<float2 *>(p.part) + ((int64_t)blockIdx.z * p.batch + b) * (int64_t)p.M * p.N
