@@ -141,7 +141,10 @@ gett_mfma(GettArgs p) {
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
     const int tiles_m = (p.M + BM - 1) / BM;
-    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    // a masked launch keeps the dispatch order, which deals consecutive tiles
+    // round-robin over the XCDs: with contiguous per-XCD ranges the tiles of
+    // one sample would sit on one or two XCDs and the others would idle
+    const int tile = p.mask ? (int)blockIdx.x : xcd_remap(blockIdx.x, tiles_m * tiles_n);
     const int m0 = (tile / tiles_n) * BM;
     const int n0 = (tile % tiles_n) * BN;
     const int kbeg = blockIdx.z * p.kchunk;
@@ -395,7 +398,10 @@ gett_bf16_direct(GettArgs p) {
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
     const int tiles_m = (p.M + BM - 1) / BM;
-    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    // a masked launch keeps the dispatch order, which deals consecutive tiles
+    // round-robin over the XCDs: with contiguous per-XCD ranges the tiles of
+    // one sample would sit on one or two XCDs and the others would idle
+    const int tile = p.mask ? (int)blockIdx.x : xcd_remap(blockIdx.x, tiles_m * tiles_n);
     const int m0 = (tile / tiles_n) * BM;
     const int n0 = (tile % tiles_n) * BN;
     const int kbeg = blockIdx.z * p.kchunk;
@@ -617,7 +623,10 @@ gett_bf16(GettArgs p) {
     const int tid = threadIdx.x;
     const int tiles_n = (p.N + BN - 1) / BN;
     const int tiles_m = (p.M + BM - 1) / BM;
-    const int tile = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+    // a masked launch keeps the dispatch order, which deals consecutive tiles
+    // round-robin over the XCDs: with contiguous per-XCD ranges the tiles of
+    // one sample would sit on one or two XCDs and the others would idle
+    const int tile = p.mask ? (int)blockIdx.x : xcd_remap(blockIdx.x, tiles_m * tiles_n);
     const int m0 = (tile / tiles_n) * BM;
     const int n0 = (tile % tiles_n) * BN;
     const int kbeg = blockIdx.z * p.kchunk;
