@@ -260,6 +260,14 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
                      int method);
 tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cutoff, int chi_min, void *U, void *SV,
                       int esz, int32_t *k);
+/* tn_test_set_mask: later tn_test_contract calls skip the output tiles of the
+ *   items i of index letter `letter` with mask[i] == 0 (device int32 array
+ *   over that letter's extent; those parts of C keep their contents), as the
+ *   sampler's s = 1 environment steps do; mask = NULL clears it.  The skip
+ *   applies when the letter is the slowest of the contraction's batch, row or
+ *   column indices and its blocks align with the tiles, else everything is
+ *   computed. */
+tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter);
 
 #ifdef __cplusplus
 }

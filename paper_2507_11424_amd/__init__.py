@@ -31,7 +31,7 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 # every symbol declared in include/tn.h
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
            "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
-           "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd"]
+           "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask"]
 
 
 class TnError(RuntimeError):
@@ -91,9 +91,10 @@ def lib(path: Optional[str] = None):
     L.tn_test_qr.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int]
     L.tn_test_svd.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, ctypes.c_int, vp, vp,
                               ctypes.c_int, vp]
+    L.tn_test_set_mask.argtypes = [vp, vp, ctypes.c_char]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
-              "tn_test_qr", "tn_test_svd", "tn_amplitude", "tn_sample_stats"):
+              "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -309,7 +310,19 @@ class Handle:
 
     # ---------------------------------------------------------------- test hooks
     def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
-                      accumulate=False, cfg: int = -1, ksplit: int = 0):
+                      accumulate=False, cfg: int = -1, ksplit: int = 0, mask=None, mask_letter: str = "z"):
+        """C[ic] (+)= A[ia] B[ib] through the contraction engine; with `mask`
+        (device int32 over letter mask_letter) the tiles of masked-out items
+        are skipped (see tn_test_set_mask)."""
+        if mask is not None:
+            self._check(lib().tn_test_set_mask(self.h, ctypes.c_void_p(mask.data_ptr()), mask_letter.encode()))
+        try:
+            self._test_contract(prec, ia, A, ib, B, ic, C, conjA, conjB, accumulate, cfg, ksplit)
+        finally:
+            if mask is not None:
+                lib().tn_test_set_mask(self.h, None, b"z")
+
+    def _test_contract(self, prec, ia, A, ib, B, ic, C, conjA, conjB, accumulate, cfg, ksplit):
         self._check(lib().tn_test_contract(self.h, PREC[prec], ia.encode(), ctypes.c_void_p(A.data_ptr()),
                                            _i32(A.shape), int(conjA), ib.encode(), ctypes.c_void_p(B.data_ptr()),
                                            _i32(B.shape), int(conjB), ic.encode(), ctypes.c_void_p(C.data_ptr()),

@@ -449,6 +449,13 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
     }
 }
 
+tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter) {
+    if (!h || !h->E) return TN_ERR_INVALID;
+    if (mask) h->E->set_mask(mask, letter);
+    else h->E->clear_mask();
+    return TN_OK;
+}
+
 tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cutoff, int chi_min, void *U, void *SV,
                       int esz, int32_t *k) {
     try {

@@ -336,6 +336,7 @@ __global__ void __launch_bounds__(256) splitk_reduce(GettArgs p) {
         const int b = (int)(e / per);
         const int64_t mn = e - (int64_t)b * per;
         const int m = (int)(mn / p.N), n = (int)(mn - (int64_t)m * p.N);
+        if (gett_skip(p, b, m, n)) continue;  // the masked tiles wrote no partials
         double sr = 0.0, si = 0.0;
         for (int z = 0; z < p.ksplit; ++z) {
             const C2 v = P[(int64_t)z * total + e];
@@ -797,12 +798,8 @@ hipError_t launch_k(K kernel, const GettArgs &a, int bm, int bn, int nt, hipStre
     if (tiles <= 0 || a.batch <= 0) return hipSuccess;
     const int gz = a.ksplit > 1 ? a.ksplit : 1;
     if ((!a.a_kaff || !a.b_kaff) && a.kchunk > GETT_KTAB) return hipErrorInvalidValue;
-    if (a.mask && (a.mask_div <= 0 || (a.mask_mode == 2 && a.mask_div % bm) || (a.mask_mode == 3 && a.mask_div % bn) ||
-                   a.mask_mode < 1 || a.mask_mode > 3)) {
-        GettArgs u = a;  // tiles would straddle mask items: compute everything
-        u.mask = nullptr;
-        return launch_k(kernel, u, bm, bn, nt, s);
-    }
+    if (a.mask && ((a.mask_mode == 2 && a.mask_div % bm) || (a.mask_mode == 3 && a.mask_div % bn)))
+        return hipErrorInvalidValue;  // launch_gett clears a mask the tiles do not align with
     const size_t dyn = (size_t)((a.a_kaff ? 0 : a.kchunk) + (a.b_kaff ? 0 : a.kchunk)) * sizeof(int);
     static bool attr = false;  // one per kernel instantiation
     if (!attr) {
@@ -861,8 +858,17 @@ void gett_tile(int cfg, int prec, int *bm, int *bn) {
 
 static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t s);
 
-hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s) {
-    if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+hipError_t launch_gett(const GettArgs &a0, int prec, int cfg, hipStream_t s) {
+    if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
+    GettArgs a = a0;
+    if (a.mask) {
+        // tiles that would straddle mask items: compute everything
+        int bm = 64, bn = 64;
+        gett_tile(cfg, prec, &bm, &bn);
+        if (a.mask_div <= 0 || a.mask_mode < 1 || a.mask_mode > 3 || (a.mask_mode == 2 && a.mask_div % bm) ||
+            (a.mask_mode == 3 && a.mask_div % bn))
+            a.mask = nullptr;
+    }
     hipError_t e = launch_main(a, prec, cfg, s);
     if (e != hipSuccess || a.ksplit <= 1) return e;
     return prec == P_FP64 ? launch_reduce<double2>(a, s) : launch_reduce<float2>(a, s);

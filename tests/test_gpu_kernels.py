@@ -348,3 +348,50 @@ def test_svd_truncation(handle, case, cutoff, chi_min, esz):
         assert np.abs(G - np.eye(kk)).max() <= (1e-11 if esz == 16 else 1e-5)
         # rows of SV carry the singular values, in descending order
         assert np.allclose(np.linalg.norm(SV[b][:kk], axis=1), s[:kk], rtol=tol * 10, atol=tol * s[0])
+
+
+# ---------------------------------------------------------------- masked launches
+
+MASK_CASES = [
+    # (A, B, C letters, dims, mode): the sample letter z slowest in the kernel's
+    # rows (the sampler's environment steps), columns, or the batch index
+    ("zab", "bc", "zac", dict(z=5, a=128, b=70, c=96)),
+    ("ab", "zbc", "zac", dict(z=5, a=40, b=33, c=64)),
+    ("zab", "zbc", "zac", dict(z=5, a=70, b=50, c=66)),
+    ("zab", "bc", "zac", dict(z=5, a=100, b=40, c=30)),  # rows per item not a tile multiple: all computed
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", range(len(MASK_CASES)))
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("ksplit", [1, 3])
+def test_masked_contraction(handle, prec, case, cfg, ksplit):
+    import torch
+    ia, ib, ic, dims = MASK_CASES[case]
+    rng = np.random.default_rng(100 + case)
+    A = _rand(rng, tuple(dims[c] for c in ia))
+    B = _rand(rng, tuple(dims[c] for c in ib))
+    ref = np.einsum(f"{ia},{ib}->{ic}", A, B)
+    td = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+        ref = np.einsum(f"{ia},{ib}->{ic}", A, B)
+    sentinel = 7.0 - 3.0j
+    C = torch.full(tuple(dims[c] for c in ic), sentinel, dtype=td, device="cuda")
+    mask = torch.tensor([1, 0, 1, 1, 0], dtype=torch.int32, device="cuda")
+    handle.test_contract(prec, ia, torch.from_numpy(A).to("cuda", td), ib, torch.from_numpy(B).to("cuda", td),
+                         ic, C, cfg=cfg, ksplit=ksplit, mask=mask)
+    got = C.cpu().numpy().astype(np.complex128)
+    tol = TOL[prec] * np.abs(A).max() * np.abs(B).max() * dims[[c for c in ia if c in ib][-1]] * 4
+    zc = ic.index("z")
+    for z in range(5):
+        g = np.take(got, z, axis=zc)
+        r = np.take(ref, z, axis=zc)
+        if z in (0, 2, 3):
+            assert np.abs(g - r).max() <= tol, (z, np.abs(g - r).max())
+        elif case < 3:
+            assert np.all(g == sentinel), z  # skipped: untouched
+        else:
+            assert np.abs(g - r).max() <= tol  # misaligned: computed
