@@ -66,7 +66,7 @@ def copy_reference(nbytes: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gett_brick12x12_D8_chi64_fp64_traffic.txt")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "gett_brick12x12_D8_chi64_counters.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11424_amd", "csrc", f) for f in ("gett.hip", "kernels.hpp")]
 
 
@@ -79,23 +79,26 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(workload: str):
-    """HBM bytes per contraction launch from the committed counter summary
-    (rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by the copy-kernel
-    calibration), if it was taken on this workload with the current kernel
-    sources; else None."""
+def stored_counters(workload: str) -> dict:
+    """The committed rocprofv3 counter record of the contraction launches for
+    this workload (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE scaled by
+    the copy-kernel calibration, HBM GB/s, MFMA busy fraction), if it was taken
+    with the current kernel sources; else {}."""
     try:
-        with open(TRAFFIC_FILE) as f:
-            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+        with open(COUNTER_FILE) as f:
+            text = f.read()
     except OSError:
-        return None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("workload") != workload or kv.get("kernel_sources_sha256") != kernel_hash():
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    h = kernel_hash()
+    for block in text.split("\n\n"):
+        kv = {}
+        for line in block.splitlines():
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("workload") == workload and kv.get("kernel_sources_sha256") == h:
+            return kv
+    return {}
 
 
 def cpu_baseline(lat, T, chi, chi_x, contraction_flops):
@@ -262,6 +265,7 @@ def main():
     con_t, con_f = acc["contract"]
     workload = (f"{a.config} {a.prec} samples={a.samples} chi={chi} chi_x={chi_x} cutoff={cutoff:g} "
                 f"env={'no' if a.no_env else 'yes'}")
+    ctr = stored_counters(workload)
     out = {
         "metric": METRIC,
         "value": samples / dt,
@@ -285,8 +289,10 @@ def main():
         "log_abs_Z": lz,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[a.prec] if achieved else None,
-                     "traffic": stored_traffic(workload),
+                     "traffic": float(ctr["traffic_bytes_per_launch"]) if ctr else None,
                      "traffic_unit": "HBM bytes per launch (all contraction launches, masked included)",
+                     "hbm_gbs_rocprof": float(ctr["hbm_gbs"]) if ctr else None,
+                     "mfma_util_rocprof": float(ctr["mfma_util"]) if ctr else None,
                      "algorithmic_bytes_per_launch": gemm_bytes / launches if launches else None,
                      "kernel": "gett (complex contraction engine, all tile variants, with its split-K "
                                "reduction)",
