@@ -451,9 +451,10 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
 void Engine::tune(Plan *P, tnk::GettArgs g) {
     struct Cand { int cfg, ks; };
     std::vector<Cand> cands;
-    const int cfgs[4] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64, tnk::CFG_128x64W};
+    const int cfgs[5] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64, tnk::CFG_128x64W, tnk::CFG_128x128W};
     for (int c : cfgs) {
-        if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W) && P->kM < 128) continue;
+        if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W || c == tnk::CFG_128x128W) && P->kM < 128) continue;
+        if (c == tnk::CFG_128x128W && (!P->pack || P->kN < 128)) continue;  // packed split-BF16 only
         if (c == tnk::CFG_64x16 && P->kN > 64) continue;
         int bm = 64, bn = 64;
         tnk::gett_tile(c, prec, &bm, &bn);
@@ -646,6 +647,8 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     g.conjB = (P->swapped ? A.conj : B.conj) ? 1 : 0;
     g.accumulate = accumulate ? 1 : 0;
     int cfg = P->cfg;
+    if (force_cfg == tnk::CFG_128x128W && !P->pack)
+        throw TnError(ST_UNSUPPORTED, "the 128x128 tile serves packed split-BF16 operands only");
     if (force_cfg >= 0) {
         Plan tmp = *P;  // shares the tables, owns nothing
         set_split(&tmp, force_cfg, force_ksplit);

@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(256) k_pack_bf16(const float2 *X, const int64_
 // packed planes (rows M / N, p.kpad columns), p.a_bytes / p.b_bytes one batch
 // item's planes.  Each stage copies 16-byte chunks (8 k values of one plane
 // row) through LDS; rows past M / N read as zero (buffer range check).
-template <int NP, int BM, int BN, int WGM, int WGN>
+template <int NP, int BM, int BN, int WGM, int WGN, bool PF2 = true>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 gett_bf16(GettArgs p) {
     constexpr int BK = 32;
@@ -659,9 +659,10 @@ gett_bf16(GettArgs p) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[i][j][r] = 0.f; accI[i][j][r] = 0.f; }
         // operand chunks are prefetched two k-steps ahead into alternating
-        // register sets: one k-step of MFMA work is shorter than a global load's
-        // latency, so a single step of lead leaves the CU waiting at the barrier
-        v8s ra0[LA], rb0[LB], ra1[LA], rb1[LB];
+        // register sets (PF2): one k-step of MFMA work is shorter than a global
+        // load's latency, so a single step of lead leaves the CU waiting at the
+        // barrier; tiles short of registers keep one set and one step of lead
+        v8s ra0[LA], rb0[LB], ra1[PF2 ? LA : 1], rb1[PF2 ? LB : 1];
         // loads are issued on every step (past kend they read the zero of an
         // out-of-range offset): a branch around them would leave the count of
         // loads in flight unknown at the LDS store, and the wait there would
@@ -756,13 +757,29 @@ gett_bf16(GettArgs p) {
         __syncthreads();
         gload(kbeg, ra0, rb0);
         lstore(0, ra0, rb0);
-        gload(kbeg + BK, ra0, rb0);
-        __syncthreads();
-        // both halves run on every trip (the second is idle past kend) so that
-        // every trip issues the same loads
-        for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
-            step(k0, ra0, rb0, ra1, rb1);
-            step(k0 + BK, ra1, rb1, ra0, rb0);
+        if constexpr (PF2) {
+            gload(kbeg + BK, ra0, rb0);
+            __syncthreads();
+            // both halves run on every trip (the second is idle past kend) so
+            // that every trip issues the same loads
+            for (int k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+                step(k0, ra0, rb0, ra1, rb1);
+                step(k0 + BK, ra1, rb1, ra0, rb0);
+            }
+        } else {
+            __syncthreads();
+            for (int k0 = kbeg; k0 < kend; k0 += BK) {
+                const bool more = k0 + BK < kend;
+                if (more) gload(k0 + BK, ra0, rb0);
+                compute(st);
+                if (more) {
+                    if (S == 1) __syncthreads();
+                    const int nx = (S == 2) ? (st ^ 1) : 0;
+                    lstore(nx, ra0, rb0);
+                    __syncthreads();
+                    st = nx;
+                }
+            }
         }
         float2 *Pb = p.ksplit > 1
                          ? reinterpret_cast<float2 *>(p.part) + ((int64_t)blockIdx.z * p.batch + b) * (int64_t)p.M * p.N
@@ -851,6 +868,7 @@ void gett_tile(int cfg, int prec, int *bm, int *bn) {
         case CFG_128x64: *bm = 128; *bn = 64; break;
         case CFG_64x16: *bm = 64; *bn = 16; break;
         case CFG_128x64W: *bm = 128; *bn = 64; break;
+        case CFG_128x128W: *bm = 128; *bn = 128; break;
         default: *bm = 64; *bn = 64; break;
     }
     (void)prec;
@@ -903,6 +921,8 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
                                           : launch_k(gett_bf16_direct<2, 64, 16, 4, 1>, a, 64, 16, 256, s);
             case CFG_128x64W: return a.kpad ? launch_k(gett_bf16<2, 128, 64, 4, 2>, a, 128, 64, 512, s)
                                             : launch_k(gett_bf16_direct<2, 128, 64, 4, 2>, a, 128, 64, 512, s);
+            case CFG_128x128W: return a.kpad ? launch_k(gett_bf16<2, 128, 128, 2, 4, false>, a, 128, 128, 512, s)
+                                             : hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }
@@ -915,6 +935,8 @@ static hipError_t launch_main(const GettArgs &a, int prec, int cfg, hipStream_t 
                                       : launch_k(gett_bf16_direct<3, 64, 16, 4, 1>, a, 64, 16, 256, s);
         case CFG_128x64W: return a.kpad ? launch_k(gett_bf16<3, 128, 64, 4, 2>, a, 128, 64, 512, s)
                                         : launch_k(gett_bf16_direct<3, 128, 64, 4, 2>, a, 128, 64, 512, s);
+        case CFG_128x128W: return a.kpad ? launch_k(gett_bf16<3, 128, 128, 2, 4, false>, a, 128, 128, 512, s)
+                                         : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -59,7 +59,8 @@ enum GettCfg : int {
     CFG_128x64 = 1,   // 4 waves, 64x32 per wave
     CFG_64x16 = 2,    // skinny N
     CFG_128x64W = 3,  // 8 waves, 32x32 per wave
-    CFG_COUNT = 4
+    CFG_128x128W = 4, // 8 waves, 64x32 per wave (packed split-BF16 only)
+    CFG_COUNT = 5
 };
 
 hipError_t launch_gett(const GettArgs &a, int prec, int cfg, hipStream_t s);
