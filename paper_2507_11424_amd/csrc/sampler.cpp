@@ -30,32 +30,6 @@ namespace tnb {
 
 namespace {
 
-// [z,a,b,g,h,k] + column -> [z,A,B,G,H,K]; s < 0 sums the physical index.
-Ten env_left(Engine &E, const Ten &L, const Ten &m, const SiteRef &a, const Ten &B, int s) {
-    Ten t1 = E.contract_new(op(L, "zabghk"), op(m, "zauA"), "zbghkuA");
-    Ten out;
-    if (s < 0) {
-        Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop(a, "suhdH"), "zbgkAsdH");
-        E.drop(t1);
-        Ten t3 = E.contract_new(op(t2, "zbgkAsdH"), op(B, "gdeG"), "zbkAsHeG");
-        E.drop(t2);
-        Ten W = E.contract_new(op(m, "zbvB", true), sop(a, "svkeK", true), "zbBskeK");
-        out = E.contract_new(op(t3, "zbkAsHeG"), op(W, "zbBskeK"), "zABGHK");
-        E.drop(t3);
-        E.drop(W);
-    } else {
-        Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop_proj(a, s, "uhdH"), "zbgkAdH");
-        E.drop(t1);
-        Ten t3 = E.contract_new(op(t2, "zbgkAdH"), op(B, "gdeG"), "zbkAHeG");
-        E.drop(t2);
-        Ten W = E.contract_new(op(m, "zbvB", true), sop_proj(a, s, "vkeK", true), "zbBkeK");
-        out = E.contract_new(op(t3, "zbkAHeG"), op(W, "zbBkeK"), "zABGHK");
-        E.drop(t3);
-        E.drop(W);
-    }
-    return out;
-}
-
 // First contraction of a left step, shared by both projections: L . m.
 // Direct route: [z,b,g,h,k,u,A]; transfer-matrix route (u = 1): [z,A,b,g,h,k].
 Ten left_t1(Engine &E, const Ten &L, const Ten &m, bool via_T) {
@@ -79,6 +53,21 @@ Ten left_rest_T(Engine &E, const Ten &t1, const Ten &m, const Ten &T) {
     Ten t2 = E.contract_new(op(t1, "zAbghk"), op(T, "ghkGHK"), "zAbGHK");
     Ten out = E.contract_new(op(t2, "zAbGHK"), op(m, "zbvB", true), "zABGHK");
     E.drop(t2);
+    return out;
+}
+
+// Left step with the physical index summed (sites without a qubit):
+// [z,a,b,g,h,k] + column -> [z,A,B,G,H,K].
+Ten env_left_traced(Engine &E, const Ten &L, const Ten &m, const SiteRef &a, const Ten &B) {
+    Ten t1 = left_t1(E, L, m, false);
+    Ten t2 = E.contract_new(op(t1, "zbghkuA"), sop(a, "suhdH"), "zbgkAsdH");
+    E.drop(t1);
+    Ten t3 = E.contract_new(op(t2, "zbgkAsdH"), op(B, "gdeG"), "zbkAsHeG");
+    E.drop(t2);
+    Ten W = E.contract_new(op(m, "zbvB", true), sop(a, "svkeK", true), "zbBskeK");
+    Ten out = E.contract_new(op(t3, "zbkAsHeG"), op(W, "zbBskeK"), "zABGHK");
+    E.drop(t3);
+    E.drop(W);
     return out;
 }
 
@@ -117,11 +106,9 @@ Ten transfer(Engine &E, const SiteRef &a, const Ten &B, int s) {
 
 // Left step through a u = 1 site with its transfer matrix: [z,a,b,g,h,k] -> [z,A,B,G,H,K].
 Ten env_left_T(Engine &E, const Ten &L, const Ten &m, const Ten &T) {
-    Ten t1 = E.contract_new(op(L, "zabghk"), op(m, "zauA"), "zAbghk");
-    Ten t2 = E.contract_new(op(t1, "zAbghk"), op(T, "ghkGHK"), "zAbGHK");
+    Ten t1 = left_t1(E, L, m, true);
+    Ten out = left_rest_T(E, t1, m, T);
     E.drop(t1);
-    Ten out = E.contract_new(op(t2, "zAbGHK"), op(m, "zbvB", true), "zABGHK");
-    E.drop(t2);
     return out;
 }
 
@@ -407,7 +394,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     const SiteRef &a = V.at(r, c);
                     int *xs = xsel + (size_t)c * Zw;
                     if (a.dim(0) == 1) {
-                        Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left(E, Lc, m[c], a, Bb.site[c], -1);
+                        Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left_traced(E, Lc, m[c], a, Bb.site[c]);
                         E.drop(Lc);
                         Lc = L2;
                         unit(E, Lc, Z);
