@@ -169,7 +169,7 @@ def cpu_baseline(lat, T, chi, chi_x, contraction_flops):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if a.copy_ref:
         copy_reference(a.copy_ref)

@@ -55,7 +55,7 @@ typedef enum {
     TN_ERR_OOM = 3,         /* device allocation failed or workspace cap reached */
     TN_ERR_HIP = 4,         /* a HIP runtime call failed (incl. no device)       */
     TN_ERR_NUMERIC = 5,     /* non-finite or non-positive norm or marginal       */
-    TN_ERR_UNSUPPORTED = 6  /* valid request outside what this build implements  */
+    TN_ERR_UNSUPPORTED = 6  /* valid request outside what this library implements */
 } tn_status;
 
 typedef enum { TN_C128 = 0, TN_C64 = 1 } tn_dtype;
