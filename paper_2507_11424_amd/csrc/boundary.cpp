@@ -112,6 +112,13 @@ void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R, bool well_conditio
         rd.push_back((int)n);
         *R = E.make(rd, T.esz);
     }
+    if (m == n) {
+        // a square factor spans the whole space: Q = I, R = T is an exact
+        // factorisation in another gauge (every output is gauge invariant)
+        TN_HIP(tnk::launch_eye(Q.p, Q.esz, (int)n, (int)batch, E.s));
+        if (R) TN_HIP(tnk::launch_convert(T.p, T.esz, R->p, R->esz, T.numel(), E.s));
+        return;
+    }
     tnk::QrArgs a{};
     a.m = (int)m; a.n = (int)n; a.batch = (int)batch;
     a.A = T.p; a.a_esz = T.esz; a.a_bs = m * n; a.a_rs = n; a.a_cs = 1; a.a_conj = 0;
@@ -137,6 +144,11 @@ void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *Lf, bool well_condit
         ld.push_back((int)m);
         ld.push_back((int)k);
         *Lf = E.make(ld, T.esz);
+    }
+    if (m == n) {  // square: Q = I, L = T (see qr_left)
+        TN_HIP(tnk::launch_eye(Q.p, Q.esz, (int)n, (int)batch, E.s));
+        if (Lf) TN_HIP(tnk::launch_convert(T.p, T.esz, Lf->p, Lf->esz, T.numel(), E.s));
+        return;
     }
     // QR of T^H (n x m): T^H(i, j) = conj(T[j][i])
     tnk::QrArgs a{};

@@ -133,6 +133,8 @@ hipError_t launch_convert(const void *src, int src_esz, void *dst, int dst_esz, 
 hipError_t launch_init_tensor(void *out, int esz, int64_t n, int batch, int64_t bs,
                               uint64_t seed, uint64_t tag, uint64_t row, uint64_t site,
                               const uint64_t *sample, hipStream_t s);
+// batch n x n identity matrices, back to back.
+hipError_t launch_eye(void *x, int esz, int n, int batch, hipStream_t s);
 // Fill with a complex constant.
 hipError_t launch_fill(void *x, int esz, int64_t n, double re, double im, hipStream_t s);
 // out[b] = sum_i x[b][i] * y[b][i] (no conjugation), complex FP64 result (2 doubles).

@@ -88,6 +88,15 @@ __global__ void __launch_bounds__(NT) k_fill(void *x, int esz, int64_t n, double
         stc(x, esz, i, make_double2(re, im));
 }
 
+// x[b] = n x n identity, `batch` matrices back to back.
+__global__ void __launch_bounds__(NT) k_eye(void *x, int esz, int n, int64_t total) {
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int64_t r = e % nn;
+        stc(x, esz, e, make_double2(r / n == r % n ? 1.0 : 0.0, 0.0));
+    }
+}
+
 // Philox4x64-10: ten rounds of two 64x64 -> 128-bit products with a Weyl key schedule.
 __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -354,6 +363,13 @@ hipError_t launch_convert(const void *src, int se, void *dst, int de, int64_t n,
 hipError_t launch_fill(void *x, int esz, int64_t n, double re, double im, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(NT), 0, s, x, esz, n, re, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_eye(void *x, int esz, int n, int batch, hipStream_t s) {
+    const int64_t total = (int64_t)n * n * batch;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eye, dim3(grid_for(total)), dim3(NT), 0, s, x, esz, n, total);
     return hipGetLastError();
 }
 
