@@ -689,6 +689,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
             g.mask = mask_;
             g.mask_mode = mode;
             g.mask_div = (int)d;
+            g.mask_skip = mask_skip_;
             masked = true;
         }
     }

@@ -131,11 +131,15 @@ class Engine {
     // the fit's matrices rank-deficient (CholeskyQR needs full column rank)
     bool householder_only = false;
     // Contractions issued while a mask is set skip the tiles of the items z of
-    // letter `letter` with mask[z] == 0 (device int array over that letter's
+    // letter `letter` with mask[z] == skip (device int array over that letter's
     // extent) when the letter is the slowest of the batch, M or N index space;
     // otherwise they compute everything.  Skipped parts of the output keep
     // whatever they held.
-    void set_mask(const int *mask, char letter) { mask_ = mask; mask_letter_ = letter; }
+    void set_mask(const int *mask, char letter, int skip = 0) {
+        mask_ = mask;
+        mask_letter_ = letter;
+        mask_skip_ = skip;
+    }
     void clear_mask() { mask_ = nullptr; }
 
     void set_prec(int p) { prec = p; esz = (p == tnk::P_FP64) ? 16 : 8; }
@@ -192,6 +196,7 @@ class Engine {
     bool in_qr_ = false;  // contractions issued by the QR: flops booked as qr_gemm_flops
     const int *mask_ = nullptr;
     char mask_letter_ = 0;
+    int mask_skip_ = 0;
     bool autotune_ = false;
     std::string tune_path_;
     std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)

@@ -59,7 +59,7 @@ __device__ inline int xcd_remap(int t, int ntiles) {
 __device__ inline bool gett_skip(const GettArgs &p, int b, int m0, int n0) {
     if (!p.mask) return false;
     const int c = p.mask_mode == 1 ? b : (p.mask_mode == 2 ? m0 : n0);
-    return p.mask[c / p.mask_div] == 0;
+    return p.mask[c / p.mask_div] == p.mask_skip;
 }
 
 // --------------------------------------------------------------------------

@@ -41,13 +41,13 @@ struct GettArgs {
     // kpad columns (K rounded up to 32); a_bytes / b_bytes are one batch item's
     // planes
     int kpad;
-    // optional tile skip: a tile whose item mask[coord / mask_div] is 0 is not
-    // computed (its part of C is left as it was); coord is the batch index
-    // (mask_mode 1), the tile's first row m0 (2) or first column n0 (3).  For
-    // modes 2 and 3 mask_div must be a multiple of the tile edge (else the
-    // launch ignores the mask).
+    // optional tile skip: a tile whose item mask[coord / mask_div] equals
+    // mask_skip is not computed (its part of C is left as it was); coord is the
+    // batch index (mask_mode 1), the tile's first row m0 (2) or first column n0
+    // (3).  For modes 2 and 3 mask_div must be a multiple of the tile edge
+    // (else the launch ignores the mask).
     const int *mask;
-    int mask_mode, mask_div;
+    int mask_mode, mask_div, mask_skip;
 };
 // Largest K slice a block handles when a k table is not affine (LDS table).
 constexpr int GETT_KTAB = 1024;

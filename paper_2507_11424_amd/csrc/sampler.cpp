@@ -347,6 +347,26 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     int *kbuf = o.svd_cutoff > 0 ? reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * std::max(cols - 1, 1))) : nullptr;
     std::vector<uint64_t> hidx(Zw);
     std::vector<int> hflags(Zw);
+    // Per qubit, the outcome whose environment step runs for every sample: the
+    // larger of |A[0]|^2 and |A[1]|^2 (a local guess at the likelier bit; the
+    // other step runs masked for the samples that drew the other bit, so a
+    // better guess only means fewer unmasked tiles, never another result)
+    std::vector<int> favour((size_t)rows * cols, 0);
+    {
+        double *sn = reinterpret_cast<double *>(E.raw((size_t)rows * cols * 16));
+        std::vector<double> hsn((size_t)rows * cols * 2, 0.0);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) {
+                const SiteRef &a = V.at(r, c);
+                if (a.dim(0) != 2) continue;
+                const int64_t half = a.t->numel() / 2;
+                E.norm2(a.t->p, a.t->esz, half, 2, half, sn + 2 * ((size_t)r * cols + c));
+            }
+        TN_HIP(hipMemcpyAsync(hsn.data(), sn, hsn.size() * 8, hipMemcpyDeviceToHost, E.s));
+        E.sync();
+        E.unraw(sn);
+        for (size_t i = 0; i < favour.size(); ++i) favour[i] = hsn[2 * i + 1] > hsn[2 * i] ? 1 : 0;
+    }
     // truncated (zero-padded) boundaries make the fit's QR inputs rank-deficient
     struct HouseholderScope {
         Engine &E;
@@ -401,24 +421,31 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
                         continue;
                     }
-                    // P~(0) = <L_c . site(s=0), R_{c+1}>.  For c >= 1 the traced right
-                    // environment gives P~(0) + P~(1) = |R_c| <L_c, R_c>, so P~(1)
-                    // needs no second projected step; the step with s = 1 is then
-                    // extended only for the samples that drew 1 (the others' tiles
-                    // are skipped).  Site 0 computes both projections.
+                    // P~(f) = <L_c . site(s=f), R_{c+1}> for the favoured bit f.  For
+                    // c >= 1 the traced right environment gives P~(0) + P~(1) =
+                    // |R_c| <L_c, R_c>, so the other P~ needs no second projected
+                    // step; that step is then extended only for the samples that
+                    // drew the other bit (the others' tiles are skipped).  Site 0
+                    // computes both projections.
+                    const int f = favour[(size_t)r * cols + c];
+                    auto rest_step = [&](const Ten &t1, int s) {
+                        return useT[c] ? left_rest_T(E, t1, m[c], s ? T1[c] : T0[c])
+                                       : left_rest(E, t1, m[c], a, Bb.site[c], s);
+                    };
+                    double *ptf = pt + (f ? 2 * Zw : 0), *pto = pt + (f ? 0 : 2 * Zw);
                     Ten t1 = left_t1(E, Lc, m[c], useT[c] != 0);
-                    Ten L0 = useT[c] ? left_rest_T(E, t1, m[c], T0[c]) : left_rest(E, t1, m[c], a, Bb.site[c], 0);
-                    const int64_t per = L0.numel() / Z;
-                    E.dot(L0.p, R[c + 1].p, L0.esz, per, Z, per, pt);
-                    Ten L1;
+                    Ten Lf = rest_step(t1, f);
+                    const int64_t per = Lf.numel() / Z;
+                    E.dot(Lf.p, R[c + 1].p, Lf.esz, per, Z, per, ptf);
+                    Ten Lo;
                     const bool rest = c >= 1;
                     if (rest) {
                         const int64_t perc = Lc.numel() / Z;
                         E.dot(Lc.p, R[c].p, Lc.esz, perc, Z, perc, ptot);
-                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, pt, pt + 2 * Zw, Z, E.s));
+                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, ptf, pto, Z, E.s));
                     } else {
-                        L1 = useT[c] ? left_rest_T(E, t1, m[c], T1[c]) : left_rest(E, t1, m[c], a, Bb.site[c], 1);
-                        E.dot(L1.p, R[c + 1].p, L1.esz, per, Z, per, pt + 2 * Zw);
+                        Lo = rest_step(t1, 1 - f);
+                        E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, pto);
                     }
                     tnk::DrawArgs d{};
                     d.batch = Z;
@@ -437,10 +464,9 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     d.flags = flags;
                     TN_HIP(tnk::launch_draw(d, E.s));
                     if (rest) {
-                        E.set_mask(xs, 'z');
+                        E.set_mask(xs, 'z', f);  // skip the samples that drew f
                         try {
-                            L1 = useT[c] ? left_rest_T(E, t1, m[c], T1[c])
-                                         : left_rest(E, t1, m[c], a, Bb.site[c], 1);
+                            Lo = rest_step(t1, 1 - f);
                         } catch (...) {
                             E.clear_mask();
                             throw;
@@ -449,11 +475,12 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     }
                     E.drop(t1);
                     // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
+                    const Ten &L0 = f ? Lo : Lf, &L1 = f ? Lf : Lo;
                     E.drop(Lc);
                     Lc = E.make(L0.d);
                     TN_HIP(tnk::launch_select2(L0.p, L1.p, L0.esz, per, per, xs, Z, Lc.p, E.s));
-                    E.drop(L0);
-                    E.drop(L1);
+                    E.drop(Lf);
+                    E.drop(Lo);
                     unit(E, Lc, Z);
                 }
                 E.drop(Lc);
