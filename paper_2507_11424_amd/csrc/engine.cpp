@@ -144,7 +144,7 @@ std::string Engine::plan_report(int top) const {
         const Plan *p = v[i];
         if (p->calls == 0) continue;
         const double tf = p->ms > 0 ? p->flops * p->calls / (p->ms * 1e-3) / 1e12 : 0.0;
-        os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << " cfg=" << p->cfg
+        os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << (p->pack ? " packed" : "") << " cfg=" << p->cfg
            << " split=" << p->base.ksplit << (p->tuned ? " tuned" : "") << '\n';
     }
     os << "calls\tfactorisation\n";
@@ -376,7 +376,8 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     g.b_bytes = (uint32_t)wb;
     (void)kml; (void)knl;
     P->kM = kM; P->kN = kN; P->K = K; P->Z = Z;
-    P->pack = (prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B);
+    P->can_pack = (prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B);
+    P->pack = P->can_pack;
     P->bl = bl;
     P->kml = swap ? nl : ml;
     P->knl = swap ? ml : nl;
@@ -386,13 +387,13 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     {
         std::ostringstream d;
         d << A.idx << ',' << B.idx << "->" << C.idx << " M=" << M << " N=" << N << " K=" << K << " batch=" << Z
-          << (swap ? " swapped" : "")
-          << ((prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && pack_pays(A, B) ? " packed" : "");
+          << (swap ? " swapped" : "");
         P->desc = d.str();
     }
     auto tc = tune_cache_.find(P->key);
     if (tc != tune_cache_.end()) {
-        set_split(P.get(), tc->second.first, tc->second.second);
+        P->pack = P->can_pack && tc->second.pack;
+        set_split(P.get(), tc->second.cfg, tc->second.ks);
         P->tuned = true;
     } else {
         int cfg;
@@ -440,40 +441,48 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
     if (!on || cache_path.empty()) return;
     std::ifstream f(cache_path);
     std::string k;
-    int cfg, ks;
-    while (f >> k >> cfg >> ks)
-        if (cfg >= 0 && cfg < tnk::CFG_COUNT && ks >= 1) tune_cache_[k] = {cfg, ks};
+    int cfg, ks, pk;
+    while (f >> k >> cfg >> ks >> pk)
+        if (cfg >= 0 && cfg < tnk::CFG_COUNT && ks >= 1) tune_cache_[k] = {cfg, ks, pk ? 1 : 0};
 }
 
 // Times every candidate (tile configuration x split-K choice) on the call's own
 // operands; only for calls that overwrite C, so repeated launches leave the
 // same result.  The last launch of the caller then runs with the winner.
 void Engine::tune(Plan *P, tnk::GettArgs g) {
-    struct Cand { int cfg, ks; };
+    // candidates: tile configuration x K slices, and for split-BF16 shapes that
+    // may pack, packed or split while staging (the packing is timed with it)
+    struct Cand { int cfg, ks; bool pack; };
     std::vector<Cand> cands;
     const int cfgs[5] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64, tnk::CFG_128x64W, tnk::CFG_128x128W};
-    for (int c : cfgs) {
-        if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W || c == tnk::CFG_128x128W) && P->kM < 128) continue;
-        if (c == tnk::CFG_128x128W && (!P->pack || P->kN < 128)) continue;  // packed split-BF16 only
-        if (c == tnk::CFG_64x16 && P->kN > 64) continue;
-        int bm = 64, bn = 64;
-        tnk::gett_tile(c, prec, &bm, &bn);
-        const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
-        cands.push_back({c, 1});
-        // K slices only pay when the output tiles leave CUs idle
-        if (tiles >= 1024) continue;
-        for (int64_t ks = 2; ks <= 16; ks *= 2) {
-            if (P->K < 64 * ks) break;
-            if (tiles * ks > 4096) break;
-            cands.push_back({c, (int)ks});
+    for (int pk = 0; pk < 2; ++pk) {
+        const bool pack = pk == 1;
+        if (pack && !P->can_pack) continue;
+        for (int c : cfgs) {
+            if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W || c == tnk::CFG_128x128W) && P->kM < 128) continue;
+            if (c == tnk::CFG_128x128W && (!pack || P->kN < 128)) continue;  // packed split-BF16 only
+            if (c == tnk::CFG_64x16 && P->kN > 64) continue;
+            int bm = 64, bn = 64;
+            tnk::gett_tile(c, prec, &bm, &bn);
+            const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
+            cands.push_back({c, 1, pack});
+            // K slices only pay when the output tiles leave CUs idle
+            if (tiles >= 1024) continue;
+            for (int64_t ks = 2; ks <= 16; ks *= 2) {
+                if (P->K < 64 * ks) break;
+                if (tiles * ks > 4096) break;
+                cands.push_back({c, (int)ks, pack});
+            }
         }
     }
     hipEvent_t e0, e1;
     TN_HIP(hipEventCreate(&e0));
     TN_HIP(hipEventCreate(&e1));
     const tnk::GettArgs saved = P->base;
-    const Cand start{P->cfg, std::max(P->base.ksplit, 1)};
+    const bool saved_pack = P->pack;
+    const Cand start{P->cfg, std::max(P->base.ksplit, 1), P->pack};
     auto run = [&](const Cand &c, int reps) {
+        P->pack = c.pack;
         set_split(P, c.cfg, c.ks);
         tnk::GettArgs t = g;
         t.ksplit = P->base.ksplit;
@@ -481,7 +490,14 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
         void *part = t.ksplit > 1 ? pool_.get((size_t)t.ksplit * t.batch * (size_t)t.M * t.N * esz) : nullptr;
         t.part = part;
         TN_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) TN_HIP(tnk::launch_gett(t, prec, c.cfg, s));
+        for (int r = 0; r < reps; ++r) {
+            tnk::GettArgs u = t;
+            void *pa = nullptr, *pb = nullptr;
+            if (c.pack) pack_bf16(u, &pa, &pb);
+            TN_HIP(tnk::launch_gett(u, prec, c.cfg, s));
+            if (pa) pool_.put(pa);
+            if (pb) pool_.put(pb);
+        }
         TN_HIP(hipEventRecord(e1, s));
         TN_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -497,12 +513,13 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
         const int reps = best < 0.05f ? 3 : 1;
         if (reps > 1) best = run(start, reps);
         for (const Cand &c : cands) {
-            if (c.cfg == start.cfg && c.ks == start.ks) continue;
+            if (c.cfg == start.cfg && c.ks == start.ks && c.pack == start.pack) continue;
             const float ms = run(c, reps);
             if (ms < best) { best = ms; win = c; }
         }
     } catch (...) {
         P->base = saved;
+        P->pack = saved_pack;
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         throw;
@@ -510,12 +527,13 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     P->base = saved;
+    P->pack = win.pack;
     set_split(P, win.cfg, win.ks);
     P->tuned = true;
-    tune_cache_[P->key] = {win.cfg, win.ks};
+    tune_cache_[P->key] = {win.cfg, win.ks, win.pack ? 1 : 0};
     if (!tune_path_.empty()) {
         std::ofstream f(tune_path_, std::ios::app);
-        f << P->key << ' ' << win.cfg << ' ' << win.ks << '\n';
+        f << P->key << ' ' << win.cfg << ' ' << win.ks << ' ' << (win.pack ? 1 : 0) << '\n';
     }
 }
 
@@ -657,18 +675,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
         g.kchunk = tmp.base.kchunk;
         cfg = force_cfg;
     } else if (autotune_ && !P->tuned && !accumulate) {
-        void *ta = nullptr, *tb = nullptr;
-        tnk::GettArgs gt = g;
-        if (P->pack) pack_bf16(gt, &ta, &tb);
-        try {
-            tune(P, gt);
-        } catch (...) {
-            if (ta) pool_.put(ta);
-            if (tb) pool_.put(tb);
-            throw;
-        }
-        if (ta) pool_.put(ta);
-        if (tb) pool_.put(tb);
+        tune(P, g);
         g.ksplit = P->base.ksplit;
         g.kchunk = P->base.kchunk;
         cfg = P->cfg;

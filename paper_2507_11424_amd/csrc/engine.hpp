@@ -89,6 +89,7 @@ struct Plan {
     bool tuned = false;   // tile configuration chosen by measurement
     int64_t kM = 0, kN = 0, K = 0, Z = 0;
     bool pack = false;    // split-BF16 on packed operand planes (else split while staging)
+    bool can_pack = false;  // packing is offered (both matrix sides above 128); the tuner decides
     // letters of the batch, kernel-M and kernel-N index spaces, slowest first,
     // and every letter's extent (for masked launches)
     std::string bl, kml, knl;
@@ -199,7 +200,8 @@ class Engine {
     int mask_skip_ = 0;
     bool autotune_ = false;
     std::string tune_path_;
-    std::map<std::string, std::pair<int, int>> tune_cache_;  // key -> (cfg, ksplit)
+    struct TuneChoice { int cfg, ks, pack; };
+    std::map<std::string, TuneChoice> tune_cache_;  // key -> tile configuration, K slices, packing
     std::map<std::string, int64_t> qr_shapes_;               // factorisation calls by shape
     void set_split(Plan *P, int cfg, int ksplit_hint);
     void pack_bf16(tnk::GettArgs &g, void **pa, void **pb);

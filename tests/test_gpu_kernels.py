@@ -148,6 +148,38 @@ def test_autotuned_contract_matches_einsum(tuned_handle, prec, case):
     assert path.exists() and path.read_text().strip()
 
 
+@pytest.mark.parametrize("case", [10, 11, 12])
+def test_autotune_choices_reload(tuned_handle, case):
+    """A fresh handle reading the choices file (tile, K slices, packing) runs
+    the stored choice and still matches einsum."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    h0, path = tuned_handle
+    ia, ib, ic, dims = CASES[case]
+    rng = np.random.default_rng(400 + case)
+    A = _rand(rng, [dims[c] for c in ia]).astype(np.complex64).astype(np.complex128)
+    B = _rand(rng, [dims[c] for c in ib]).astype(np.complex64).astype(np.complex128)
+    ref = np.einsum(f"{ia},{ib}->{ic}", A, B)
+    scale = np.einsum(f"{ia},{ib}->{ic}", np.abs(A), np.abs(B))
+    dA = torch.from_numpy(A).to("cuda", torch.complex64)
+    dB = torch.from_numpy(B).to("cuda", torch.complex64)
+    dC = torch.zeros([dims[c] for c in ic], dtype=torch.complex64, device="cuda")
+    h0.test_contract("bf16x3", ia, dA, ib, dB, ic, dC)  # writes the choice if new
+    torch.cuda.synchronize()
+    lines = path.read_text().split("\n")
+    assert all(len(x.split()) == 4 for x in lines if x.strip())  # key, cfg, ksplit, packing
+    h = tnb.Handle(0)
+    try:
+        h.set_autotune(True, str(path))
+        dC.zero_()
+        h.test_contract("bf16x3", ia, dA, ib, dB, ic, dC)
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    got = dC.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - ref) / np.maximum(scale, 1e-300)) < TOL["bf16x3"]
+
+
 def test_contract_accumulate(handle):
     import torch
     rng = np.random.default_rng(7)
