@@ -30,6 +30,8 @@ namespace tnb {
 
 namespace {
 
+constexpr int ENV_RENORM = 4;  // sites between rescalings of the sampler's environments
+
 // First contraction of a left step, shared by both projections: L . m.
 // Direct route: [z,b,g,h,k,u,A]; transfer-matrix route (u = 1): [z,A,b,g,h,k].
 Ten left_t1(Engine &E, const Ten &L, const Ten &m, bool via_T) {
@@ -400,14 +402,19 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         T1[c] = transfer(E, a, Bb.site[c], 1);
                     }
                 }
-                // R[c] is stored divided by its norm; lnR[c][z] keeps the log of that norm
+                // Environments are rescaled to unit norm every ENV_RENORM sites only
+                // (probabilities are ratios; the stride keeps them far from under-
+                // and overflow).  R[c] is stored divided by exp(lnR[c][z]).
                 std::vector<Ten> R(cols + 1);
                 R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
                 for (int c = cols - 1; c >= 1; --c) {
                     R[c] = useT[c] ? env_right_T(E, R[c + 1], m[c], Ts[c])
                                    : env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
                     const int64_t per = R[c].numel() / Z;
-                    E.normalise(R[c].p, R[c].esz, per, Z, per, lnR + (size_t)c * Zw, false, nullptr);
+                    if ((cols - c) % ENV_RENORM == 0 || c == 1)
+                        E.normalise(R[c].p, R[c].esz, per, Z, per, lnR + (size_t)c * Zw, false, nullptr);
+                    else
+                        TN_HIP(tnk::launch_fill_f64(lnR + (size_t)c * Zw, Z, 0.0, E.s));
                 }
                 Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
                 for (int c = 0; c < cols; ++c) {
@@ -417,7 +424,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left_traced(E, Lc, m[c], a, Bb.site[c]);
                         E.drop(Lc);
                         Lc = L2;
-                        unit(E, Lc, Z);
+                        if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
                         TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
                         continue;
                     }
@@ -481,7 +488,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     TN_HIP(tnk::launch_select2(L0.p, L1.p, L0.esz, per, per, xs, Z, Lc.p, E.s));
                     E.drop(Lf);
                     E.drop(Lo);
-                    unit(E, Lc, Z);
+                    if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
                 }
                 E.drop(Lc);
                 for (auto &x : R)
