@@ -14,6 +14,8 @@
 #include "tn_core.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 
 namespace tnb {
@@ -82,6 +84,13 @@ Op sop_proj(const SiteRef &a, int s, const std::string &L, bool conj) {
 }
 
 // ---------------------------------------------------------------- helpers
+
+// TN_PROGRESS=1 in the environment: long loops wait for each row and report it
+// on stderr (for runs whose single calls take minutes).
+bool progress_enabled() {
+    const char *v = std::getenv("TN_PROGRESS");
+    return v && v[0] == '1';
+}
 
 Ten ones(Engine &E, const std::vector<int> &dims) {
     Ten t = E.make(dims);
@@ -369,8 +378,15 @@ BoundarySet boundary_set(Engine &E, const LView &V, const FitOpts &o, uint64_t t
         const int d = V.at(V.rows - 1, c).dim(3);
         last.site.push_back(ones(E, {1, d, d, 1}));
     }
-    for (int r = V.rows - 1; r >= 1; --r)
+    const bool progress = progress_enabled();
+    for (int r = V.rows - 1; r >= 1; --r) {
         S.below[r - 1] = fit_double(E, S.below[r], V, r, o, tag, S.logs + (r - 1), &S.mode[r - 1]);
+        if (progress) {
+            E.sync();
+            std::fprintf(stderr, "tn: boundary below row %d done\n", r - 1);
+            std::fflush(stderr);
+        }
+    }
     return S;
 }
 

@@ -605,6 +605,38 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     // slices that fit (a summed letter accumulates over its slices).
     const bool bf16 = prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6;
     const int64_t lim = (int64_t)tnk::GETT_MAX_WINDOW;
+    // The output's row and column offsets are int32 tables: an output spanning
+    // 2^31 elements or more (outside its batch letters) is cut along its
+    // widest-stride letter into equal slices that fit.
+    {
+        const int64_t winc = op_window(C, A, B) / C.esz;  // elements reachable through the tables
+        if (winc > (int64_t)INT32_MAX) {
+            int best = -1;
+            int64_t span = 0;
+            for (size_t i = 0; i < C.idx.size(); ++i) {
+                const char c = C.idx[i];
+                if (C.dims[i] < 2) continue;
+                if (A.idx.find(c) != std::string::npos && B.idx.find(c) != std::string::npos) continue;
+                const int64_t sp = (int64_t)(C.dims[i] - 1) * C.str[i];
+                if (sp > span) { span = sp; best = (int)i; }
+            }
+            if (best < 0) throw TnError(ST_UNSUPPORTED, "contraction output cannot be cut below 2^31 elements");
+            const char c = C.idx[best];
+            const int dim = C.dims[best];
+            const int64_t rest = winc - (int64_t)(dim - 1) * C.str[best];
+            int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(dim / 2, ((int64_t)INT32_MAX - rest) / C.str[best] + 1));
+            const int nsl = (dim + chunk - 1) / chunk;
+            chunk = (dim + nsl - 1) / nsl;
+            const int *mask = mask_;
+            for (int i0 = 0; i0 < dim; i0 += chunk) {
+                const int n = std::min(chunk, dim - i0);
+                if (mask && c == mask_letter_) mask_ = mask + i0;
+                contract(slice(A, c, i0, n), slice(B, c, i0, n), slice(C, c, i0, n), accumulate);
+                mask_ = mask;
+            }
+            return;
+        }
+    }
     const int64_t wina = op_window(A, B, C), winb = op_window(B, A, C);
     int64_t wa = wina, wb = winb;
     if (bf16 && pack_pays(A, B)) {
@@ -746,6 +778,12 @@ Ten Engine::contract_new(const Op &A, const Op &B, const std::string &ic) {
 }
 
 void Engine::qr(const tnk::QrArgs &a) {
+    if (a.n > 64 && a.m >= a.n && (int64_t)a.m * a.n > 8192) {
+        // one workgroup per matrix would factor it alone: blocks of 64 columns,
+        // block Gram-Schmidt between them and Householder TSQR within
+        ortho_impl(a, true);
+        return;
+    }
     const size_t ws = tnk::qr_workspace_bytes(a.m, a.n, a.batch);
     void *w = pool_.get(ws);
     {
@@ -753,11 +791,12 @@ void Engine::qr(const tnk::QrArgs &a) {
         k << "householder m=" << a.m << " n=" << a.n << " batch=" << a.batch << (a.R ? " R" : "");
         qr_shapes_[k.str()] += 1;
     }
-    const size_t ev = timing ? next_pair(1) : NOEV;
+    // inside a wider factorisation the outer call's pair covers this one
+    const size_t ev = (timing && !in_qr_) ? next_pair(1) : NOEV;
     if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].a, s));
     TN_HIP(tnk::launch_qr(a, w, s));
     if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
-    ctr.qr_launches += 1;
+    if (!in_qr_) ctr.qr_launches += 1;
     pool_.put(w);
 }
 
@@ -784,6 +823,14 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
         qr(a);
         return;
     }
+    ortho_impl(a, false);
+}
+
+// CholeskyQR3 (n <= 64) or the blocked scheme (n > 64) behind orthonormalise;
+// with householder_blocks the blocks of the wide case are factored by
+// Householder TSQR (exact for rank-deficient input) instead of CholeskyQR3.
+void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
+    const int m = a.m, n = a.n, Z = a.batch;
     const int saved = prec;
     const bool nested = in_qr_;  // a block of a wider orthonormalisation
     set_prec(tnk::P_FP64);
@@ -877,7 +924,42 @@ void Engine::orthonormalise(const tnk::QrArgs &a) {
                     b.R = static_cast<char *>(R->p) + ((int64_t)j0 * n + j0) * 16;
                     b.r_esz = 16; b.r_bs = (int64_t)n * n; b.r_rs = n; b.r_cs = 1; b.r_conj = 0;
                 }
-                orthonormalise(b);
+                if (householder_blocks) {
+                    qr(b);
+                    if (j0 > 0) {
+                        // Householder completes a rank-deficient block with
+                        // directions built from unit vectors, which the finished
+                        // blocks know nothing about: project them out of Q_j and
+                        // factor it again, Q_j = Q' R2, and fold R2 into R_jj
+                        const Op Qp = view(qp, "bij", {Z, m, j0}, {bs, n, 1});
+                        const Op Qpc = view(qp, "bij", {Z, m, j0}, {bs, n, 1}, true);
+                        const Op Qj = view(qp + (int64_t)j0 * 16, "bik", {Z, m, nb}, {bs, n, 1});
+                        Ten W = make({Z, j0, nb}, 16);
+                        contract(Qpc, Qj, op(W, "bjk"));
+                        TN_HIP(tnk::launch_scale(W.p, W.numel(), -1.0, 0.0, s));
+                        contract(Qp, op(W, "bjk"), Qj, true);
+                        drop(W);
+                        Ten R2 = make({Z, nb, nb}, 16);
+                        tnk::QrArgs c2 = b;
+                        c2.A = qp + (int64_t)j0 * 16;
+                        c2.R = R2.p; c2.r_esz = 16; c2.r_bs = (int64_t)nb * nb; c2.r_rs = nb; c2.r_cs = 1;
+                        c2.r_conj = 0;
+                        qr(c2);  // in place: the factorisation reads A before it writes Q
+                        if (R) {
+                            const Op Rjj = view(static_cast<char *>(R->p) + ((int64_t)j0 * n + j0) * 16, "bjk",
+                                                {Z, nb, nb}, {(int64_t)n * n, n, 1});
+                            Ten T = make({Z, nb, nb}, 16);
+                            contract(op(R2, "bij"), Rjj, op(T, "bik"));
+                            TN_HIP(tnk::launch_strided_copy(T.p, 16, (int64_t)nb * nb, nb, 1,
+                                                            static_cast<char *>(R->p) + ((int64_t)j0 * n + j0) * 16,
+                                                            16, (int64_t)n * n, n, 1, nb, nb, Z, 0, s));
+                            drop(T);
+                        }
+                        drop(R2);
+                    }
+                } else {
+                    orthonormalise(b);
+                }
             }
             TN_HIP(tnk::launch_strided_copy(Q.p, 16, bs, n, 1, a.Q, a.q_esz, a.q_bs, a.q_rs, a.q_cs, m, n, Z, a.q_conj,
                                             s));

@@ -164,6 +164,7 @@ class Engine {
     // columns, each orthogonalised against the previous ones by three passes of
     // block Gram-Schmidt before its CholeskyQR3.
     void orthonormalise(const tnk::QrArgs &a);
+    void ortho_impl(const tnk::QrArgs &a, bool householder_blocks);
     // norm2 per batch item into dev[batch]; normalise in place; logscale +=.
     void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
     void normalise(void *x, int e, int64_t n, int batch, int64_t bs, double *logscale, bool acc,

@@ -21,6 +21,7 @@
 // contracted with the last projected row.  Probabilities are FP64; P(s) =
 // max(Re P~(s), 0) / sum, x = 0 iff u < P(0).
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <vector>
 
@@ -520,6 +521,12 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     last_row_amplitude(E, m, X, mlog, amp, log_p + w0, nullptr);
                 }
                 for (auto &x : X) E.drop(x);
+                if (progress_enabled()) {
+                    E.sync();
+                    std::fprintf(stderr, "tn: samples %lld-%lld row %d done\n", (long long)(first + w0),
+                                 (long long)(first + w0 + Z - 1), r);
+                    std::fflush(stderr);
+                }
             }
             for (auto &x : m) E.drop(x);
             TN_HIP(hipMemcpyAsync(hflags.data(), flags, (size_t)Z * 4, hipMemcpyDeviceToHost, E.s));

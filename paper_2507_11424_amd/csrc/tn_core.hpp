@@ -56,6 +56,8 @@ struct BoundarySet {
 void free_mps(Engine &E, DMps &m);
 Ten ones(Engine &E, const std::vector<int> &dims);
 // QR of T as batch x m x n (first nb dims batch, n = last dim); R optional.
+// TN_PROGRESS=1: long loops synchronise per row and report it on stderr.
+bool progress_enabled();
 void qr_left(Engine &E, const Ten &T, int nb, Ten &Q, Ten *R, bool well_conditioned = false);
 // LQ of T as batch x m x n (m = dim nb, n = the rest); L optional.
 void lq_right(Engine &E, const Ten &T, int nb, Ten &Q, Ten *L, bool well_conditioned = false);

@@ -216,6 +216,32 @@ def test_qr(handle, m, n, batch, esz):
         assert np.abs(np.tril(R[b], -1)).max() == 0.0
 
 
+@pytest.mark.parametrize("m,n,batch", [(16384, 256, 1), (2000, 130, 2)])
+@pytest.mark.parametrize("esz", [16, 8])
+def test_qr_wide_rank_deficient(handle, m, n, batch, esz):
+    """Householder QR wider than one block (blocks of 64 columns, block
+    Gram-Schmidt between them, TSQR within) on matrices of half rank."""
+    import torch
+    rng = np.random.default_rng(m + n)
+    A = _rand(rng, (batch, m, n))
+    A[:, :, n // 2:] = A[:, :, : n - n // 2] @ _rand(rng, (n - n // 2, n - n // 2))  # rank n - n // 2
+    if esz == 8:
+        A = A.astype(np.complex64).astype(np.complex128)
+    td = torch.complex128 if esz == 16 else torch.complex64
+    dA = torch.from_numpy(A).to("cuda", td)
+    dQ = torch.zeros((batch, m, n), dtype=td, device="cuda")
+    dR = torch.zeros((batch, n, n), dtype=td, device="cuda")
+    handle.test_qr(dA, dQ, dR, "householder")
+    torch.cuda.synchronize()
+    Q = dQ.cpu().numpy().astype(np.complex128)
+    R = dR.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if esz == 16 else 2e-6
+    for b in range(batch):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(n)).max() < tol * 64
+        assert np.abs(Q[b] @ R[b] - A[b]).max() < tol * 64 * np.abs(A[b]).max() * np.sqrt(n)
+        assert np.abs(np.tril(R[b], -1)).max() == 0.0
+
+
 @pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (700, 33, 2), (512, 8, 5), (8192, 128, 1),
                                        (300, 200, 2), (1024, 65, 1)])
 @pytest.mark.parametrize("esz", [16, 8])
@@ -439,3 +465,32 @@ def test_masked_contraction(handle, prec, case, cfg, ksplit):
             assert np.all(g == sentinel), z  # skipped: untouched
         else:
             assert np.abs(g - r).max() <= tol  # misaligned: computed
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_contract_output_over_2g_elements(handle, prec):
+    """An output spanning more than 2^31 elements (the outer product that starts
+    the fit's right partial at chi = 256, D = 16) is cut into slices whose
+    row and column offsets fit int32; sampled entries against the product."""
+    import torch
+    rng = np.random.default_rng(77)
+    n = 216  # 216^4 = 2.18e9 elements
+    A = _rand(rng, (n, n))
+    B = _rand(rng, (n, n))
+    td = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec == "fp32":
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+    C = torch.empty((n, n, n, n), dtype=td, device="cuda")
+    handle.test_contract(prec, "ab", torch.from_numpy(A).to("cuda", td), "cd", torch.from_numpy(B).to("cuda", td),
+                         "abcd", C)
+    torch.cuda.synchronize()
+    idx = rng.integers(0, n, size=(20000, 4))
+    idx[:4] = [[0, 0, 0, 0], [n - 1, n - 1, n - 1, n - 1], [n - 1, 0, n - 1, 0], [0, n - 1, 0, n - 1]]
+    t = torch.from_numpy(idx).cuda()
+    got = C[t[:, 0], t[:, 1], t[:, 2], t[:, 3]].cpu().numpy().astype(np.complex128)
+    ref = A[idx[:, 0], idx[:, 1]] * B[idx[:, 2], idx[:, 3]]
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    del C
+    torch.cuda.empty_cache()
