@@ -144,7 +144,8 @@ std::string Engine::plan_report(int top) const {
         const Plan *p = v[i];
         if (p->calls == 0) continue;
         const double tf = p->ms > 0 ? p->flops * p->calls / (p->ms * 1e-3) / 1e12 : 0.0;
-        os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << (p->pack ? " packed" : "") << " cfg=" << p->cfg
+        os << p->ms << '\t' << p->calls << '\t' << tf << '\t' << p->desc << (p->pack ? " packed" : "")
+           << (p->fp32 ? " fp32" : "") << " cfg=" << p->cfg
            << " split=" << p->base.ksplit << (p->tuned ? " tuned" : "") << '\n';
     }
     os << "calls\tfactorisation\n";
@@ -393,6 +394,7 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
     auto tc = tune_cache_.find(P->key);
     if (tc != tune_cache_.end()) {
         P->pack = P->can_pack && tc->second.pack;
+        P->fp32 = (prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6) && tc->second.fp32 && !P->pack;
         set_split(P.get(), tc->second.cfg, tc->second.ks);
         P->tuned = true;
     } else {
@@ -441,9 +443,9 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
     if (!on || cache_path.empty()) return;
     std::ifstream f(cache_path);
     std::string k;
-    int cfg, ks, pk;
-    while (f >> k >> cfg >> ks >> pk)
-        if (cfg >= 0 && cfg < tnk::CFG_COUNT && ks >= 1) tune_cache_[k] = {cfg, ks, pk ? 1 : 0};
+    int cfg, ks, pk, f32;
+    while (f >> k >> cfg >> ks >> pk >> f32)
+        if (cfg >= 0 && cfg < tnk::CFG_COUNT && ks >= 1) tune_cache_[k] = {cfg, ks, pk ? 1 : 0, f32 ? 1 : 0};
 }
 
 // Times every candidate (tile configuration x split-K choice) on the call's own
@@ -452,12 +454,17 @@ void Engine::set_autotune(bool on, const std::string &cache_path) {
 void Engine::tune(Plan *P, tnk::GettArgs g) {
     // candidates: tile configuration x K slices, and for split-BF16 shapes that
     // may pack, packed or split while staging (the packing is timed with it)
-    struct Cand { int cfg, ks; bool pack; };
+    // In the split-BF16 modes the FP32 kernel (same complex64 storage, at least
+    // as accurate) is a candidate too: it can win on shapes whose short K or
+    // narrow N leave the split products little to amortise.
+    struct Cand { int cfg, ks; bool pack, fp32; };
     std::vector<Cand> cands;
+    const bool bf16 = prec == tnk::P_BF16X3 || prec == tnk::P_BF16X6;
     const int cfgs[5] = {tnk::CFG_64x16, tnk::CFG_64x64, tnk::CFG_128x64, tnk::CFG_128x64W, tnk::CFG_128x128W};
-    for (int pk = 0; pk < 2; ++pk) {
-        const bool pack = pk == 1;
+    for (int pk = 0; pk < 3; ++pk) {
+        const bool pack = pk == 1, f32 = pk == 2;
         if (pack && !P->can_pack) continue;
+        if (f32 && !bf16) continue;
         for (int c : cfgs) {
             if ((c == tnk::CFG_128x64 || c == tnk::CFG_128x64W || c == tnk::CFG_128x128W) && P->kM < 128) continue;
             if (c == tnk::CFG_128x128W && (!pack || P->kN < 128)) continue;  // packed split-BF16 only
@@ -465,13 +472,13 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
             int bm = 64, bn = 64;
             tnk::gett_tile(c, prec, &bm, &bn);
             const int64_t tiles = ((P->kM + bm - 1) / bm) * ((P->kN + bn - 1) / bn) * P->Z;
-            cands.push_back({c, 1, pack});
+            cands.push_back({c, 1, pack, f32});
             // K slices only pay when the output tiles leave CUs idle
             if (tiles >= 1024) continue;
             for (int64_t ks = 2; ks <= 16; ks *= 2) {
                 if (P->K < 64 * ks) break;
                 if (tiles * ks > 4096) break;
-                cands.push_back({c, (int)ks, pack});
+                cands.push_back({c, (int)ks, pack, f32});
             }
         }
     }
@@ -479,10 +486,11 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
     TN_HIP(hipEventCreate(&e0));
     TN_HIP(hipEventCreate(&e1));
     const tnk::GettArgs saved = P->base;
-    const bool saved_pack = P->pack;
-    const Cand start{P->cfg, std::max(P->base.ksplit, 1), P->pack};
+    const bool saved_pack = P->pack, saved_fp32 = P->fp32;
+    const Cand start{P->cfg, std::max(P->base.ksplit, 1), P->pack, P->fp32};
     auto run = [&](const Cand &c, int reps) {
         P->pack = c.pack;
+        P->fp32 = c.fp32;
         set_split(P, c.cfg, c.ks);
         tnk::GettArgs t = g;
         t.ksplit = P->base.ksplit;
@@ -494,7 +502,7 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
             tnk::GettArgs u = t;
             void *pa = nullptr, *pb = nullptr;
             if (c.pack) pack_bf16(u, &pa, &pb);
-            TN_HIP(tnk::launch_gett(u, prec, c.cfg, s));
+            TN_HIP(tnk::launch_gett(u, c.fp32 ? (int)tnk::P_FP32 : prec, c.cfg, s));
             if (pa) pool_.put(pa);
             if (pb) pool_.put(pb);
         }
@@ -513,13 +521,14 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
         const int reps = best < 0.05f ? 3 : 1;
         if (reps > 1) best = run(start, reps);
         for (const Cand &c : cands) {
-            if (c.cfg == start.cfg && c.ks == start.ks && c.pack == start.pack) continue;
+            if (c.cfg == start.cfg && c.ks == start.ks && c.pack == start.pack && c.fp32 == start.fp32) continue;
             const float ms = run(c, reps);
             if (ms < best) { best = ms; win = c; }
         }
     } catch (...) {
         P->base = saved;
         P->pack = saved_pack;
+        P->fp32 = saved_fp32;
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         throw;
@@ -528,12 +537,14 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
     hipEventDestroy(e1);
     P->base = saved;
     P->pack = win.pack;
+    P->fp32 = win.fp32;
     set_split(P, win.cfg, win.ks);
     P->tuned = true;
-    tune_cache_[P->key] = {win.cfg, win.ks, win.pack ? 1 : 0};
+    tune_cache_[P->key] = {win.cfg, win.ks, win.pack ? 1 : 0, win.fp32 ? 1 : 0};
     if (!tune_path_.empty()) {
         std::ofstream f(tune_path_, std::ios::app);
-        f << P->key << ' ' << win.cfg << ' ' << win.ks << ' ' << (win.pack ? 1 : 0) << '\n';
+        f << P->key << ' ' << win.cfg << ' ' << win.ks << ' ' << (win.pack ? 1 : 0) << ' ' << (win.fp32 ? 1 : 0)
+          << '\n';
     }
 }
 
@@ -747,7 +758,7 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     }
     void *pka = nullptr, *pkb = nullptr;
     if (P->pack) pack_bf16(g, &pka, &pkb);
-    TN_HIP(tnk::launch_gett(g, prec, cfg, s));
+    TN_HIP(tnk::launch_gett(g, P->fp32 ? (int)tnk::P_FP32 : prec, cfg, s));
     if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
     if (part) pool_.put(part);
     if (pka) pool_.put(pka);

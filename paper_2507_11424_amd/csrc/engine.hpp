@@ -90,6 +90,7 @@ struct Plan {
     int64_t kM = 0, kN = 0, K = 0, Z = 0;
     bool pack = false;    // split-BF16 on packed operand planes (else split while staging)
     bool can_pack = false;  // packing is offered (both matrix sides above 128); the tuner decides
+    bool fp32 = false;      // split-BF16 modes: this shape runs on the FP32 kernel (chosen by the tuner)
     // letters of the batch, kernel-M and kernel-N index spaces, slowest first,
     // and every letter's extent (for masked launches)
     std::string bl, kml, knl;
@@ -201,7 +202,7 @@ class Engine {
     int mask_skip_ = 0;
     bool autotune_ = false;
     std::string tune_path_;
-    struct TuneChoice { int cfg, ks, pack; };
+    struct TuneChoice { int cfg, ks, pack, fp32; };
     std::map<std::string, TuneChoice> tune_cache_;  // key -> tile configuration, K slices, packing
     std::map<std::string, int64_t> qr_shapes_;               // factorisation calls by shape
     void set_split(Plan *P, int cfg, int ksplit_hint);

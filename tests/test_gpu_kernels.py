@@ -150,8 +150,8 @@ def test_autotuned_contract_matches_einsum(tuned_handle, prec, case):
 
 @pytest.mark.parametrize("case", [10, 11, 12])
 def test_autotune_choices_reload(tuned_handle, case):
-    """A fresh handle reading the choices file (tile, K slices, packing) runs
-    the stored choice and still matches einsum."""
+    """A fresh handle reading the choices file (tile, K slices, packing, FP32
+    kernel) runs the stored choice and still matches einsum."""
     import torch
     import paper_2507_11424_amd as tnb
     h0, path = tuned_handle
@@ -167,7 +167,7 @@ def test_autotune_choices_reload(tuned_handle, case):
     h0.test_contract("bf16x3", ia, dA, ib, dB, ic, dC)  # writes the choice if new
     torch.cuda.synchronize()
     lines = path.read_text().split("\n")
-    assert all(len(x.split()) == 4 for x in lines if x.strip())  # key, cfg, ksplit, packing
+    assert all(len(x.split()) == 5 for x in lines if x.strip())  # key, cfg, ksplit, packing, fp32
     h = tnb.Handle(0)
     try:
         h.set_autotune(True, str(path))
