@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--plan-report", default="", help="write the per-shape contraction timing table here")
     ap.add_argument("--no-timing", action="store_true",
                     help="no HIP events around the launches (for counter runs; roofline.achieved is then null)")
+    ap.add_argument("--compare", default="bf16x3", choices=["none"] + list(PEAK_TFLOPS),
+                    help="with --prec fp64: also time this mode on the same workload and samples and report "
+                         "its rate and its agreement with fp64 under 'compare'")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -166,6 +169,44 @@ def cpu_baseline(lat, T, chi, chi_x, contraction_flops):
                 contraction_tflops=contraction_flops / per_norm / 1e12 if per_norm > 0 else None)
 
 
+def compare_mode(a, h, lat, T, chi, chi_x, cutoff, chi_x_min, step, last, lz_ref):
+    """The same step in another precision mode (one warmup step, one timed step)
+    on the same samples (same seed and indices): its rate, its boundary
+    contraction rate, and how far its log|Z|, log q and log p lie from the FP64
+    run's on the samples that drew the same bits."""
+    import torch
+    import paper_2507_11424_amd as tnb
+
+    ref_bits, ref_lq, ref_lp = (x.clone() for x in last["res"][:3])
+    P2 = tnb.Peps.from_numpy(lat, T, dtype="c128" if a.compare == "fp64" else "c64", device="cuda:0")
+    o2 = tnb.make_opts(chi=chi, chi_x=chi_x, prec=a.compare, svd_cutoff=cutoff, chi_x_min=chi_x_min)
+    tw = time.perf_counter()
+    step(P=P2, o=o2)
+    print(f"{a.compare} warmup step done in {time.perf_counter() - tw:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lz, rec = step(timing=not a.no_timing, P=P2, o=o2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"{a.compare} timed step done ({dt:.1f} s)", file=sys.stderr, flush=True)
+    con_t, con_c = rec["contract"]
+    con_f = con_c["gemm_flops"] - con_c["qr_gemm_flops"]
+    bits, lq, lp = last["res"][:3]
+    same = (bits == ref_bits).all(dim=1)
+    n_same = int(same.sum())
+    dq = (lq - ref_lq)[same].abs()
+    dp = (lp - ref_lp)[same].abs()
+    return {"prec": a.compare, "dtype": DTYPE[a.compare], "value": a.samples / dt, "unit": "samples/s",
+            "ms_per_step": 1e3 * dt, "contraction_tflops": con_f / con_t / 1e12 if con_t > 0 else None,
+            "speedup_vs_fp64": None,
+            "log_abs_Z_minus_fp64": lz - lz_ref,
+            "same_bitstrings": n_same, "samples": int(bits.shape[0]),
+            "max_abs_dlog_q": float(dq.max()) if n_same else None,
+            "max_abs_dlog_p": float(dp.max()) if n_same else None,
+            "note": "one warmup and one timed step after the fp64 steps, same seed and sample indices; "
+                    "log q and log p differences over the samples that drew the same bits"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -197,7 +238,9 @@ def main():
 
     phases = ("contract", "environments", "sample")
 
-    def step(timing=False):
+    last = {}
+
+    def step(timing=False, P=P, o=o):
         """One pass of the hot path; returns log|Z| and per-phase (seconds, counters)."""
         h.set_timing(timing)
         rec = {}
@@ -218,6 +261,7 @@ def main():
         if cutoff > 0:
             used.append(res[3][:, 1:].float())
         rec["sample"] = (time.perf_counter() - t0, h.counters())
+        last["res"] = res
         return lz, rec
 
     for i in range(a.warmup):
@@ -306,8 +350,9 @@ def main():
                      "qr_ms_per_step": qr_ms,
                      "masked_launches_per_step": masked,
                      "masked_ms_per_step": masked_ms,
-                     "masked_note": "launches that extend the s = 1 environment only for the samples that "
-                                    "drew 1 (other tiles skipped); excluded from achieved, flops and launches"},
+                     "masked_note": "launches that extend a qubit's environment by its less likely bit only for "
+                                    "the samples that drew that bit (other tiles skipped); excluded from "
+                                    "achieved, flops and launches"},
     }
     if cutoff > 0:
         cu = torch.cat(used)
@@ -315,6 +360,9 @@ def main():
         out["config"]["chi_x_min"] = chi_x_min
         out["chi_x_used"] = {"mean": float(cu.mean()), "min": int(cu.min()), "max": int(cu.max()),
                              "note": "largest kept bond per row of each sample's amplitude boundary"}
+    if a.prec == "fp64" and a.compare != "none" and a.compare != a.prec:
+        out["compare"] = compare_mode(a, h, lat, T, chi, chi_x, cutoff, chi_x_min, step, last, lz)
+        out["compare"]["speedup_vs_fp64"] = out["compare"]["value"] / out["value"]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, T, chi, chi_x, con_f / a.steps)
     print(json.dumps(out))
