@@ -271,12 +271,14 @@ static Ten left_partial(Engine &E, const Ten &Le, const Ten &B, const SiteRef &a
     return t3;
 }
 
-// t[g,h,k,u,v,Y] = sum B[g,d,e,G] A[s,u,h,d,H] conj(A)[s,v,k,e,K] R[Y,G,H,K]
+// t[g,Y,u,h,v,k] = sum B[g,d,e,G] A[s,u,h,d,H] conj(A)[s,v,k,e,K] R[Y,G,H,K]
+// (the letters of t2 keep their order in t, h innermost, as in t2, so that the
+// last product streams t2 along its contiguous letter)
 static Ten right_partial(Engine &E, const Ten &Re, const Ten &B, const SiteRef &a) {
     Ten t1 = E.contract_new(op(B, "gdeG"), op(Re, "YGHK"), "gdeYHK");
     Ten t2 = E.contract_new(op(t1, "gdeYHK"), sop(a, "suhdH"), "geYKsuh");
     E.drop(t1);
-    Ten t3 = E.contract_new(op(t2, "geYKsuh"), sop(a, "svkeK", true), "ghkuvY");
+    Ten t3 = E.contract_new(op(t2, "geYKsuh"), sop(a, "svkeK", true), "gYuhvk");
     E.drop(t2);
     return t3;
 }
@@ -322,7 +324,7 @@ static DMps fit_double(Engine &E, const DMps &Bin, const LView &V, int r, const 
     Le[0] = ones(E, {1, 1, 1, 1});
     for (int c = L - 1; c >= 1; --c) {
         Ten tR = right_partial(E, Re[c + 1], Bin.site[c], V.at(r, c));
-        Re[c] = E.contract_new(op(Y.site[c], "yuvY", true), op(tR, "ghkuvY"), "yghk");
+        Re[c] = E.contract_new(op(Y.site[c], "yuvY", true), op(tR, "gYuhvk"), "yghk");
         E.drop(tR);
     }
     for (int sw = 0; sw < o.sweeps; ++sw) {
@@ -340,20 +342,20 @@ static DMps fit_double(Engine &E, const DMps &Bin, const LView &V, int r, const 
         }
         for (int c = L - 1; c >= 1; --c) {
             Ten tR = right_partial(E, Re[c + 1], Bin.site[c], V.at(r, c));
-            Ten N = E.contract_new(op(Le[c], "yghk"), op(tR, "ghkuvY"), "yuvY");
+            Ten N = E.contract_new(op(Le[c], "yghk"), op(tR, "gYuhvk"), "yuvY");
             Ten Q;
             lq_right(E, N, 0, Q, nullptr);
             E.drop(N);
             E.drop(Y.site[c]);
             Y.site[c] = Q;
             if (Re[c].p) E.drop(Re[c]);
-            Re[c] = E.contract_new(op(Y.site[c], "yuvY", true), op(tR, "ghkuvY"), "yghk");
+            Re[c] = E.contract_new(op(Y.site[c], "yuvY", true), op(tR, "gYuhvk"), "yghk");
             E.drop(tR);
         }
     }
     {
         Ten tR = right_partial(E, Re[1], Bin.site[0], V.at(r, 0));
-        Ten N = E.contract_new(op(Le[0], "yghk"), op(tR, "ghkuvY"), "yuvY");
+        Ten N = E.contract_new(op(Le[0], "yghk"), op(tR, "gYuhvk"), "yuvY");
         E.drop(tR);
         E.drop(Y.site[0]);
         Y.site[0] = N;
