@@ -184,6 +184,9 @@ def test_environments_exact(name):
                 q2 = lat.site_index[r + 1, c]
                 zz = np.sum(P * (1 - 2 * idx[q]) * (1 - 2 * idx[q2]))
                 assert abs(zz - env["zz_v"][r, c]) < 1e-12
+                # (s, t) = (upper, lower) qubit: a swapped order leaves zz unchanged but not p2
+                p2 = [np.sum(P * (idx[q] == s) * (idx[q2] == t)) for s in (0, 1) for t in (0, 1)]
+                assert np.abs(np.array(p2) - env["p2_v"][r, c]).max() < 1e-12
 
 
 @pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1", "rotsq10D2"])
