@@ -30,6 +30,13 @@
  *  - Errors are returned as tn_status; no exception crosses the ABI.  On error
  *    the outputs are unspecified and tn_last_error() describes the failure.
  *  - One handle must not be used by two threads at once.
+ *  - The cached norm boundary set: tn_boundary_contract (direction 0) always
+ *    recomputes it; tn_environments and tn_sample reuse it only when the
+ *    lattice, the options chi, sweeps, init, prec and init_seed, the site
+ *    pointers and a 64-bit fingerprint of the site tensors' bytes (computed on
+ *    the device at every call) all equal those of the call that computed it,
+ *    and recompute it otherwise.  A state overwritten in place, or a new state
+ *    placed at an old one's addresses, therefore gets a fresh set.
  *
  * Site tensor layout: complex, interleaved (re, im), row-major with index order
  * [p][u][l][d][r] (physical, up, left, down, right).  A bond that is absent or
@@ -148,7 +155,7 @@ tn_status tn_environments(tn_handle *h, const tn_peps *peps, const tn_opts *opts
  *              amplitude boundary that conditions each row (1 for the first
  *              row; with svd_cutoff > 0 it varies per sample).
  * Computes (and caches) the norm boundary set if the cached one does not match
- * the state and options.  A sample is a function of (state, options, seed,
+ * the state and options (rule at the top of this file).  A sample is a function of (state, options, seed,
  * sample index) only, so split runs reproduce one run.
  * Synchronises the stream (marginal checks). */
 tn_status tn_sample(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
@@ -268,6 +275,15 @@ tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cuto
  *   column indices and its blocks align with the tiles, else everything is
  *   computed. */
 tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter);
+/* tn_test_sample_config: later tn_sample calls on this handle run waves of
+ *   `wave` samples (0 = sized from free device memory), stop after the first
+ *   `rows_limit` rows (0 = all; bits of later rows are 0, log_q is the partial
+ *   sum, log_p is NaN), and, if log_cond is not NULL, write into it (device
+ *   [n][N] doubles, same indexing as bits) log P(x_q | earlier qubits) for
+ *   every drawn qubit q (entries of undrawn qubits are left as they were).
+ *   Calling it with (0, 0, NULL) restores the defaults.  Errors:
+ *   TN_ERR_INVALID for a NULL handle or negative wave / rows_limit. */
+tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond);
 
 #ifdef __cplusplus
 }

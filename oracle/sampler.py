@@ -220,14 +220,20 @@ def _unit(x):
 
 def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: int,
                sample: int, uniforms=None, forced_bits=None, force_fit: bool = False,
-               svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None):
+               svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None, rows_limit=None,
+               log_cond=None):
     """One sample. ``uniforms[q]`` is the uniform for qubit q; ``forced_bits``
     (optional) replaces the draw by a given bitstring (for enumerating q(x)).
     ``svd_cutoff`` > 0 adds the SVD truncation after every fit; ``chi_used``
     (optional, length rows) receives the largest kept bond of the amplitude
-    boundary that conditions each row (1 for the first row).
+    boundary that conditions each row (1 for the first row).  ``rows_limit``
+    (optional) stops after that many rows (bits of later rows stay 0, log q is
+    the partial sum, log p is NaN); ``log_cond`` (optional, length N) receives
+    log P(x_q | earlier qubits) of every drawn qubit q.
     Returns (bits, log_q, log_p_from_final_m)."""
     rows, cols = len(tensors), len(tensors[0])
+    if rows_limit is not None:
+        rows = min(rows, int(rows_limit))
     n_q = int(np.max(site_index)) + 1
     bits = np.zeros(n_q, dtype=np.uint8)
     logq = 0.0
@@ -266,10 +272,14 @@ def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: i
                 x = 0 if uniforms[q] < P0 else 1
             px = P0 if x == 0 else p1 / tot
             logq += math.log(px) if px > 0 else -math.inf
+            if log_cond is not None:
+                log_cond[q] = math.log(px) if px > 0 else -math.inf
             bits[q] = x
             xs.append(x)
             Lenv = _unit(Ls[x])
         X = [row[c][xs[c]] for c in range(cols)]  # [u,h,d,H]
+        if rows < len(tensors) and r == rows - 1:
+            break  # stopped early: no fit for rows that are not sampled
         if r < rows - 1:
             m, lg = fit_single(m, X, chi_x, sweeps, init_seed, r, sample, force_fit)
             mlog += lg
@@ -291,11 +301,11 @@ def sample_one(tensors, site_index, below, chi_x: int, sweeps: int, init_seed: i
 
 def sample(tensors, site_index, chi: int, chi_x: int, n: int, seed: int, first: int = 0,
            sweeps: int = 2, init_seed: int = 0, uniforms=None, below=None, force_fit=False,
-           svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None):
+           svd_cutoff: float = 0.0, chi_x_min: int = 1, chi_used=None, rows_limit=None, log_cond=None):
     """n samples (indices first..first+n-1). ``uniforms`` [n][N] overrides the
     Philox draws; ``chi_used`` (optional int array [n][rows]) receives the
-    per-row bonds (see sample_one). Returns (bits [n][N] uint8, log_q [n],
-    log_p [n])."""
+    per-row bonds; ``rows_limit`` and ``log_cond`` (optional [n][N]) as in
+    sample_one. Returns (bits [n][N] uint8, log_q [n], log_p [n])."""
     if below is None:
         below, _, _ = boundary_set(tensors, chi, sweeps, init_seed, TAG_INIT_DOWN, force_fit)
     n_q = int(np.max(site_index)) + 1
@@ -308,6 +318,7 @@ def sample(tensors, site_index, chi: int, chi_x: int, n: int, seed: int, first: 
         b, q, p = sample_one(tensors, site_index, below, chi_x, sweeps, init_seed, first + i,
                              uniforms[i], force_fit=force_fit, svd_cutoff=svd_cutoff,
                              chi_x_min=chi_x_min,
-                             chi_used=None if chi_used is None else chi_used[i])
+                             chi_used=None if chi_used is None else chi_used[i], rows_limit=rows_limit,
+                             log_cond=None if log_cond is None else log_cond[i])
         bits[i], lq[i], lp[i] = b, q, p
     return bits, lq, lp

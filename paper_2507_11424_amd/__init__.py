@@ -31,7 +31,8 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 # every symbol declared in include/tn.h
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
            "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
-           "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask"]
+           "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask",
+           "tn_test_sample_config"]
 
 
 class TnError(RuntimeError):
@@ -92,9 +93,11 @@ def lib(path: Optional[str] = None):
     L.tn_test_svd.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, ctypes.c_int, vp, vp,
                               ctypes.c_int, vp]
     L.tn_test_set_mask.argtypes = [vp, vp, ctypes.c_char]
+    L.tn_test_sample_config.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
-              "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats"):
+              "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats",
+              "tn_test_sample_config"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -309,6 +312,14 @@ class Handle:
         return buf.value.decode()
 
     # ---------------------------------------------------------------- test hooks
+    def test_sample_config(self, wave: int = 0, rows_limit: int = 0, log_cond=None):
+        """Later samples run in waves of `wave` (0 = automatic), stop after
+        `rows_limit` rows (0 = all) and write log P(x_q | earlier) into
+        log_cond (device float64 [n][N]) if given (see tn_test_sample_config).
+        The tensor must stay alive while the setting is in force."""
+        ptr = ctypes.c_void_p(log_cond.data_ptr()) if log_cond is not None else None
+        self._check(lib().tn_test_sample_config(self.h, int(wave), int(rows_limit), ptr))
+
     def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
                       accumulate=False, cfg: int = -1, ksplit: int = 0, mask=None, mask_letter: str = "z"):
         """C[ic] (+)= A[ia] B[ib] through the contraction engine; with `mask`

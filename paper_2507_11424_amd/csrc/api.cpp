@@ -22,6 +22,9 @@ struct tn_handle {
     BoundarySet cache;
     std::string cache_key;
     PepsDev cache_peps;
+    // sampler test hooks (tn_test_sample_config)
+    int sample_wave = 0, sample_rows_limit = 0;
+    double *sample_log_cond = nullptr;
 };
 
 namespace {
@@ -132,9 +135,49 @@ FitOpts fit_opts(const tn_opts *o) {
     return f;
 }
 
-// Bottom-up boundary set of the state, cached in the handle.
+// 64-bit fingerprint of the bytes of every site tensor (device-side sum of
+// mixed words, read back to the host: synchronises the stream).  Part of the
+// cache key, so a state overwritten in place, or a new state placed at the
+// freed addresses of an old one, is never served the old boundary set.
+uint64_t fingerprint(Engine &E, const tn_peps *p) {
+    const int n = p->rows * p->cols;
+    const int esz = p->dtype == TN_C128 ? 16 : 8;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(E.raw(8));
+    try {
+        TN_HIP(tnk::launch_fill_f64(reinterpret_cast<double *>(acc), 1, 0.0, E.s));
+        tnk::FingerprintSet f{};
+        for (int i = 0; i < n; ++i) {
+            const int r = i / p->cols, c = i % p->cols;
+            const int64_t u = r > 0 ? p->dim_v[(r - 1) * p->cols + c] : 1;
+            const int64_t d = r + 1 < p->rows ? p->dim_v[r * p->cols + c] : 1;
+            const int64_t l = c > 0 ? p->dim_h[r * (p->cols - 1) + c - 1] : 1;
+            const int64_t rr = c + 1 < p->cols ? p->dim_h[r * (p->cols - 1) + c] : 1;
+            f.ptr[f.count] = p->site[i];
+            f.words[f.count] = p->phys[i] * u * l * d * rr * esz / 8;
+            f.salt[f.count] = (uint64_t)i << 40;
+            if (++f.count == tnk::FP_MAX || i + 1 == n) {
+                TN_HIP(tnk::launch_fingerprint(f, acc, E.s));
+                f.count = 0;
+            }
+        }
+        unsigned long long hv = 0;
+        TN_HIP(hipMemcpyAsync(&hv, acc, 8, hipMemcpyDeviceToHost, E.s));
+        E.sync();
+        E.unraw(acc);
+        return hv;
+    } catch (...) {
+        E.unraw(acc);
+        throw;
+    }
+}
+
+// Bottom-up boundary set of the state, cached in the handle.  The key holds the
+// lattice, the options that shape the set, the site pointers and the content
+// fingerprint of the site tensors.
 const BoundarySet &cached_set(tn_handle *h, const tn_peps *p, const tn_opts *o, bool recompute) {
-    const std::string key = peps_key(p, o);
+    std::string key = peps_key(p, o);
+    const uint64_t fp = fingerprint(*h->E, p);
+    key.append(reinterpret_cast<const char *>(&fp), 8);
     if (!recompute && key == h->cache_key && !h->cache.below.empty()) return h->cache;
     free_set(*h->E, h->cache);
     unstage(*h->E, h->cache_peps);
@@ -269,6 +312,9 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
         so.seed = seed;
         so.svd_cutoff = o->svd_cutoff;
         so.chi_x_min = o->chi_x_min;
+        so.wave = h->sample_wave;
+        so.rows_limit = h->sample_rows_limit;
+        so.log_cond = h->sample_log_cond;
         if (so.svd_cutoff > 0 && o->chi_x > tnk::SVD_NMAX)
             throw TnError(ST_UNSUPPORTED, "svd_cutoff needs chi_x <= " + std::to_string(tnk::SVD_NMAX));
         sample(*h->E, h->cache_peps, S, so, first, n, uniforms, bits, log_q, log_p, chi_x_used);
@@ -447,6 +493,18 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
     } catch (const TnError &e) {
         return fail(h, e);
     }
+}
+
+tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond) {
+    if (!h || !h->E) return TN_ERR_INVALID;
+    if (wave < 0 || rows_limit < 0) {
+        h->err = "tn_test_sample_config: wave and rows_limit must be >= 0";
+        return TN_ERR_INVALID;
+    }
+    h->sample_wave = wave;
+    h->sample_rows_limit = rows_limit;
+    h->sample_log_cond = log_cond;
+    return TN_OK;
 }
 
 tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter) {

@@ -374,7 +374,7 @@ BoundarySet boundary_set(Engine &E, const LView &V, const FitOpts &o, uint64_t t
     S.below.resize(V.rows);
     S.mode.assign(V.rows, 0);
     S.logs = reinterpret_cast<double *>(E.raw((size_t)V.rows * 8));
-    TN_HIP(hipMemsetAsync(S.logs, 0, (size_t)V.rows * 8, E.s));
+    TN_HIP(tnk::launch_fill_f64(S.logs, V.rows, 0.0, E.s));
     DMps &last = S.below[V.rows - 1];
     for (int c = 0; c < V.cols; ++c) {
         const int d = V.at(V.rows - 1, c).dim(3);
@@ -395,7 +395,7 @@ BoundarySet boundary_set(Engine &E, const LView &V, const FitOpts &o, uint64_t t
 void norm_close(Engine &E, const LView &V, const BoundarySet &B, double *logabs, double *arg) {
     Ten Le = ones(E, {1, 1, 1, 1});
     double *lg = reinterpret_cast<double *>(E.raw(8));
-    TN_HIP(hipMemsetAsync(lg, 0, 8, E.s));
+    TN_HIP(tnk::launch_fill_f64(lg, 1, 0.0, E.s));
     for (int c = 0; c < V.cols; ++c) {
         Ten t3 = left_partial(E, Le, B.below[0].site[c], V.at(0, c));  // [y,G,u,H,v,K], y=u=v=1
         E.drop(Le);

@@ -1003,10 +1003,11 @@ void Engine::normalise(void *x, int e, int64_t n, int batch, int64_t bs, double 
     pool_.put(q);
 }
 
-void Engine::dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out) {
+void Engine::dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out,
+                 const int *mask, int mask_skip) {
     const int P = tnk::reduce_partial_count(n);
     void *w = pool_.get((size_t)P * batch * 16);
-    TN_HIP(tnk::launch_dot(x, y, e, n, batch, bs, reinterpret_cast<double *>(w), out, s));
+    TN_HIP(tnk::launch_dot(x, y, e, n, batch, bs, reinterpret_cast<double *>(w), out, s, mask, mask_skip));
     pool_.put(w);
 }
 

@@ -170,7 +170,8 @@ class Engine {
     void norm2(const void *x, int e, int64_t n, int batch, int64_t bs, double *out);
     void normalise(void *x, int e, int64_t n, int batch, int64_t bs, double *logscale, bool acc,
                    int *flags);
-    void dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out);
+    void dot(const void *x, const void *y, int e, int64_t n, int batch, int64_t bs, double *out,
+             const int *mask = nullptr, int mask_skip = 0);
 
     // Raw device memory from the pool (stream-ordered reuse after unraw).
     void *raw(size_t bytes) { return pool_.get(bytes); }

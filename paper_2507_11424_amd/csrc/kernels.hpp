@@ -138,8 +138,9 @@ hipError_t launch_eye(void *x, int esz, int n, int batch, hipStream_t s);
 // Fill with a complex constant.
 hipError_t launch_fill(void *x, int esz, int64_t n, double re, double im, hipStream_t s);
 // out[b] = sum_i x[b][i] * y[b][i] (no conjugation), complex FP64 result (2 doubles).
+// With a mask, items b with mask[b] == mask_skip are skipped (out[b] untouched).
 hipError_t launch_dot(const void *x, const void *y, int esz, int64_t n, int batch, int64_t bs,
-                      double *partial, double *out, hipStream_t s);
+                      double *partial, double *out, hipStream_t s, const int *mask = nullptr, int mask_skip = 0);
 
 // ---------------------------------------------------------------- sampler
 struct DrawArgs {
@@ -153,6 +154,7 @@ struct DrawArgs {
     double *log_q;             // [batch]
     int *xsel;                 // [batch] out: drawn bit
     int *flags;                // [batch] |= 2 on a bad marginal
+    double *log_cond;          // optional [n_total][n_qubits]: log P(x_q | earlier qubits)
 };
 hipError_t launch_draw(const DrawArgs &a, hipStream_t s);
 // Gathers per-sample pointers: dst[b] = base_off + xsel[b] * stride.
@@ -166,15 +168,26 @@ hipError_t launch_select2(const void *x0, const void *x1, int esz, int64_t n, in
                           int batch, void *out, hipStream_t s);
 // Fill n doubles with v.
 hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t s);
+// Fill n ints with v.
+hipError_t launch_fill_i32(int *x, int64_t n, int v, hipStream_t s);
 // dots [4][2] = complex rho~[s][t] (order 00, 01, 10, 11) -> out[8] = rho / Tr rho.
 hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s);
 // dots [4][2] = complex P~(s, t) -> p2[4] = Re P / sum Re P (if p2), zz = sum (-1)^(s+t) Re P / sum Re P.
 hipError_t launch_env_p2(const double *dots, double *p2, double *zz, hipStream_t s);
 // pt1[z] = exp(lnr[z]) tot[z] - pt0[z] (complex, [batch][2] doubles): the other
 // projection's P~ from the traced total, whose right environment is stored
-// divided by exp(lnr).
+// divided by exp(lnr).  need[z] = 1 unless Re pt1[z] > thr * Re(exp(lnr) tot):
+// a difference that small is left to a direct contraction.
 hipError_t launch_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch,
-                                hipStream_t s);
+                                double thr, int *need, hipStream_t s);
+// out[z] = (xs[z] == other && !need[z]).
+hipError_t launch_other_mask(const int *xs, const int *need, int other, int batch, int *out, hipStream_t s);
+// For samples with xs[z] == other: log_q[z] += log(pd/(pf+pd)) - log(pu/(pf+pu)),
+// pf = max(Re pt_f, 0), pu = max(Re pt_used, 0), pd = Re pt_direct (flags |= 2
+// if pd is not positive and finite); log_cond (optional) gets log(pd/(pf+pd)).
+hipError_t launch_fix_other(const double *pt_f, const double *pt_used, const double *pt_direct, const int *xs,
+                            int other, int batch, double *log_q, double *log_cond, int64_t row0, int n_qubits,
+                            int qubit, int *flags, hipStream_t s);
 // Final amplitude -> log p.
 // xs[z] = bits[(row0 + z) * n_qubits + qubit] (0/1) for z < batch.
 hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs,
@@ -187,6 +200,17 @@ hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t
 // k is null or cuts == 0.
 hipError_t launch_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride,
                            hipStream_t s);
+// Content fingerprint of up to FP_MAX tensors: *acc += sum over tensors t and
+// 8-byte words i of mix(word, salt[t] + i) (modulo 2^64; acc must be cleared by
+// the caller).  A changed byte changes the sum except with probability ~2^-64.
+constexpr int FP_MAX = 96;
+struct FingerprintSet {
+    int count;
+    const void *ptr[FP_MAX];
+    int64_t words[FP_MAX];
+    uint64_t salt[FP_MAX];
+};
+hipError_t launch_fingerprint(const FingerprintSet &f, unsigned long long *acc, hipStream_t s);
 hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
                        hipStream_t s);
 

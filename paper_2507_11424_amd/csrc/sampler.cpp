@@ -343,6 +343,11 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     double *mlog = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
     double *pt = reinterpret_cast<double *>(E.raw((size_t)Zw * 32));
     double *ptot = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    double *ptd = reinterpret_cast<double *>(E.raw((size_t)Zw * 16));
+    int *need = reinterpret_cast<int *>(E.raw((size_t)Zw * 4));
+    // below this fraction of the traced total, the other bit's P~ taken as a
+    // difference is not trusted: a few hundred unit roundoffs of the GEMM mode
+    const double diff_thr = E.prec == tnk::P_FP64 ? 1e-12 : (E.prec == tnk::P_BF16X3 ? 1e-2 : 1e-4);
     double *lnR = reinterpret_cast<double *>(E.raw((size_t)Zw * 8 * (cols + 1)));
     int *flags = reinterpret_cast<int *>(E.raw((size_t)Zw * 4));
     int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
@@ -353,7 +358,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     // Per qubit, the outcome whose environment step runs for every sample: the
     // larger of |A[0]|^2 and |A[1]|^2 (a local guess at the likelier bit; the
     // other step runs masked for the samples that drew the other bit, so a
-    // better guess only means fewer unmasked tiles, never another result)
+    // better guess means fewer unmasked tiles; results differ only in rounding)
     std::vector<int> favour((size_t)rows * cols, 0);
     {
         double *sn = reinterpret_cast<double *>(E.raw((size_t)rows * cols * 16));
@@ -382,13 +387,15 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
             const int Z = (int)std::min<int64_t>(Zw, n - w0);
             for (int z = 0; z < Z; ++z) hidx[z] = first + (uint64_t)(w0 + z);
             TN_HIP(hipMemcpyAsync(sidx, hidx.data(), (size_t)Z * 8, hipMemcpyHostToDevice, E.s));
-            TN_HIP(hipMemsetAsync(mlog, 0, (size_t)Z * 8, E.s));
-            TN_HIP(hipMemsetAsync(flags, 0, (size_t)Z * 4, E.s));
-            TN_HIP(hipMemsetAsync(log_q + w0, 0, (size_t)Z * 8, E.s));
+            TN_HIP(tnk::launch_fill_f64(mlog, Z, 0.0, E.s));
+            TN_HIP(tnk::launch_fill_i32(flags, Z, 0, E.s));
+            TN_HIP(tnk::launch_fill_f64(log_q + w0, Z, 0.0, E.s));
             std::vector<Ten> m(cols);
             for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
             if (chi_used) TN_HIP(tnk::launch_chi_used(nullptr, 0, Z, 1, chi_used + w0 * rows, rows, E.s));
-            for (int r = 0; r < rows; ++r) {
+            const int rows_run = o.rows_limit > 0 ? std::min(rows, o.rows_limit) : rows;
+            if (rows_run < rows && log_p) TN_HIP(tnk::launch_fill_f64(log_p + w0, Z, NAN, E.s));
+            for (int r = 0; r < rows_run; ++r) {
                 const DMps &Bb = B.below[r];
                 // sites that take the transfer-matrix route, and their matrices
                 std::vector<int> useT(cols, 0);
@@ -426,15 +433,19 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                         E.drop(Lc);
                         Lc = L2;
                         if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
-                        TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
+                        TN_HIP(tnk::launch_fill_i32(xs, Z, 0, E.s));
                         continue;
                     }
                     // P~(f) = <L_c . site(s=f), R_{c+1}> for the favoured bit f.  For
                     // c >= 1 the traced right environment gives P~(0) + P~(1) =
-                    // |R_c| <L_c, R_c>, so the other P~ needs no second projected
-                    // step; that step is then extended only for the samples that
-                    // drew the other bit (the others' tiles are skipped).  Site 0
-                    // computes both projections.
+                    // |R_c| <L_c, R_c>, so the draw takes the other P~ as the
+                    // difference, except for samples where that difference is
+                    // below a precision-dependent fraction of the total (its
+                    // rounding would dominate): those contract the projection
+                    // directly before the draw.  After the draw the other bit's
+                    // step runs only for the samples that drew it (the others'
+                    // tiles are skipped), and their log q takes the conditional
+                    // from that direct projection.  Site 0 computes both.
                     const int f = favour[(size_t)r * cols + c];
                     auto rest_step = [&](const Ten &t1, int s) {
                         return useT[c] ? left_rest_T(E, t1, m[c], s ? T1[c] : T0[c])
@@ -450,7 +461,21 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     if (rest) {
                         const int64_t perc = Lc.numel() / Z;
                         E.dot(Lc.p, R[c].p, Lc.esz, perc, Z, perc, ptot);
-                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, ptf, pto, Z, E.s));
+                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, ptf, pto, Z, diff_thr, need,
+                                                         E.s));
+                        // samples whose other-bit P~ is too small a difference to
+                        // trust: contract that projection directly (masked to them)
+                        E.set_mask(need, 'z', 0);
+                        Ten Ln;
+                        try {
+                            Ln = rest_step(t1, 1 - f);
+                        } catch (...) {
+                            E.clear_mask();
+                            throw;
+                        }
+                        E.clear_mask();
+                        E.dot(Ln.p, R[c + 1].p, Ln.esz, per, Z, per, pto, need, 0);
+                        E.drop(Ln);
                     } else {
                         Lo = rest_step(t1, 1 - f);
                         E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, pto);
@@ -470,6 +495,7 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     d.log_q = log_q + w0;
                     d.xsel = xs;
                     d.flags = flags;
+                    d.log_cond = o.log_cond;
                     TN_HIP(tnk::launch_draw(d, E.s));
                     if (rest) {
                         E.set_mask(xs, 'z', f);  // skip the samples that drew f
@@ -480,6 +506,11 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                             throw;
                         }
                         E.clear_mask();
+                        // the drawn bit's conditional from the direct projection
+                        // (log q never keeps the difference's rounding)
+                        E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, ptd, xs, f);
+                        TN_HIP(tnk::launch_fix_other(ptf, pto, ptd, xs, 1 - f, Z, log_q + w0, o.log_cond, w0, P.nq,
+                                                     d.qubit, flags, E.s));
                     }
                     E.drop(t1);
                     // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
@@ -506,7 +537,9 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                     TN_HIP(tnk::launch_select_copy(a.t->p, a.t->esz, per, per, 0, xsel + (size_t)c * Zw, Z, X[c].p,
                                                    per, E.s));
                 }
-                if (r + 1 < rows) {
+                if (r + 1 == rows_run && rows_run < rows) {
+                    // stopped early (test hook): no fit for rows that are not sampled
+                } else if (r + 1 < rows) {
                     std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
                     for (auto &x : m) E.drop(x);
                     m = mn;
@@ -539,12 +572,12 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
         }
     } catch (...) {
         E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
-        E.unraw(ptot); E.unraw(lnR);
+        E.unraw(ptot); E.unraw(lnR); E.unraw(ptd); E.unraw(need);
         if (kbuf) E.unraw(kbuf);
         throw;
     }
     E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
-    E.unraw(ptot); E.unraw(lnR);
+    E.unraw(ptot); E.unraw(lnR); E.unraw(ptd); E.unraw(need);
     if (kbuf) E.unraw(kbuf);
 }
 
@@ -592,7 +625,7 @@ void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first,
                     const SiteRef &a = V.at(r, c);
                     int *xs = xsel + (size_t)c * Zw;
                     const int q = P.site_index[(size_t)r * cols + c];
-                    if (a.dim(0) == 1 || q < 0) TN_HIP(hipMemsetAsync(xs, 0, (size_t)Z * 4, E.s));
+                    if (a.dim(0) == 1 || q < 0) TN_HIP(tnk::launch_fill_i32(xs, Z, 0, E.s));
                     else TN_HIP(tnk::launch_bits_select(bits, P.nq, w0, q, Z, xs, E.s));
                     X[c] = E.make({Z, a.dim(1), a.dim(2), a.dim(3), a.dim(4)});
                     const int64_t per = X[c].numel() / Z;

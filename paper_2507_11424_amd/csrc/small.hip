@@ -127,8 +127,10 @@ __global__ void __launch_bounds__(NT) k_init(void *out, int esz, int64_t n, int6
 }
 
 __global__ void __launch_bounds__(NT) k_dot_part(const void *x, const void *y, int esz, int64_t n,
-                                                int64_t bs, int P, double *partial) {
+                                                int64_t bs, int P, double *partial, const int *mask,
+                                                int mask_skip) {
     const int b = blockIdx.y;
+    if (mask && mask[b] == mask_skip) return;
     const char *xb = reinterpret_cast<const char *>(x) + (int64_t)b * bs * esz;
     const char *yb = reinterpret_cast<const char *>(y) + (int64_t)b * bs * esz;
     double sr = 0.0, si = 0.0;
@@ -145,9 +147,11 @@ __global__ void __launch_bounds__(NT) k_dot_part(const void *x, const void *y, i
     }
 }
 
-__global__ void k_sum_parts2(const double *partial, int P, int batch, double *out) {
+__global__ void k_sum_parts2(const double *partial, int P, int batch, double *out, const int *mask,
+                             int mask_skip) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
+    if (mask && mask[b] == mask_skip) return;
     double sr = 0.0, si = 0.0;
     for (int i = 0; i < P; ++i) {
         sr += partial[((int64_t)b * P + i) * 2];
@@ -182,6 +186,7 @@ __global__ void k_draw(DrawArgs a) {
         lp = log(x == 0 ? P0 : p1 / tot);
     }
     a.log_q[b] += lp;
+    if (a.log_cond) a.log_cond[(a.bits_row0 + b) * (int64_t)a.n_qubits + a.qubit] = lp;
     a.bits[(a.bits_row0 + b) * (int64_t)a.n_qubits + a.qubit] = (uint8_t)x;
     a.xsel[b] = x;
 }
@@ -208,6 +213,10 @@ __global__ void __launch_bounds__(NT) k_select2(const void *x0, const void *x1, 
 }
 
 __global__ void __launch_bounds__(NT) k_fill_f64(double *x, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) x[i] = v;
+}
+
+__global__ void __launch_bounds__(NT) k_fill_i32(int *x, int64_t n, int v) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) x[i] = v;
 }
 
@@ -238,12 +247,46 @@ __global__ void k_logp(const double *amp, const double *mlog, int batch, double 
     if (arg) arg[b] = atan2(amp[2 * b + 1], amp[2 * b]);
 }
 
-__global__ void k_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch) {
+__global__ void k_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch,
+                                double thr, int *need) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= batch) return;
     const double f = exp(lnr[z]);
-    pt1[2 * z] = f * tot[2 * z] - pt0[2 * z];
-    pt1[2 * z + 1] = f * tot[2 * z + 1] - pt0[2 * z + 1];
+    const double tr = f * tot[2 * z], ti = f * tot[2 * z + 1];
+    const double dr = tr - pt0[2 * z];
+    pt1[2 * z] = dr;
+    pt1[2 * z + 1] = ti - pt0[2 * z + 1];
+    // a difference below thr of the total is not trusted (not even its sign):
+    // that sample's projection is contracted directly
+    need[z] = (dr > thr * tr) ? 0 : 1;
+}
+
+// out[z] = 1 for the samples that drew the bit `other` and whose projection on
+// it was not contracted before the draw (need[z] == 0), else 0.
+__global__ void k_other_mask(const int *xs, const int *need, int other, int batch, int *out) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= batch) return;
+    out[z] = (xs[z] == other && !need[z]) ? 1 : 0;
+}
+
+// For the samples that drew `other`: replace the log-conditional the draw
+// used (from P~(other) = pt_used) by the one from the directly contracted
+// P~(other) = pt_direct, with the favoured bit's P~ = pt_f.
+__global__ void k_fix_other(const double *pt_f, const double *pt_used, const double *pt_direct, const int *xs,
+                            int other, int batch, double *log_q, double *log_cond, int64_t row0, int n_qubits,
+                            int qubit, int *flags) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= batch || xs[z] != other) return;
+    const double pf = fmax(pt_f[2 * z], 0.0);
+    const double pu = fmax(pt_used[2 * z], 0.0);
+    const double pd = pt_direct[2 * z];
+    if (!(pd > 0.0) || !isfinite(pd)) {
+        flags[z] |= 2;
+        return;
+    }
+    const double lnew = log(pd / (pf + pd));
+    log_q[z] += lnew - log(pu / (pf + pu));
+    if (log_cond) log_cond[(row0 + z) * (int64_t)n_qubits + qubit] = lnew;
 }
 
 // Per-sample bond of the amplitude boundary: the largest kept value over the cuts.
@@ -322,6 +365,26 @@ __global__ void __launch_bounds__(SN) k_sample_stats(const double *lq, const dou
     }
 }
 
+// Fingerprint of raw tensor bytes: acc += sum_i mix(word_i, salt + i), with
+// the splitmix64 finaliser as the mixer (sum modulo 2^64).  Words are 8 bytes.
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(NT) k_fingerprint(FingerprintSet f, unsigned long long *acc) {
+    const int t = blockIdx.y;
+    const uint64_t *x = reinterpret_cast<const uint64_t *>(f.ptr[t]);
+    const int64_t n = f.words[t];
+    const uint64_t salt = f.salt[t];
+    uint64_t h = 0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        h += mix64(x[i] ^ mix64(salt + (uint64_t)i * 0x9E3779B97F4A7C15ull));
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+    if ((threadIdx.x & 63) == 0 && h) atomicAdd(acc, (unsigned long long)h);
+}
+
 int grid_for(int64_t n) {
     int64_t g = (n + NT - 1) / NT;
     if (g > 4096) g = 4096;
@@ -384,10 +447,12 @@ hipError_t launch_init_tensor(void *out, int esz, int64_t n, int batch, int64_t 
 }
 
 hipError_t launch_dot(const void *x, const void *y, int esz, int64_t n, int batch, int64_t bs,
-                      double *partial, double *out, hipStream_t s) {
+                      double *partial, double *out, hipStream_t s, const int *mask, int mask_skip) {
     const int P = reduce_partial_count(n);
-    hipLaunchKernelGGL(k_dot_part, dim3(P, batch), dim3(NT), 0, s, x, y, esz, n, bs, P, partial);
-    hipLaunchKernelGGL(k_sum_parts2, dim3((batch + 63) / 64), dim3(64), 0, s, partial, P, batch, out);
+    hipLaunchKernelGGL(k_dot_part, dim3(P, batch), dim3(NT), 0, s, x, y, esz, n, bs, P, partial, mask,
+                       mask_skip);
+    hipLaunchKernelGGL(k_sum_parts2, dim3((batch + 63) / 64), dim3(64), 0, s, partial, P, batch, out, mask,
+                       mask_skip);
     return hipGetLastError();
 }
 
@@ -424,6 +489,12 @@ hipError_t launch_fill_f64(double *x, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_fill_i32(int *x, int64_t n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(NT), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_env_rho(const double *dots, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_env_rho, dim3(1), dim3(64), 0, s, dots, out);
     return hipGetLastError();
@@ -449,9 +520,25 @@ hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t
 }
 
 hipError_t launch_marginal_rest(const double *tot, const double *lnr, const double *pt0, double *pt1, int batch,
-                                hipStream_t s) {
+                                double thr, int *need, hipStream_t s) {
     if (batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_marginal_rest, dim3((batch + 63) / 64), dim3(64), 0, s, tot, lnr, pt0, pt1, batch);
+    hipLaunchKernelGGL(k_marginal_rest, dim3((batch + 63) / 64), dim3(64), 0, s, tot, lnr, pt0, pt1, batch, thr,
+                       need);
+    return hipGetLastError();
+}
+
+hipError_t launch_other_mask(const int *xs, const int *need, int other, int batch, int *out, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_other_mask, dim3((batch + 63) / 64), dim3(64), 0, s, xs, need, other, batch, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_other(const double *pt_f, const double *pt_used, const double *pt_direct, const int *xs,
+                            int other, int batch, double *log_q, double *log_cond, int64_t row0, int n_qubits,
+                            int qubit, int *flags, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fix_other, dim3((batch + 63) / 64), dim3(64), 0, s, pt_f, pt_used, pt_direct, xs, other,
+                       batch, log_q, log_cond, row0, n_qubits, qubit, flags);
     return hipGetLastError();
 }
 
@@ -465,6 +552,16 @@ hipError_t launch_chi_used(const int *k, int cuts, int batch, int constant, int 
 hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_logp, dim3((batch + 63) / 64), dim3(64), 0, s, amp, mlog, batch, log_p, arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_fingerprint(const FingerprintSet &f, unsigned long long *acc, hipStream_t s) {
+    if (f.count <= 0) return hipSuccess;
+    int64_t mx = 1;
+    for (int i = 0; i < f.count; ++i) mx = f.words[i] > mx ? f.words[i] : mx;
+    int g = grid_for(mx);
+    if (g > 64) g = 64;
+    hipLaunchKernelGGL(k_fingerprint, dim3(g, f.count), dim3(NT), 0, s, f, acc);
     return hipGetLastError();
 }
 

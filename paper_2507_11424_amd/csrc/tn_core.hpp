@@ -87,6 +87,10 @@ struct SampleOpts {
     int init_tag = 2;  // Philox stream of the fit's random initial guesses
     double svd_cutoff = 0;  // > 0: SVD truncation of every fitted amplitude boundary
     int chi_x_min = 1;      // lower clamp of the truncation
+    // test hooks: stop after rows_limit rows (0 = all rows); log_cond (device
+    // [n][N] doubles) receives every drawn qubit's log P(x_q | earlier qubits)
+    int rows_limit = 0;
+    double *log_cond = nullptr;
 };
 
 // chi_used (optional, device [n][rows] int32): largest kept bond of the

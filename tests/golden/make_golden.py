@@ -6,9 +6,13 @@ Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
     python tests/golden/make_golden.py c3_norm       # ~10 min on 8 cores
     python tests/golden/make_golden.py c3_samples    # a few samples at chi_x = 8
     python tests/golden/make_golden.py c2_env        # 8x8 D=4 environments at chi = 32
+    python tests/golden/make_golden.py c3_rows       # first 4 sampled rows at chi_x = 64 (~1 h)
+    python tests/golden/make_golden.py c3_env        # c3 environments at chi = 64 (~40 min)
 """
 import json
 import math
+
+import numpy as np
 import os
 import sys
 import time
@@ -64,5 +68,51 @@ def c2_env(chi=32):
     print({k: v for k, v in out.items() if k in ("config", "chi", "oracle_seconds")})
 
 
+def c3_rows(chi_x=64, rows_limit=4, indices=(0, 17)):
+    """The first rows of samples at the benchmark's sampling bond chi_x = 64:
+    rows 0-1 sample under an exact amplitude boundary (bond 1, then 8), the fit
+    after row 1 is exact (bond 64), the fit after row 2 truncates 512 -> 64, so
+    row 3 samples under a fitted boundary of the benchmark's shape.  Stored:
+    bits of those rows, the partial log q and every drawn qubit's
+    log P(x_q | earlier qubits), for the given sample indices (each with its
+    own row of stored uniforms)."""
+    lat, T, cfg = make_config("c3")
+    t0 = time.time()
+    below, logs, info = ob.boundary_set(T, 64, 2, 0, 0)
+    t1 = time.time()
+    u = sample_uniforms(41, len(indices), lat.n_qubits)
+    res = []
+    for i, idx in enumerate(indices):
+        lcv = np.full((1, lat.n_qubits), float("nan"))
+        bits, lq, lp = oracle.sample(T, lat.site_index, 64, chi_x, 1, seed=0, first=idx, uniforms=u[i:i + 1],
+                                     below=below, rows_limit=rows_limit, log_cond=lcv)
+        lc = [None if v != v else float(v) for v in lcv[0]]
+        res.append(dict(index=idx, bits=bits[0].tolist(), log_q=float(lq[0]), log_cond=lc))
+        print(f"sample {idx}: log q = {lq[0]!r} ({time.time() - t1:.0f} s)", flush=True)
+    out = dict(config="c3", chi=64, chi_x=chi_x, sweeps=2, init_seed=0, uniforms_seed=41,
+               rows_limit=rows_limit, samples=res, boundary_seconds=t1 - t0,
+               sample_seconds=time.time() - t1,
+               command="python tests/golden/make_golden.py c3_rows")
+    json.dump(out, open(os.path.join(HERE, "c3_rows_chix64.json"), "w"))
+
+
+def c3_env(chi=64):
+    """One-site density matrices and nearest-neighbour <ZZ> of the benchmark
+    lattice at chi = 64 (the per-marginal error reference)."""
+    lat, T, cfg = make_config("c3")
+    t0 = time.time()
+    e = oracle.environments(T, chi)
+    enc = lambda a: [[float(v.real), float(v.imag)] for v in a.reshape(-1)]  # noqa: E731
+    fl = lambda a: [None if v != v else float(v) for v in a.reshape(-1)]  # noqa: E731
+    out = dict(config="c3", chi=chi, sweeps=2, init_seed=0,
+               rho1=enc(e["rho1"]), rho1_shape=list(e["rho1"].shape),
+               zz_h=fl(e["zz_h"]), zz_h_shape=list(e["zz_h"].shape),
+               zz_v=fl(e["zz_v"]), zz_v_shape=list(e["zz_v"].shape),
+               oracle_seconds=time.time() - t0, command="python tests/golden/make_golden.py c3_env")
+    json.dump(out, open(os.path.join(HERE, "c3_env_chi64.json"), "w"))
+    print({k: v for k, v in out.items() if k in ("config", "chi", "oracle_seconds")})
+
+
 if __name__ == "__main__":
-    {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env}[sys.argv[1]]()
+    {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env, "c3_rows": c3_rows,
+     "c3_env": c3_env}[sys.argv[1]]()

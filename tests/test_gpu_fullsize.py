@@ -28,12 +28,15 @@ def state():
     h.close()
 
 
-# bf16x3 keeps about 16 significand bits per operand, and over 144 sites its
-# log|Z| error depends on how the rounding falls: measured 5.3e-6, and 8.7e-5
-# after the fits' random initial guesses were canonicalised by CholeskyQR
-# instead of Householder (same state to 1e-14; FP64 unchanged).  It is held to
-# 2e-4 on log|Z| and 1e-4 on arg Z (measured 2.6e-5); bf16x6 is the split mode
-# that meets 1e-5 on both (measured 1.2e-6 on log|Z|).
+# bf16x3 keeps two bf16 parts (16 significand bits) of each operand and drops
+# the lo*lo product, so each product carries a relative error of about
+# 2^-16 = 1.5e-5 before any accumulation; over 144 sites of fits the log|Z|
+# error is a sum of many such terms and cannot be held to 1e-5 (measured 5.3e-6
+# and 8.7e-5 for two fits that differ only in the rounding of their initial
+# guesses).  bf16x3 is therefore a mode that misses the 1e-5 bound: it is held
+# to 2e-4 on log|Z| and 1e-4 on arg Z with its error printed.  bf16x6 (three
+# parts, 24 significand bits, the benchmark's split-BF16 mode) meets 1e-5
+# (measured 1.2e-6 on log|Z|).
 ARG_TOL = {"fp64": 1e-9, "fp32": 1e-5, "bf16x6": 1e-5, "bf16x3": 1e-4}
 
 
@@ -53,11 +56,10 @@ def test_c3_norm_matches_oracle(state, prec, tol):
 SAMP = json.load(open(os.path.join(HERE, "golden", "c3_samples_chix8.json")))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5), ("bf16x6", 1e-5), ("bf16x3", 3e-4)])
 def test_c3_samples_match_oracle(state, prec, tol):
     """Two samples at chi_x = 8 with the stored uniforms: identical bits, and
-    log q, log p within tolerance (the reduced-precision tolerance covers the
-    accumulated rounding of 144 conditionals)."""
+    log q, log p within tolerance (bf16x3 held to its own bound, see above)."""
     import torch
     import paper_2507_11424_amd as tnb
     from peps_inputs import sample_uniforms

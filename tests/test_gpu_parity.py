@@ -161,7 +161,7 @@ def test_sample_svd_cutoff(handle, name, chi, chi_x, cutoff, chi_min, prec):
     o = opts(chi=chi, chi_x=chi_x, svd_cutoff=cutoff, chi_x_min=chi_min, prec=prec)
     bits, lq, lp, cu = handle.sample(dev_peps(lat, T, dtype), o, n, seed=77, first=3, want_chi=True)
     bits, lq, lp, cu = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy(), cu.cpu().numpy()
-    tol = 1e-9 if prec == "fp64" else 1e-4
+    tol = 1e-9 if prec == "fp64" else 1e-5
     assert np.array_equal(bits, rb)
     assert np.array_equal(cu, used)
     assert np.abs(lq - rq).max() < tol
@@ -181,3 +181,35 @@ def test_sample_svd_cutoff_truncates_and_reports(handle):
     assert np.all(cu1 <= cu0) and np.all(cu1[:, 1:] >= 2)
     assert (cu1 < cu0).any()
     assert len({tuple(r) for r in cu1}) > 1
+
+
+@pytest.mark.parametrize("call", ["sample", "environments"])
+def test_cache_follows_contents_not_addresses(handle, call):
+    """A state overwritten in place (same device pointers, same lattice and
+    options) must not be served the boundary set cached for the old contents:
+    sample / environments of state A, copy state B into A's buffers, call again,
+    compare with the oracle on B."""
+    import torch
+    lat = square_lattice(4, 4, 3)
+    TA = random_peps(lat, "haar", 0.6, 61)
+    TB = random_peps(lat, "haar", 0.6, 62)
+    P = dev_peps(lat, TA)
+    o = opts(chi=4, chi_x=3)
+    if call == "sample":
+        handle.sample(P, o, 8, seed=3)
+    else:
+        handle.environments(P, o)
+    flat = [t for row in TB for t in row]
+    for dst, src in zip(P.tensors, flat):
+        dst.copy_(torch.from_numpy(np.ascontiguousarray(src)).to(dst.device))
+    if call == "sample":
+        rb, rq, rp = oracle.sample(TB, lat.site_index, 4, 3, 8, seed=3)
+        bits, lq, lp = handle.sample(P, o, 8, seed=3)
+        assert np.array_equal(bits.cpu().numpy(), rb)
+        assert np.abs(lq.cpu().numpy() - rq).max() < 1e-9
+        assert np.abs(lp.cpu().numpy() - rp).max() < 1e-9
+    else:
+        ref = oracle.environments(TB, 4)
+        got = handle.environments(P, o)
+        assert np.nanmax(np.abs(got["rho1"].cpu().numpy() - ref["rho1"])) < 1e-10
+        assert np.nanmax(np.abs(got["zz_h"].cpu().numpy() - ref["zz_h"])) < 1e-10

@@ -253,3 +253,36 @@ def test_plan_bonds_consistency():
     assert not ok and t == [64, 64, 64, 64, 1]
     ok, t = plan_bonds([2, 2, 2, 2], [100, 3, 100], 8)
     assert t == [2, 3, 2]
+
+
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2"])
+@pytest.mark.parametrize("rows_limit", [1, 2])
+def test_sampler_partial_rows_and_conditionals_exact(name, rows_limit):
+    """At exact bond, the per-qubit conditionals are ratios of statevector
+    marginals of the prefixes in sampling order (rows top-down, columns
+    left-to-right), and a run stopped after k rows has log q = log of the
+    marginal probability of the drawn bits of those rows."""
+    lat, T, chi = _case(name)
+    psi = statevector(T, lat.site_index)
+    P = np.abs(psi) ** 2
+    P = P / P.sum()
+    n_q = lat.n_qubits
+    order = [int(lat.site_index[r, c]) for r in range(lat.rows) for c in range(lat.cols)
+             if lat.site_index[r, c] >= 0]
+    n = 6
+    lc = np.full((n, n_q), np.nan)
+    bits, lq, lp = sample(T, lat.site_index, chi, chi, n, seed=91, rows_limit=rows_limit, log_cond=lc)
+    done = [int(lat.site_index[r, c]) for r in range(rows_limit) for c in range(lat.cols)
+            if lat.site_index[r, c] >= 0]
+    for i in range(n):
+        prev = 0.0
+        for k in range(1, len(done) + 1):
+            sel = order[:k]
+            marg = np.moveaxis(P, sel, list(range(k))).reshape((2,) * k + (-1,)).sum(axis=-1)
+            lm = math.log(marg[tuple(int(bits[i, q]) for q in sel)])
+            assert abs((lm - prev) - lc[i, sel[-1]]) < 1e-10
+            prev = lm
+        assert abs(prev - lq[i]) < 1e-10
+        assert np.all(np.isnan(lc[i, [q for q in range(n_q) if q not in done]]))
+        assert not np.any(bits[i, [q for q in range(n_q) if q not in done]])
+        assert math.isnan(lp[i])
