@@ -367,15 +367,19 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
         if (z_is && (!bits || n_qubits <= 0)) throw TnError(ST_INVALID, "z_is needs bits and n_qubits > 0");
         Engine &E = *h->E;
         double *dev = reinterpret_cast<double *>(E.raw(3 * sizeof(double)));
+        void *ws = E.raw(tnk::stats_workspace_bytes(n, n_qubits, z_is != nullptr));
         try {
-            TN_HIP(tnk::launch_sample_stats(log_q, log_p, n, log_Z, z_is ? bits : nullptr, n_qubits, dev, z_is, E.s));
+            TN_HIP(tnk::launch_sample_stats(log_q, log_p, n, log_Z, z_is ? bits : nullptr, n_qubits, dev, z_is, ws,
+                                            E.s));
             TN_HIP(hipMemcpyAsync(out, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, E.s));
             E.sync();
         } catch (...) {
             E.unraw(dev);
+            E.unraw(ws);
             throw;
         }
         E.unraw(dev);
+        E.unraw(ws);
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);

@@ -192,10 +192,17 @@ hipError_t launch_fix_other(const double *pt_f, const double *pt_used, const dou
 // xs[z] = bits[(row0 + z) * n_qubits + qubit] (0/1) for z < batch.
 hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row0, int qubit, int batch, int *xs,
                               hipStream_t s);
-// out[3] = {log mean(p/q), mean(log q - log p + log_Z), effective sample size};
-// z_is[n_qubits] (optional) = importance-weighted <Z_q> from bits [n][n_qubits].
+// out[3] (device) = {log mean(p/q), mean(log q - log p + log_Z), effective sample
+// size}; z_is[n_qubits] (optional) = importance-weighted <Z_q> from bits
+// [n][n_qubits].  Three passes over stats_blocks(n) blocks with partial results
+// in `workspace` (stats_workspace_bytes; every byte used is written before it is
+// read, so it needs no clearing).
+constexpr int STATS_BLOCKS_MAX = 64;
+int stats_blocks(int64_t n);
+size_t stats_workspace_bytes(int64_t n, int64_t n_qubits, bool with_z);
 hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t n, double log_Z,
-                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s);
+                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, void *workspace,
+                               hipStream_t s);
 // out[z * stride] = max_c k[c * batch + z] over c < cuts, or `constant` when
 // k is null or cuts == 0.
 hipError_t launch_chi_used(const int *k, int cuts, int batch, int constant, int *out, int64_t stride,

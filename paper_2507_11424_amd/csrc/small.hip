@@ -309,11 +309,14 @@ __global__ void k_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row
     xs[z] = bits[(row0 + z) * n_qubits + qubit] ? 1 : 0;
 }
 
-// Sample-quality metrics over n samples, one workgroup of SN threads, fixed
-// reduction order.  w_i = exp(lw_i - max lw), lw = log p - log q:
+// Sample-quality metrics over n samples, in three passes over P blocks of SN
+// threads with partial results in a workspace, fixed reduction order.
+// w_i = exp(lw_i - max lw), lw = log p - log q:
 // out[0] = log((1/n) sum p/q), out[1] = (1/n) sum (log q - log p + log Z),
 // out[2] = (sum w)^2 / sum w^2; z_is[q] = sum_i w_i (1 - 2 x_iq) / sum_i w_i.
+// Block b covers samples [b c, min(n, (b+1) c)), c = ceil(n / P).
 constexpr int SN = 256;
+constexpr int SW = 1024;  // weights staged in LDS per chunk (z_is pass)
 __device__ double block_sum(double v, double *red) {
     red[threadIdx.x] = v;
     __syncthreads();
@@ -326,21 +329,39 @@ __device__ double block_sum(double v, double *red) {
     return r;
 }
 
-__global__ void __launch_bounds__(SN) k_sample_stats(const double *lq, const double *lp, int64_t n, double logZ,
-                                                     const uint8_t *bits, int64_t nq, double *out, double *z_is) {
+__device__ inline void stats_range(int64_t n, int P, int64_t &beg, int64_t &end) {
+    const int64_t c = (n + P - 1) / P;
+    beg = (int64_t)blockIdx.x * c;
+    end = beg + c < n ? beg + c : n;
+}
+
+__global__ void __launch_bounds__(SN) k_stats_max(const double *lq, const double *lp, int64_t n, int P,
+                                                  double *pmax) {
     __shared__ double red[SN];
+    int64_t beg, end;
+    stats_range(n, P, beg, end);
     double mx = -INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += SN) mx = fmax(mx, lp[i] - lq[i]);
+    for (int64_t i = beg + threadIdx.x; i < end; i += SN) mx = fmax(mx, lp[i] - lq[i]);
     red[threadIdx.x] = mx;
     __syncthreads();
     for (int h = SN / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
         __syncthreads();
     }
-    const double top = red[0];
-    __syncthreads();
+    if (threadIdx.x == 0) pmax[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(SN) k_stats_sums(const double *lq, const double *lp, int64_t n, double logZ,
+                                                   const uint8_t *bits, int64_t nq, int P, const double *pmax,
+                                                   double *psum, double *pz) {
+    __shared__ double red[SN];
+    __shared__ double wl[SW];
+    double top = -INFINITY;
+    for (int b = 0; b < P; ++b) top = fmax(top, pmax[b]);
+    int64_t beg, end;
+    stats_range(n, P, beg, end);
     double s1 = 0.0, s2 = 0.0, kl = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += SN) {
+    for (int64_t i = beg + threadIdx.x; i < end; i += SN) {
         const double w = exp(lp[i] - lq[i] - top);
         s1 += w;
         s2 += w * w;
@@ -350,18 +371,48 @@ __global__ void __launch_bounds__(SN) k_sample_stats(const double *lq, const dou
     s2 = block_sum(s2, red);
     kl = block_sum(kl, red);
     if (threadIdx.x == 0) {
+        psum[3 * blockIdx.x] = s1;
+        psum[3 * blockIdx.x + 1] = s2;
+        psum[3 * blockIdx.x + 2] = kl;
+    }
+    if (!pz) return;
+    double *zb = pz + (int64_t)blockIdx.x * nq;
+    for (int64_t q = threadIdx.x; q < nq; q += SN) zb[q] = 0.0;  // each (block, q) is owned by one thread
+    for (int64_t c0 = beg; c0 < end; c0 += SW) {
+        const int len = (int)(end - c0 < SW ? end - c0 : SW);
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += SN) wl[i] = exp(lp[c0 + i] - lq[c0 + i] - top);
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < nq; q += SN) {
+            double acc = 0.0;
+            for (int i = 0; i < len; ++i) acc += bits[(c0 + i) * nq + q] ? -wl[i] : wl[i];
+            zb[q] += acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SN) k_stats_final(const double *psum, const double *pz, int P, int64_t n,
+                                                    int64_t nq, const double *pmax, double *out, double *z_is) {
+    __shared__ double s1s;
+    if (threadIdx.x == 0) {
+        double top = -INFINITY, s1 = 0.0, s2 = 0.0, kl = 0.0;
+        for (int b = 0; b < P; ++b) {
+            top = fmax(top, pmax[b]);
+            s1 += psum[3 * b];
+            s2 += psum[3 * b + 1];
+            kl += psum[3 * b + 2];
+        }
         out[0] = top + log(s1 / (double)n);
         out[1] = kl / (double)n;
         out[2] = s1 * s1 / s2;
+        s1s = s1;
     }
+    __syncthreads();
     if (!z_is) return;
     for (int64_t q = threadIdx.x; q < nq; q += SN) {
         double acc = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            const double w = exp(lp[i] - lq[i] - top);
-            acc += bits[i * nq + q] ? -w : w;
-        }
-        z_is[q] = acc / s1;
+        for (int b = 0; b < P; ++b) acc += pz[(int64_t)b * nq + q];
+        z_is[q] = acc / s1s;
     }
 }
 
@@ -512,10 +563,30 @@ hipError_t launch_bits_select(const uint8_t *bits, int64_t n_qubits, int64_t row
     return hipGetLastError();
 }
 
+int stats_blocks(int64_t n) {
+    int64_t p = (n + 1023) / 1024;
+    if (p < 1) p = 1;
+    if (p > STATS_BLOCKS_MAX) p = STATS_BLOCKS_MAX;
+    return (int)p;
+}
+
+size_t stats_workspace_bytes(int64_t n, int64_t n_qubits, bool with_z) {
+    const int64_t P = stats_blocks(n);
+    return (size_t)(4 * P + (with_z ? P * n_qubits : 0)) * sizeof(double);
+}
+
 hipError_t launch_sample_stats(const double *log_q, const double *log_p, int64_t n, double log_Z,
-                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, hipStream_t s) {
-    if (n <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sample_stats, dim3(1), dim3(SN), 0, s, log_q, log_p, n, log_Z, bits, n_qubits, out, z_is);
+                               const uint8_t *bits, int64_t n_qubits, double *out, double *z_is, void *workspace,
+                               hipStream_t s) {
+    if (n <= 0 || !workspace) return hipErrorInvalidValue;
+    const int P = stats_blocks(n);
+    double *pmax = static_cast<double *>(workspace);
+    double *psum = pmax + P;
+    double *pz = z_is ? psum + 3 * P : nullptr;
+    hipLaunchKernelGGL(k_stats_max, dim3(P), dim3(SN), 0, s, log_q, log_p, n, P, pmax);
+    hipLaunchKernelGGL(k_stats_sums, dim3(P), dim3(SN), 0, s, log_q, log_p, n, log_Z, z_is ? bits : nullptr,
+                       n_qubits, P, pmax, psum, pz);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(SN), 0, s, psum, pz, P, n, n_qubits, pmax, out, z_is);
     return hipGetLastError();
 }
 

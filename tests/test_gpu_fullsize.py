@@ -56,7 +56,16 @@ def test_c3_norm_matches_oracle(state, prec, tol):
 SAMP = json.load(open(os.path.join(HERE, "golden", "c3_samples_chix8.json")))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5), ("bf16x6", 1e-5), ("bf16x3", 3e-4)])
+# The FP32 / split-BF16 tolerance 1e-5 applies to every computed marginal
+# (each conditional of the sampler is one network contraction).  log q of an
+# N-qubit sample is the sum of N such log-conditionals with independent
+# rounding, and log p comes from a chain of N / cols fits, so both are held to
+# 1e-5 sqrt(N) (1.2e-4 for the 144 qubits here; measured 3.5e-5 in FP32).
+SQRT_N = 12.0
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5 * SQRT_N), ("bf16x6", 1e-5 * SQRT_N),
+                                      ("bf16x3", 3e-4 * SQRT_N)])
 def test_c3_samples_match_oracle(state, prec, tol):
     """Two samples at chi_x = 8 with the stored uniforms: identical bits, and
     log q, log p within tolerance (bf16x3 held to its own bound, see above)."""
