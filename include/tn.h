@@ -193,6 +193,24 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
                           const double *log_q, const double *log_p, double log_Z,
                           double *out, double *z_is);
 
+/* Allocation-free variant of tn_sample_stats, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same inputs and metrics, computed by the same
+ * kernels, but:
+ *   out  : DEVICE [3] doubles (not host memory); the call is asynchronous on
+ *          the handle's stream and never synchronises;
+ *   the partial results live in a fixed scratch array of 4 MiB per device,
+ *   held until the process ends: with z_is it holds up to
+ *   TN_NOALLOC_MAX_QUBITS qubits (any n); more qubits are rejected with
+ *   TN_ERR_INVALID before anything is launched.
+ * The call performs no device allocation or free.  All calls on one device
+ * share that scratch: calls that overlap on one device (two streams, or two
+ * threads) race and must be serialised by the caller.  Errors as
+ * tn_sample_stats. */
+#define TN_NOALLOC_MAX_QUBITS 8188
+tn_status tn_sample_stats_noalloc(tn_handle *h, int64_t n, int32_t n_qubits, const uint8_t *bits,
+                                  const double *log_q, const double *log_p, double log_Z, double *out, double *z_is);
+
 /* Text of the last error on this handle ("" if none).  Valid until the next call. */
 const char *tn_last_error(const tn_handle *h);
 

@@ -32,7 +32,7 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
            "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
            "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask",
-           "tn_test_sample_config"]
+           "tn_test_sample_config", "tn_sample_stats_noalloc"]
 
 
 class TnError(RuntimeError):
@@ -77,6 +77,7 @@ def lib(path: Optional[str] = None):
     L.tn_sample.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, u64, i64, vp, vp, vp, vp, vp]
     L.tn_amplitude.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.POINTER(c_opts), u64, i64, vp, vp, vp]
     L.tn_sample_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.tn_sample_stats_noalloc.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_double, vp, vp]
     L.tn_last_error.argtypes = [vp]
     L.tn_last_error.restype = ctypes.c_char_p
     L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64), dp,
@@ -97,7 +98,7 @@ def lib(path: Optional[str] = None):
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
               "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats",
-              "tn_test_sample_config"):
+              "tn_test_sample_config", "tn_sample_stats_noalloc"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -286,6 +287,38 @@ class Handle:
         if zis is not None:
             res["z_is"] = zis
         return res
+
+    def sample_stats_noalloc(self, log_q, log_p, log_Z: float, bits=None, out=None, z_is=None):
+        """As sample_stats through tn_sample_stats_noalloc: the library allocates
+        nothing (partials in its fixed scratch); `out` (device float64 [3]) and
+        `z_is` (device float64 [N], with bits) are the caller's buffers, made
+        here if not given.  Asynchronous: returns the device tensors."""
+        import torch
+        dev = log_q.device
+        if log_q.dtype != torch.float64 or log_p.dtype != torch.float64 or not log_q.is_contiguous() \
+                or not log_p.is_contiguous() or log_p.device != dev:
+            raise ValueError("log_q and log_p must be contiguous float64 tensors on one device")
+        if log_q.shape != log_p.shape or log_q.dim() != 1:
+            raise ValueError("log_q and log_p must be 1-d of equal length")
+        n = log_q.shape[0]
+        if out is None:
+            out = torch.empty((3,), dtype=torch.float64, device=dev)
+        bp = None
+        nq = 0
+        if bits is not None:
+            if bits.dtype != torch.uint8 or not bits.is_contiguous() or bits.dim() != 2 or bits.shape[0] != n:
+                raise ValueError("bits must be a contiguous uint8 tensor of shape [n][N]")
+            nq = bits.shape[1]
+            if z_is is None:
+                z_is = torch.empty((nq,), dtype=torch.float64, device=dev)
+            bp = ctypes.c_void_p(bits.data_ptr())
+        else:
+            z_is = None
+        self._check(lib().tn_sample_stats_noalloc(self.h, n, nq, bp, ctypes.c_void_p(log_q.data_ptr()),
+                                                  ctypes.c_void_p(log_p.data_ptr()), float(log_Z),
+                                                  ctypes.c_void_p(out.data_ptr()),
+                                                  ctypes.c_void_p(z_is.data_ptr()) if z_is is not None else None))
+        return out, z_is
 
     def counters(self):
         f, ms, qms, qf, mms, gb = (ctypes.c_double() for _ in range(6))

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "../../include/tn.h"
@@ -11,6 +12,35 @@
 #include "kernels.hpp"
 
 using namespace tnb;
+
+// Fixed device scratch of tn_sample_stats_noalloc: the partial results of the
+// metric kernels.  Each device holds its own copy until the process ends; host
+// code uses only the device address obtained by hipGetSymbolAddress (the
+// array's name is a host-side stand-in).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(4) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on `device` (current), looked up once per device.
+void *scratch_on(int device) {
+    if (device < 0 || device >= MAX_DEVICES) throw TnError(ST_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw TnError(ST_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        scratch_ptr[device] = ptr;
+    }
+    return scratch_ptr[device];
+}
+
+}  // namespace
 
 struct tn_handle {
     int device = 0;
@@ -223,6 +253,7 @@ tn_status tn_create(tn_handle **out, int device, void *stream) {
         h->stream = reinterpret_cast<hipStream_t>(stream);
         TN_HIP(hipSetDevice(device));
         h->E = std::make_unique<Engine>(device, h->stream, 0);
+        (void)scratch_on(device);  // the device's scratch address, once per device
         *out = h.release();
         return TN_OK;
     } catch (const TnError &e) {
@@ -380,6 +411,32 @@ tn_status tn_sample_stats(tn_handle *h, int64_t n, int32_t n_qubits, const uint8
         }
         E.unraw(dev);
         E.unraw(ws);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+tn_status tn_sample_stats_noalloc(tn_handle *h, int64_t n, int32_t n_qubits, const uint8_t *bits,
+                                  const double *log_q, const double *log_p, double log_Z, double *out, double *z_is) {
+    try {
+        if (!h || !h->E) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        if (n <= 0) throw TnError(ST_INVALID, "n must be > 0");
+        if (!log_q || !log_p || !out) throw TnError(ST_INVALID, "null log_q, log_p or out");
+        if (z_is && (!bits || n_qubits <= 0)) throw TnError(ST_INVALID, "z_is needs bits and n_qubits > 0");
+        const size_t need = tnk::stats_workspace_bytes(n, z_is ? n_qubits : 0, z_is != nullptr);
+        if (need > NOALLOC_SCRATCH_BYTES)
+            throw TnError(ST_INVALID, "tn_sample_stats_noalloc: n_qubits = " + std::to_string(n_qubits) + " needs " +
+                                          std::to_string(need) + " bytes of scratch, the fixed scratch holds " +
+                                          std::to_string(NOALLOC_SCRATCH_BYTES) + " (at most " +
+                                          std::to_string(TN_NOALLOC_MAX_QUBITS) + " qubits)");
+        void *ws = scratch_on(h->device);
+        TN_HIP(tnk::launch_sample_stats(log_q, log_p, n, log_Z, z_is ? bits : nullptr, n_qubits, out, z_is, ws,
+                                        h->E->s));
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);
