@@ -78,11 +78,21 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_11424_amd", "csrc", f) for f in
 
 
 def kernel_hash() -> str:
+    """sha256 of the contraction kernel's source: gett.hip and the part of
+    kernels.hpp that declares its arguments, tiles and launches (from
+    `struct GettArgs` to the linear-algebra section), so that edits to other
+    kernels' declarations keep the counter record valid."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, "rb") as fh:
-            h.update(fh.read())
+            text = fh.read()
+        if f.endswith("kernels.hpp"):
+            i = text.find(b"struct GettArgs")
+            j = text.find(b"// ---------------------------------------------------------------- linear algebra")
+            if i >= 0 and j > i:
+                text = text[i:j]
+        h.update(text)
     return h.hexdigest()
 
 
