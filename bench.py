@@ -345,6 +345,9 @@ def compare_mode(a, prec, h, lat, T, chi, chi_x, cutoff, chi_x_min, step, ref_re
     achieved = g_fl / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None
     peak = PEAK_TFLOPS[prec]
     ceiling = peak * 8 / (2 * BF16_PRODUCTS[prec]) if prec in BF16_PRODUCTS else peak
+    workload = (f"{a.config} {prec} samples={a.samples} chi={chi} chi_x={chi_x} cutoff={cutoff:g} "
+                f"env={'no' if a.no_env else 'yes'}")
+    ctr = stored_counters(workload)
     bits, lq, lp = last["res"][:3]
     same = (bits == ref_bits).all(dim=1)
     n_same = int(same.sum())
@@ -362,6 +365,11 @@ def compare_mode(a, prec, h, lat, T, chi, chi_x, cutoff, chi_x_min, step, ref_re
                         if prec in BF16_PRODUCTS else "the mode's own MFMA peak",
                         "kernel": "gett (all tile variants; the autotuner may run a contraction on the FP32 "
                                   "kernel in split-BF16 modes)",
+                        "traffic": float(ctr["traffic_bytes_per_launch"]) if ctr else None,
+                        "traffic_unit": "HBM bytes per launch (all contraction launches, masked included)",
+                        "hbm_gbs_rocprof": float(ctr["hbm_gbs"]) if ctr else None,
+                        "mfma_util_rocprof": float(ctr["mfma_util"]) if ctr else None,
+                        "counter_workload": workload,
                         "launches_per_step": g_n,
                         "kernel_avg_us": 1e3 * g_ms / g_n if g_n and g_ms > 0 else None,
                         "algorithmic_bytes_per_launch": g_by / g_n if g_n else None,
