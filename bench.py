@@ -53,6 +53,10 @@ def parse():
                     help="with --prec fp64: comma-separated modes also timed on the same workload and samples "
                          "('none' for none); each reports its rate, its contraction roofline and its agreement "
                          "with fp64 and with the oracle under 'compare'")
+    ap.add_argument("--replay-step", action="store_true",
+                    help="after the timed steps, one more step without per-launch timing, in which the sampler "
+                         "replays its captured wave graph for every full wave after the second; reported under "
+                         "'graph_replay_step'")
     ap.add_argument("--cpu-full", action="store_true",
                     help="cpu_baseline also runs the oracle on the 8x8 D=4 lattice at chi=32 (norm, "
                          "environments, a few samples), all threads and one thread: several minutes")
@@ -452,7 +456,7 @@ def main():
     t0 = time.perf_counter()
     acc = {k: [0.0, 0.0] for k in phases}
     gemm_ms = gemm_flops = qr_ms = qr_gemm_flops = masked_ms = gemm_bytes = 0.0
-    launches = masked = 0
+    launches = masked = graphs = 0
     for i in range(a.steps):
         lz, rec = step(timing=not a.no_timing)
         for k, (sec, c) in rec.items():
@@ -466,6 +470,7 @@ def main():
             masked += c["masked_launches"]
             masked_ms += c["masked_ms"]
             gemm_bytes += c["gemm_bytes"]
+            graphs += c["graph_launches"]
         print(f"timed step {i} done ({time.perf_counter() - t0:.1f} s so far)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -508,6 +513,7 @@ def main():
         "phases": {k: {"ms_per_step": 1e3 * v[0] / a.steps, "tflop_per_step": v[1] / a.steps / 1e12,
                        "tflops": v[1] / v[0] / 1e12 if v[0] > 0 else None} for k, v in acc.items()},
         "log_abs_Z": lz,
+        "sampler_waves_replayed_per_step": graphs / a.steps,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[a.prec] if achieved else None,
                      "traffic": float(ctr["traffic_bytes_per_launch"]) if ctr else None,
@@ -535,8 +541,26 @@ def main():
         cu = torch.cat(used)
         out["config"]["svd_cutoff"] = cutoff
         out["config"]["chi_x_min"] = chi_x_min
+        vals, counts = torch.unique(cu.to(torch.int64).flatten(), return_counts=True)
         out["chi_x_used"] = {"mean": float(cu.mean()), "min": int(cu.min()), "max": int(cu.max()),
-                             "note": "largest kept bond per row of each sample's amplitude boundary"}
+                             "histogram": {str(int(v)): int(c) for v, c in zip(vals.cpu(), counts.cpu())},
+                             "note": "largest kept bond per row (rows 1..) of each sample's amplitude boundary"}
+    n_cfg = int(cfg.get("n_samples", 0))
+    if n_cfg > a.samples:
+        out["configured_samples"] = n_cfg
+        out["projected_total_s"] = n_cfg / out["value"]
+        out["projected_note"] = (f"time-boxed prefix: {a.samples} samples per step timed; the configured "
+                                 f"{n_cfg} samples would take n / value at this rate")
+    if a.replay_step:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rec = step(timing=False)
+        torch.cuda.synchronize()
+        dt_r = time.perf_counter() - t0
+        out["graph_replay_step"] = {"value": a.samples / dt_r, "unit": "samples/s", "ms": 1e3 * dt_r,
+                                    "waves_replayed": rec["sample"][1]["graph_launches"],
+                                    "note": "one step without per-launch event timing (timed steps issue every "
+                                            "launch from the host so that each is timed)"}
     oref = oracle_reference(a.config, chi) if cutoff == 0 else {}
     out["vs_oracle"] = marginal_errors(last.get("env"), oref, lz)
     modes = [m for m in a.compare.split(",") if m and m != "none" and m != a.prec]

@@ -142,7 +142,12 @@ tn_status tn_environments(tn_handle *h, const tn_peps *peps, const tn_opts *opts
                           double *rho1, double *zz_h, double *zz_v,
                           double *p2_h, double *p2_v);
 
-/* Draws samples first_sample .. first_sample+n-1 (paper's sampler).
+/* Draws samples first_sample .. first_sample+n-1 (paper's sampler).  Samples
+ * run in waves sized to the free device memory; the launch sequence of the
+ * second full wave is captured into a HIP graph and replayed for the later
+ * full waves of the call (same kernels, arguments and memory, so the results
+ * equal those of running every wave directly); with timing enabled
+ * (tn_set_timing) every wave runs directly, so that each launch is timed.
  *   uniforms : optional device [n][N] doubles in [0,1) (N = number of qubits):
  *              the uniform that draws qubit q of sample i; NULL = Philox4x64-10
  *              with key (seed, 3) and counter (q, first_sample+i, 0, 0), the
@@ -177,6 +182,44 @@ tn_status tn_sample(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
 tn_status tn_amplitude(tn_handle *h, const tn_peps *peps, const tn_opts *opts,
                        uint64_t first_sample, int64_t n, const uint8_t *bits,
                        double *log_p, double *arg);
+
+/* Belief propagation (BP) on the norm network <psi|psi> and the loop BP error
+ * (Methods, "Quantum Circuit Simulation": message tensors from BP, exact
+ * without loops; "The Boundary Matrix Product State Method": BP contraction
+ * and Eqs. avBPError, loopBPerror; Appendix, "Applying Gates to a Tensor
+ * Network State": message update and normalisation; "Computing the BP Error").
+ * Messages live on every bond in both directions as D x D matrices over the
+ * bond's ket and bra indices; they start as identity / sqrt(D) and are updated
+ * in parallel sweeps: the message a site sends through a bond is the site's
+ * (A, conj A) pair closed with its incoming messages on its other bonds, taken
+ * as its Hermitian part (exact arithmetic keeps it Hermitian; rounding would
+ * otherwise seed the update's unstable anti-Hermitian directions) and divided
+ * by its Frobenius norm.  Sweeps stop when the largest element change is below
+ * tol (checked every 4 sweeps) or after max_sweeps.  FP64 throughout; the
+ * state may be complex128 or complex64.
+ *   log_abs_Z, arg_Z : host, Z_BP = prod_sites Z_v / prod_bonds Z_e (Z_v the
+ *                      pair closed with all its messages, Z_e = sum m_{v->w}
+ *                      m_{w->v} elementwise);
+ *   sweeps, last_change : optional host outputs;
+ *   eps_mean, eps_loops, n_loops : optional host outputs of the loop BP error;
+ *                      the primitive loops are the bounded faces of the grid
+ *                      embedding (grid cells merged across absent bonds),
+ *                      ordered by their first site (row-major); eps_l = 1 -
+ *                      |lambda_1| / sum |lambda_i| over the eigenvalues of the
+ *                      loop's transfer matrix (BP messages on the loop's
+ *                      boundary, one loop bond cut open); eps_loops holds
+ *                      eps_capacity entries (TN_ERR_INVALID if there are more
+ *                      loops; n_loops is written first).  Bond dimensions up to
+ *                      16 (transfer matrices up to 256 x 256).
+ *   messages         : optional DEVICE buffer [rows*cols][4][Dm][Dm] complex128
+ *                      (Dm = the largest bond; legs up, left, down, right;
+ *                      message into the site; padded entries zero; legs
+ *                      without a bond hold e0 e0^T).
+ * Synchronises the stream.  TN_ERR_NUMERIC if a message vanishes or the
+ * eigenvalue iteration does not converge. */
+tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, double *log_abs_Z, double *arg_Z,
+                int *sweeps, double *last_change, double *eps_mean, double *eps_loops, int eps_capacity,
+                int *n_loops, void *messages);
 
 /* Sample-quality metrics from per-sample log q and log p (device [n] doubles,
  * natural logs), with w_i = p(x_i)/q(x_i) (Methods, the unbiased norm
@@ -226,12 +269,14 @@ const char *tn_last_error(const tn_handle *h);
  * samples that drew it: those launches skip the other samples' tiles, and are
  * counted apart (masked_launches, masked_ms), outside gemm_*.  gemm_bytes:
  * algorithmic operand bytes of the counted launches (A and B read once, C
- * written once, and read once more when accumulating).
+ * written once, and read once more when accumulating).  graph_launches: the
+ * sampler waves replayed from a captured launch graph (their contraction
+ * launches are included in the other counters).
  * Any pointer may be NULL. */
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches,
                           double *gemm_ms, double *qr_ms, int64_t *qr_launches,
                           double *qr_gemm_flops, int64_t *masked_launches, double *masked_ms,
-                          double *gemm_bytes);
+                          double *gemm_bytes, int64_t *graph_launches);
 
 /* Enables (1) or disables (0) per-launch HIP-event timing: an event pair is
  * recorded around every contraction and QR launch on the handle's stream and read
@@ -293,15 +338,24 @@ tn_status tn_test_svd(tn_handle *h, int n, int batch, const void *R, double cuto
  *   column indices and its blocks align with the tiles, else everything is
  *   computed. */
 tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter);
+/* tn_test_eig: eigenvalues of `batch` general complex n x n DEVICE matrices A
+ *   (complex128, row-major, read only; n <= 256) by the kernel of tn_bp's loop
+ *   error: lam (device [batch][n] complex128, unordered), eps (device [batch]
+ *   doubles: 1 - max|lambda| / sum|lambda|), info (device [batch] int32, 1 if
+ *   the iteration limit was reached).  Enqueued on the handle's stream. */
+tn_status tn_test_eig(tn_handle *h, int n, int batch, const void *A, void *lam, double *eps, int32_t *info);
 /* tn_test_sample_config: later tn_sample calls on this handle run waves of
  *   `wave` samples (0 = sized from free device memory), stop after the first
  *   `rows_limit` rows (0 = all; bits of later rows are 0, log_q is the partial
  *   sum, log_p is NaN), and, if log_cond is not NULL, write into it (device
  *   [n][N] doubles, same indexing as bits) log P(x_q | earlier qubits) for
  *   every drawn qubit q (entries of undrawn qubits are left as they were).
- *   Calling it with (0, 0, NULL) restores the defaults.  Errors:
- *   TN_ERR_INVALID for a NULL handle or negative wave / rows_limit. */
-tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond);
+ *   graphs = 1 (the default) replays the full waves after the second from the
+ *   captured launch graph of the second; 0 runs every wave directly.
+ *   Calling it with (0, 0, NULL, 1) restores the defaults.  Errors:
+ *   TN_ERR_INVALID for a NULL handle, negative wave / rows_limit or graphs
+ *   other than 0 and 1. */
+tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond, int graphs);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
            "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
            "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask",
-           "tn_test_sample_config", "tn_sample_stats_noalloc"]
+           "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig"]
 
 
 class TnError(RuntimeError):
@@ -81,7 +81,7 @@ def lib(path: Optional[str] = None):
     L.tn_last_error.argtypes = [vp]
     L.tn_last_error.restype = ctypes.c_char_p
     L.tn_get_counters.argtypes = [vp, dp, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64), dp,
-                                  ctypes.POINTER(i64), dp, dp]
+                                  ctypes.POINTER(i64), dp, dp, ctypes.POINTER(i64)]
     L.tn_set_timing.argtypes = [vp, ctypes.c_int]
     L.tn_set_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.tn_plan_report.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
@@ -94,11 +94,15 @@ def lib(path: Optional[str] = None):
     L.tn_test_svd.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, ctypes.c_int, vp, vp,
                               ctypes.c_int, vp]
     L.tn_test_set_mask.argtypes = [vp, vp, ctypes.c_char]
-    L.tn_test_sample_config.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.tn_test_sample_config.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.tn_bp.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.c_int, ctypes.c_double, dp, dp, ip, dp, dp, dp,
+                        ctypes.c_int, ip, vp]
+    L.tn_test_eig.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
               "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats",
-              "tn_test_sample_config", "tn_sample_stats_noalloc"):
+              "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -288,6 +292,48 @@ class Handle:
             res["z_is"] = zis
         return res
 
+    def bp(self, peps: Peps, max_sweeps: int = 1000, tol: float = 1e-13, loops: bool = True,
+           want_messages: bool = False):
+        """Belief propagation on the norm network: log|Z_BP|, arg Z_BP, sweeps,
+        last change and (with loops) the loop BP error eps with its per-loop
+        values; with want_messages also the final messages [N][4][Dm][Dm]
+        (see tn_bp)."""
+        import torch
+        la, ar, ch, em = (ctypes.c_double() for _ in range(4))
+        sw, nl = ctypes.c_int(), ctypes.c_int()
+        L = peps.lattice
+        cap = max(1, (L.rows - 1) * (L.cols - 1))
+        eps = (ctypes.c_double * cap)()
+        msgs = None
+        if want_messages:
+            dm = int(max(1, np.max(L.dim_h) if L.dim_h.size else 1, np.max(L.dim_v) if L.dim_v.size else 1))
+            msgs = torch.empty((L.rows * L.cols, 4, dm, dm), dtype=torch.complex128, device=peps.tensors[0].device)
+        self._check(lib().tn_bp(self.h, ctypes.byref(peps.c), int(max_sweeps), float(tol), ctypes.byref(la),
+                                ctypes.byref(ar), ctypes.byref(sw), ctypes.byref(ch),
+                                ctypes.byref(em) if loops else None, eps if loops else None, cap,
+                                ctypes.byref(nl) if loops else None,
+                                ctypes.c_void_p(msgs.data_ptr()) if msgs is not None else None))
+        res = dict(log_abs_Z=la.value, arg_Z=ar.value, sweeps=sw.value, last_change=ch.value)
+        if loops:
+            res["eps"] = em.value
+            res["eps_loops"] = np.array(eps[:nl.value])
+        if msgs is not None:
+            res["messages"] = msgs
+        return res
+
+    def test_eig(self, A):
+        """Eigenvalues (unordered), eps and info of complex128 matrices A
+        [batch][n][n] by the loop-error eigenvalue kernel (see tn_test_eig)."""
+        import torch
+        A = A.to(torch.complex128).contiguous()
+        batch, n = A.shape[0], A.shape[1]
+        lam = torch.empty((batch, n), dtype=torch.complex128, device=A.device)
+        eps = torch.empty((batch,), dtype=torch.float64, device=A.device)
+        info = torch.empty((batch,), dtype=torch.int32, device=A.device)
+        self._check(lib().tn_test_eig(self.h, n, batch, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                      ctypes.c_void_p(eps.data_ptr()), ctypes.c_void_p(info.data_ptr())))
+        return lam, eps, info
+
     def sample_stats_noalloc(self, log_q, log_p, log_Z: float, bits=None, out=None, z_is=None):
         """As sample_stats through tn_sample_stats_noalloc: the library allocates
         nothing (partials in its fixed scratch); `out` (device float64 [3]) and
@@ -322,13 +368,14 @@ class Handle:
 
     def counters(self):
         f, ms, qms, qf, mms, gb = (ctypes.c_double() for _ in range(6))
-        n, qn, mn = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        n, qn, mn, gl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().tn_get_counters(self.h, ctypes.byref(f), ctypes.byref(n), ctypes.byref(ms),
                                           ctypes.byref(qms), ctypes.byref(qn), ctypes.byref(qf),
-                                          ctypes.byref(mn), ctypes.byref(mms), ctypes.byref(gb)))
+                                          ctypes.byref(mn), ctypes.byref(mms), ctypes.byref(gb),
+                                          ctypes.byref(gl)))
         return dict(gemm_flops=f.value, gemm_launches=n.value, gemm_ms=ms.value, qr_ms=qms.value,
                     qr_launches=qn.value, qr_gemm_flops=qf.value, masked_launches=mn.value,
-                    masked_ms=mms.value, gemm_bytes=gb.value)
+                    masked_ms=mms.value, gemm_bytes=gb.value, graph_launches=gl.value)
 
     def set_timing(self, on: bool):
         self._check(lib().tn_set_timing(self.h, 1 if on else 0))
@@ -345,13 +392,14 @@ class Handle:
         return buf.value.decode()
 
     # ---------------------------------------------------------------- test hooks
-    def test_sample_config(self, wave: int = 0, rows_limit: int = 0, log_cond=None):
+    def test_sample_config(self, wave: int = 0, rows_limit: int = 0, log_cond=None, graphs: bool = True):
         """Later samples run in waves of `wave` (0 = automatic), stop after
-        `rows_limit` rows (0 = all) and write log P(x_q | earlier) into
-        log_cond (device float64 [n][N]) if given (see tn_test_sample_config).
-        The tensor must stay alive while the setting is in force."""
+        `rows_limit` rows (0 = all), write log P(x_q | earlier) into log_cond
+        (device float64 [n][N]) if given, and replay full waves from a captured
+        graph unless graphs is False (see tn_test_sample_config).  The tensor
+        must stay alive while the setting is in force."""
         ptr = ctypes.c_void_p(log_cond.data_ptr()) if log_cond is not None else None
-        self._check(lib().tn_test_sample_config(self.h, int(wave), int(rows_limit), ptr))
+        self._check(lib().tn_test_sample_config(self.h, int(wave), int(rows_limit), ptr, 1 if graphs else 0))
 
     def test_contract(self, prec: str, ia: str, A, ib: str, B, ic: str, C, conjA=False, conjB=False,
                       accumulate=False, cfg: int = -1, ksplit: int = 0, mask=None, mask_letter: str = "z"):

@@ -53,7 +53,7 @@ struct tn_handle {
     std::string cache_key;
     PepsDev cache_peps;
     // sampler test hooks (tn_test_sample_config)
-    int sample_wave = 0, sample_rows_limit = 0;
+    int sample_wave = 0, sample_rows_limit = 0, sample_graphs = 1;
     double *sample_log_cond = nullptr;
 };
 
@@ -346,9 +346,59 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
         so.wave = h->sample_wave;
         so.rows_limit = h->sample_rows_limit;
         so.log_cond = h->sample_log_cond;
+        so.graphs = h->sample_graphs;
         if (so.svd_cutoff > 0 && o->chi_x > tnk::SVD_NMAX)
             throw TnError(ST_UNSUPPORTED, "svd_cutoff needs chi_x <= " + std::to_string(tnk::SVD_NMAX));
         sample(*h->E, h->cache_peps, S, so, first, n, uniforms, bits, log_q, log_p, chi_x_used);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
+tn_status tn_bp(tn_handle *h, const tn_peps *p, int max_sweeps, double tol, double *log_abs_Z, double *arg_Z,
+                int *sweeps, double *last_change, double *eps_mean, double *eps_loops, int eps_capacity,
+                int *n_loops, void *messages) {
+    try {
+        begin(h, nullptr);
+        tn_opts dflt;
+        tn_default_opts(&dflt);
+        validate(p, &dflt);
+        if (max_sweeps < 1 || !(tol >= 0.0)) throw TnError(ST_INVALID, "max_sweeps must be >= 1 and tol >= 0");
+        if (!log_abs_Z || !arg_Z) throw TnError(ST_INVALID, "null output");
+        if (eps_loops && eps_capacity < 0) throw TnError(ST_INVALID, "eps_capacity must be >= 0");
+        Engine &E = *h->E;
+        E.set_prec(tnk::P_FP64);
+        PepsDev P = stage(E, p);
+        BpOpts bo;
+        bo.max_sweeps = max_sweeps;
+        bo.tol = tol;
+        bo.loops = eps_mean || eps_loops || n_loops;
+        bo.messages = messages;
+        BpResult r;
+        try {
+            bp_contract(E, P, bo, r);
+        } catch (...) {
+            unstage(E, P);
+            throw;
+        }
+        unstage(E, P);
+        E.sync();
+        *log_abs_Z = r.log_abs;
+        *arg_Z = r.arg;
+        if (sweeps) *sweeps = r.sweeps;
+        if (last_change) *last_change = r.delta;
+        if (eps_mean) *eps_mean = r.eps_mean;
+        if (n_loops) *n_loops = (int)r.eps.size();
+        if (r.eig_info) throw TnError(ST_NUMERIC, "loop eigenvalue iteration did not converge");
+        if (eps_loops) {
+            if ((int)r.eps.size() > eps_capacity)
+                throw TnError(ST_INVALID, "eps_loops holds " + std::to_string(eps_capacity) + " entries, " +
+                                              std::to_string(r.eps.size()) + " loops found");
+            std::copy(r.eps.begin(), r.eps.end(), eps_loops);
+        }
         return TN_OK;
     } catch (const TnError &e) {
         return fail(h, e);
@@ -449,7 +499,7 @@ const char *tn_last_error(const tn_handle *h) { return h ? h->err.c_str() : "nul
 
 tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_launches, double *gemm_ms,
                           double *qr_ms, int64_t *qr_launches, double *qr_gemm_flops, int64_t *masked_launches,
-                          double *masked_ms, double *gemm_bytes) {
+                          double *masked_ms, double *gemm_bytes, int64_t *graph_launches) {
     if (!h || !h->E) return TN_ERR_INVALID;
     try {
         const_cast<Engine *>(h->E.get())->collect_timing();
@@ -466,6 +516,7 @@ tn_status tn_get_counters(const tn_handle *h, double *gemm_flops, int64_t *gemm_
     if (masked_launches) *masked_launches = c.masked_launches;
     if (masked_ms) *masked_ms = c.masked_ms;
     if (gemm_bytes) *gemm_bytes = c.gemm_bytes;
+    if (graph_launches) *graph_launches = c.graph_launches;
     return TN_OK;
 }
 
@@ -556,16 +607,39 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
     }
 }
 
-tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond) {
+tn_status tn_test_sample_config(tn_handle *h, int wave, int rows_limit, double *log_cond, int graphs) {
     if (!h || !h->E) return TN_ERR_INVALID;
-    if (wave < 0 || rows_limit < 0) {
-        h->err = "tn_test_sample_config: wave and rows_limit must be >= 0";
+    if (wave < 0 || rows_limit < 0 || graphs < 0 || graphs > 1) {
+        h->err = "tn_test_sample_config: wave and rows_limit must be >= 0, graphs 0 or 1";
         return TN_ERR_INVALID;
     }
     h->sample_wave = wave;
     h->sample_rows_limit = rows_limit;
     h->sample_log_cond = log_cond;
+    h->sample_graphs = graphs;
     return TN_OK;
+}
+
+tn_status tn_test_eig(tn_handle *h, int n, int batch, const void *A, void *lam, double *eps, int32_t *info) {
+    try {
+        if (!h || !h->E) throw TnError(ST_INVALID, "null handle");
+        h->err.clear();
+        TN_HIP(hipSetDevice(h->device));
+        if (n < 1 || n > tnk::BP_EIG_NMAX || batch < 0) throw TnError(ST_INVALID, "tn_test_eig: bad n or batch");
+        if (!A || !lam || !eps || !info) throw TnError(ST_INVALID, "tn_test_eig: null pointer");
+        Engine &E = *h->E;
+        const size_t bytes = (size_t)batch * n * n * 16;
+        void *w = E.raw(bytes);
+        TN_HIP(hipMemcpyAsync(w, A, bytes, hipMemcpyDeviceToDevice, E.s));
+        const hipError_t e = tnk::launch_eig(w, n, batch, lam, eps, info, E.s);
+        E.unraw(w);
+        TN_HIP(e);
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
 }
 
 tn_status tn_test_set_mask(tn_handle *h, const int32_t *mask, char letter) {

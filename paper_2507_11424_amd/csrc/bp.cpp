@@ -1,0 +1,351 @@
+// Belief propagation on the norm network <psi|psi> and the loop BP error
+// (Methods, "Quantum Circuit Simulation" -- message tensors by BP -- and "The
+// Boundary Matrix Product State Method" -- BP contraction, Eqs. avBPError and
+// loopBPerror; Appendix, "Applying Gates to a Tensor Network State" -- the
+// message update and its normalisation -- and "Computing the BP Error").
+//
+// Every site tensor is embedded in a uniform layout A[z][s][u][l][d][r] with
+// all bond legs padded (with zeros) to the largest bond Dm; messages are
+// msg[z][leg][k][k'] (into site z through leg, ket index k, bra index k'),
+// e0 e0^T on legs without a bond, so padded entries never contribute.  A
+// parallel sweep computes, for each of the four legs, the message every site
+// sends through it -- the pair (A, conj A) closed with the site's other three
+// incoming messages, three batched contractions over all sites and one with
+// conj(A) -- then k_bp_update takes each one's Hermitian part, normalises it to
+// unit Frobenius norm and stores it as the neighbour's incoming message.
+// FP64 throughout.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "tn_core.hpp"
+
+namespace tnb {
+
+namespace {
+
+constexpr int NLEG = 4;  // 0 up, 1 left, 2 down, 3 right (axes 1..4 of a site tensor)
+const char KET[NLEG] = {'a', 'b', 'c', 'd'};
+const char BRA[NLEG] = {'e', 'f', 'g', 'h'};
+const int DR[NLEG] = {-1, 0, 1, 0}, DC[NLEG] = {0, -1, 0, 1};
+
+// View of the incoming messages of one leg: [z][k][k'] inside msg[z][leg][k][k'].
+Op msg_op(const Ten &msg, int leg, int N, int Dm) {
+    Op o;
+    o.p = static_cast<const char *>(msg.p) + (size_t)leg * Dm * Dm * msg.esz;
+    o.esz = msg.esz;
+    o.idx = std::string("z") + KET[leg] + BRA[leg];
+    o.dims = {N, Dm, Dm};
+    o.str = {(int64_t)NLEG * Dm * Dm, Dm, 1};
+    return o;
+}
+
+// The pair (A, conj A) of every site with the incoming messages on all legs not
+// in `keep` contracted; result [z] + (ket, bra) letters of the kept legs in
+// order, written to `out` (dense, dims {N, Dm, Dm, ...}).
+void pair_closed(Engine &E, const Ten &A, const Ten &msg, const std::vector<int> &keep, const Op &out, int N,
+                 int Dm) {
+    std::string cur = "zsabcd";
+    Ten t;  // current intermediate (empty: A itself)
+    for (int leg = 0; leg < NLEG; ++leg) {
+        if (std::find(keep.begin(), keep.end(), leg) != keep.end()) continue;
+        std::string nxt;
+        for (char ch : cur)
+            if (ch != KET[leg]) nxt += ch;
+        nxt += BRA[leg];
+        Ten r = E.contract_new(t.p ? op(t, cur) : op(A, cur), msg_op(msg, leg, N, Dm), nxt);
+        if (t.p) E.drop(t);
+        t = r;
+        cur = nxt;
+    }
+    // close with conj(A) over s and the bra legs of the contracted legs
+    E.contract(op(t, cur), op(A, "zsefgh", true), out);
+    E.drop(t);
+}
+
+// Faces of the planar grid embedding (grid cells merged across absent bonds,
+// those not connected to the outside), each as the cycle of its boundary
+// sites: (site, in_leg, out_leg) in walk order, starting at the smallest site
+// (row-major) and stepping first to its smaller boundary neighbour.
+struct LoopSite { int z, lin, lout; };
+std::vector<std::vector<LoopSite>> faces(const PepsDev &P) {
+    const int rows = P.rows, cols = P.cols;
+    auto hb = [&](int r, int c) { return c + 1 < cols && P.at(r, c).d[4] > 1; };
+    auto vb = [&](int r, int c) { return r + 1 < rows && P.at(r, c).d[3] > 1; };
+    std::vector<std::vector<LoopSite>> loops;
+    const int nr = rows - 1, nc = cols - 1;
+    if (nr <= 0 || nc <= 0) return loops;
+    const int OUT = nr * nc;
+    std::vector<int> parent(OUT + 1);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+    };
+    auto cell = [&](int i, int j) { return (i >= 0 && i < nr && j >= 0 && j < nc) ? i * nc + j : OUT; };
+    auto unite = [&](int a, int b) { parent[find(a)] = find(b); };
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) {
+            if (!hb(i, j)) unite(cell(i, j), cell(i - 1, j));
+            if (!hb(i + 1, j)) unite(cell(i, j), cell(i + 1, j));
+            if (!vb(i, j)) unite(cell(i, j), cell(i, j - 1));
+            if (!vb(i, j + 1)) unite(cell(i, j), cell(i, j + 1));
+        }
+    std::map<int, std::vector<std::pair<int, int>>> groups;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) {
+            const int root = find(cell(i, j));
+            if (root != find(OUT)) groups[root].push_back({i, j});
+        }
+    for (auto &kv : groups) {
+        std::vector<int> in(nr * nc, 0);
+        for (auto &ij : kv.second) in[ij.first * nc + ij.second] = 1;
+        auto inside = [&](int i, int j) { return i >= 0 && i < nr && j >= 0 && j < nc && in[i * nc + j]; };
+        std::map<int, std::vector<int>> adj;  // site -> boundary neighbours
+        auto add = [&](int r1, int c1, int r2, int c2) {
+            adj[r1 * cols + c1].push_back(r2 * cols + c2);
+            adj[r2 * cols + c2].push_back(r1 * cols + c1);
+        };
+        for (auto &ij : kv.second) {
+            const int i = ij.first, j = ij.second;
+            if (!inside(i - 1, j)) add(i, j, i, j + 1);
+            if (!inside(i + 1, j)) add(i + 1, j, i + 1, j + 1);
+            if (!inside(i, j - 1)) add(i, j, i + 1, j);
+            if (!inside(i, j + 1)) add(i, j + 1, i + 1, j + 1);
+        }
+        for (auto &a : adj)
+            if (a.second.size() != 2) throw TnError(ST_UNSUPPORTED, "a face of the lattice is not a simple cycle");
+        const int start = adj.begin()->first;
+        std::vector<int> cyc = {start};
+        int prev = -1, cur = start;
+        std::vector<int> &s0 = adj[start];
+        int nxt = std::min(s0[0], s0[1]);
+        while (nxt != start) {
+            cyc.push_back(nxt);
+            prev = cur;
+            cur = nxt;
+            const std::vector<int> &a = adj[cur];
+            nxt = a[0] != prev ? a[0] : a[1];
+        }
+        auto leg_to = [&](int a, int b) {
+            const int dr = b / cols - a / cols, dc = b % cols - a % cols;
+            for (int l = 0; l < NLEG; ++l)
+                if (DR[l] == dr && DC[l] == dc) return l;
+            throw TnError(ST_SHAPE, "face walk between non-neighbours");
+        };
+        const int L = (int)cyc.size();
+        std::vector<LoopSite> lp(L);
+        for (int k = 0; k < L; ++k)
+            lp[k] = {cyc[k], leg_to(cyc[k], cyc[(k + L - 1) % L]), leg_to(cyc[k], cyc[(k + 1) % L])};
+        loops.push_back(lp);
+    }
+    std::sort(loops.begin(), loops.end(),
+              [](const std::vector<LoopSite> &a, const std::vector<LoopSite> &b) { return a[0].z < b[0].z; });
+    return loops;
+}
+
+}  // namespace
+
+void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
+    const int rows = P.rows, cols = P.cols, N = rows * cols;
+    int Dm = 1;
+    for (const Ten &t : P.site)
+        for (int k = 1; k <= 4; ++k) Dm = std::max(Dm, t.d[k]);
+    const int n2 = Dm * Dm;
+    // uniform padded tensors
+    Ten A = E.make({N, 2, Dm, Dm, Dm, Dm});
+    TN_HIP(tnk::launch_fill(A.p, A.esz, A.numel(), 0.0, 0.0, E.s));
+    const size_t per = (size_t)2 * Dm * Dm * Dm * Dm;
+    for (int z = 0; z < N; ++z) {
+        const Ten &t = P.site[z];
+        TN_HIP(tnk::launch_bp_embed(t.p, t.d[0], t.d[1], t.d[2], t.d[3], t.d[4],
+                                    static_cast<char *>(A.p) + z * per * 16, Dm, E.s));
+    }
+    // neighbour table and initial messages: identity / sqrt(D) on bonds, e0 e0^T elsewhere
+    std::vector<int> hn((size_t)N * NLEG, -1);
+    std::vector<double> hm((size_t)N * NLEG * n2 * 2, 0.0);
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) {
+            const int z = r * cols + c;
+            for (int leg = 0; leg < NLEG; ++leg) {
+                const int D = P.at(r, c).d[leg + 1];
+                const int r2 = r + DR[leg], c2 = c + DC[leg];
+                const bool bond = D > 1 && r2 >= 0 && r2 < rows && c2 >= 0 && c2 < cols;
+                double *m = hm.data() + ((size_t)z * NLEG + leg) * n2 * 2;
+                if (bond) {
+                    hn[(size_t)z * NLEG + leg] = r2 * cols + c2;
+                    for (int i = 0; i < D; ++i) m[(i * Dm + i) * 2] = 1.0 / std::sqrt((double)D);
+                } else {
+                    m[0] = 1.0;
+                }
+            }
+        }
+    Ten msg = E.make({N, NLEG, Dm, Dm});
+    int *nbr = static_cast<int *>(E.raw(hn.size() * sizeof(int)));
+    Ten out = E.make({NLEG, N, Dm, Dm});
+    double *dmax = static_cast<double *>(E.raw((size_t)N * NLEG * 8));
+    double *dscal = static_cast<double *>(E.raw(64));
+    auto cleanup = [&]() {
+        E.drop(A);
+        E.drop(msg);
+        E.drop(out);
+        E.unraw(nbr);
+        E.unraw(dmax);
+        E.unraw(dscal);
+    };
+    try {
+        TN_HIP(hipMemcpyAsync(msg.p, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, E.s));
+        TN_HIP(hipMemcpyAsync(nbr, hn.data(), hn.size() * sizeof(int), hipMemcpyHostToDevice, E.s));
+        E.sync();  // the host arrays above are released on return
+        auto out_op = [&](int leg) {
+            Op q;
+            q.p = static_cast<char *>(out.p) + (size_t)leg * N * n2 * out.esz;
+            q.esz = out.esz;
+            q.idx = std::string("z") + KET[leg] + BRA[leg];
+            q.dims = {N, Dm, Dm};
+            q.str = {(int64_t)n2, Dm, 1};
+            return q;
+        };
+        double delta = INFINITY;
+        int sweep = 0;
+        while (sweep < o.max_sweeps) {
+            for (int leg = 0; leg < NLEG; ++leg) pair_closed(E, A, msg, {leg}, out_op(leg), N, Dm);
+            TN_HIP(tnk::launch_bp_update(out.p, msg.p, nbr, N, Dm, dmax, dscal, E.s));
+            ++sweep;
+            if (sweep % 4 == 0 || sweep == o.max_sweeps) {
+                TN_HIP(hipMemcpyAsync(&delta, dscal, 8, hipMemcpyDeviceToHost, E.s));
+                E.sync();
+                if (!(delta < INFINITY)) throw TnError(ST_NUMERIC, "BP message vanished or overflowed");
+                if (delta < o.tol) break;
+            }
+        }
+        res.sweeps = sweep;
+        res.delta = delta;
+        // Z_BP from the final messages
+        pair_closed(E, A, msg, {3}, out_op(3), N, Dm);
+        double *zv = static_cast<double *>(E.raw((size_t)N * 16));
+        double *ze = static_cast<double *>(E.raw((size_t)N * 32));
+        TN_HIP(tnk::launch_bp_free_energy(static_cast<char *>(out.p) + (size_t)3 * N * n2 * 16, msg.p, nbr, N, Dm,
+                                          zv, ze, dscal, E.s));
+        double h2[2];
+        TN_HIP(hipMemcpyAsync(h2, dscal, 16, hipMemcpyDeviceToHost, E.s));
+        E.sync();
+        E.unraw(zv);
+        E.unraw(ze);
+        res.log_abs = h2[0];
+        res.arg = h2[1];
+        if (o.messages) TN_HIP(hipMemcpyAsync(o.messages, msg.p, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
+        // loop BP error
+        res.eps.clear();
+        res.eps_mean = 0.0;
+        res.eig_info = 0;
+        if (o.loops) {
+            const std::vector<std::vector<LoopSite>> loops = faces(P);
+            if (!loops.empty()) {
+                if (n2 > tnk::BP_EIG_NMAX)
+                    throw TnError(ST_UNSUPPORTED, "loop BP error supports bonds up to " +
+                                                      std::to_string((int)std::sqrt((double)tnk::BP_EIG_NMAX)));
+                // pair tensors of every site for the leg pairs the loops use: [z][a][a'][b][b'], a < b
+                int pid[NLEG][NLEG];
+                for (auto &x : pid)
+                    for (int &y : x) y = -1;
+                std::vector<std::pair<int, int>> pairs;
+                for (auto &lp : loops)
+                    for (auto &s : lp) {
+                        const int a = std::min(s.lin, s.lout), b = std::max(s.lin, s.lout);
+                        if (pid[a][b] < 0) {
+                            pid[a][b] = (int)pairs.size();
+                            pairs.push_back({a, b});
+                        }
+                    }
+                Ten pt = E.make({(int)pairs.size(), N, Dm, Dm, Dm, Dm});
+                const size_t pstride = (size_t)N * n2 * n2;
+                for (size_t k = 0; k < pairs.size(); ++k) {
+                    Op q;
+                    q.p = static_cast<char *>(pt.p) + k * pstride * 16;
+                    q.esz = 16;
+                    q.idx = std::string("z") + KET[pairs[k].first] + BRA[pairs[k].first] + KET[pairs[k].second] +
+                            BRA[pairs[k].second];
+                    q.dims = {N, Dm, Dm, Dm, Dm};
+                    q.str = {(int64_t)n2 * n2, (int64_t)Dm * n2, n2, Dm, 1};
+                    pair_closed(E, A, msg, {pairs[k].first, pairs[k].second}, q, N, Dm);
+                }
+                // loops grouped by length: gather [loop][k] matrices, multiply along the walk
+                std::map<int, std::vector<int>> bylen;
+                for (int i = 0; i < (int)loops.size(); ++i) bylen[(int)loops[i].size()].push_back(i);
+                std::vector<double> heps(loops.size(), 0.0);
+                std::vector<int> hinfo(loops.size(), 0);
+                for (auto &g : bylen) {
+                    const int L = g.first, nl = (int)g.second.size();
+                    std::vector<int64_t> hoff((size_t)nl * L);
+                    std::vector<int> htr((size_t)nl * L);
+                    for (int i = 0; i < nl; ++i)
+                        for (int k = 0; k < L; ++k) {
+                            const LoopSite &s = loops[g.second[i]][k];
+                            const int a = std::min(s.lin, s.lout), b = std::max(s.lin, s.lout);
+                            hoff[(size_t)i * L + k] = (int64_t)pid[a][b] * pstride + (int64_t)s.z * n2 * n2;
+                            htr[(size_t)i * L + k] = s.lin == a ? 0 : 1;  // walk enters through the larger leg
+                        }
+                    int64_t *doff = static_cast<int64_t *>(E.raw(hoff.size() * 8));
+                    int *dtr = static_cast<int *>(E.raw(htr.size() * 4));
+                    Ten mats = E.make({nl, L, n2, n2});
+                    Ten X = E.make({nl, n2, n2}), Y = E.make({nl, n2, n2});
+                    double *deps = static_cast<double *>(E.raw((size_t)nl * 8));
+                    int *dinfo = static_cast<int *>(E.raw((size_t)nl * 4));
+                    double *lam = static_cast<double *>(E.raw((size_t)nl * n2 * 16));
+                    TN_HIP(hipMemcpyAsync(doff, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice, E.s));
+                    TN_HIP(hipMemcpyAsync(dtr, htr.data(), htr.size() * 4, hipMemcpyHostToDevice, E.s));
+                    TN_HIP(tnk::launch_gather_mats(pt.p, doff, dtr, nl * L, n2, mats.p, E.s));
+                    auto mat_op = [&](int k, const std::string &idx) {
+                        Op q;
+                        q.p = static_cast<char *>(mats.p) + (size_t)k * n2 * n2 * 16;
+                        q.esz = 16;
+                        q.idx = idx;
+                        q.dims = {nl, n2, n2};
+                        q.str = {(int64_t)L * n2 * n2, n2, 1};
+                        return q;
+                    };
+                    // X = M_0 M_1 ... M_{L-1}
+                    E.contract(mat_op(0, "xij"), mat_op(1, "xjk"), op(X, "xik"));
+                    for (int k = 2; k < L; ++k) {
+                        E.contract(op(X, "xij"), mat_op(k, "xjk"), op(Y, "xik"));
+                        std::swap(X, Y);
+                    }
+                    TN_HIP(tnk::launch_eig(X.p, n2, nl, lam, deps, dinfo, E.s));
+                    std::vector<double> e(nl);
+                    std::vector<int> inf(nl);
+                    TN_HIP(hipMemcpyAsync(e.data(), deps, (size_t)nl * 8, hipMemcpyDeviceToHost, E.s));
+                    TN_HIP(hipMemcpyAsync(inf.data(), dinfo, (size_t)nl * 4, hipMemcpyDeviceToHost, E.s));
+                    E.sync();
+                    for (int i = 0; i < nl; ++i) {
+                        heps[g.second[i]] = e[i];
+                        hinfo[g.second[i]] = inf[i];
+                    }
+                    E.unraw(doff);
+                    E.unraw(dtr);
+                    E.unraw(deps);
+                    E.unraw(dinfo);
+                    E.unraw(lam);
+                    E.drop(mats);
+                    E.drop(X);
+                    E.drop(Y);
+                }
+                E.drop(pt);
+                res.eps = heps;
+                double s = 0.0;
+                for (double v : heps) s += v;
+                res.eps_mean = s / (double)heps.size();
+                for (int v : hinfo) res.eig_info |= v;
+            }
+        }
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+}
+
+}  // namespace tnb

@@ -38,19 +38,32 @@ Pool::~Pool() {
     for (auto &kv : size_) (void)hipFree(kv.first);
 }
 
+void *Pool::take(std::multimap<size_t, void *> &fl, size_t bytes) {
+    auto it = fl.lower_bound(bytes);
+    if (it != fl.end() && it->first <= 2 * bytes + (1 << 20)) {
+        void *p = it->second;
+        fl.erase(it);
+        return p;
+    }
+    return nullptr;
+}
+
 void *Pool::get(size_t bytes) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~size_t(255);
-    auto it = free_.lower_bound(bytes);
-    if (it != free_.end() && it->first <= 2 * bytes + (1 << 20)) {
-        void *p = it->second;
-        free_.erase(it);
+    if (arena_) {
+        if (void *p = take(afree_, bytes)) return p;
+        if (void *p = take(free_, bytes)) {
+            ablocks_.push_back(p);
+            return p;
+        }
+    } else if (void *p = take(free_, bytes)) {
         return p;
     }
     size_t alloc = bytes;
     if (alloc > (1 << 20)) alloc = (alloc + (1 << 20) - 1) & ~size_t((1 << 20) - 1);
     if (cap_ && held_ + alloc > cap_) {
-        trim();
+        if (!arena_) trim();  // (trim synchronises the device: not while capturing)
         if (held_ + alloc > cap_)
             throw TnError(ST_OOM, "workspace cap reached (" + std::to_string(held_ + alloc) + " > " +
                                       std::to_string(cap_) + " bytes)");
@@ -59,6 +72,7 @@ void *Pool::get(size_t bytes) {
     hipError_t e = hipMalloc(&p, alloc);
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        if (arena_) throw TnError(ST_OOM, "hipMalloc of " + std::to_string(alloc) + " bytes failed (capture)");
         trim();
         e = hipMalloc(&p, alloc);
         if (e != hipSuccess) {
@@ -68,6 +82,7 @@ void *Pool::get(size_t bytes) {
     }
     held_ += alloc;
     size_[p] = alloc;
+    if (arena_) ablocks_.push_back(p);
     return p;
 }
 
@@ -75,7 +90,32 @@ void Pool::put(void *p) {
     if (!p) return;
     auto it = size_.find(p);
     if (it == size_.end()) return;
+    if (arena_ && std::find(ablocks_.begin(), ablocks_.end(), p) != ablocks_.end()) {
+        afree_.emplace(it->second, p);
+        return;
+    }
     free_.emplace(it->second, p);
+}
+
+void Pool::begin_arena() {
+    arena_ = true;
+    afree_.clear();
+    ablocks_.clear();
+}
+
+std::vector<void *> Pool::end_arena() {
+    arena_ = false;
+    afree_.clear();
+    std::vector<void *> b;
+    b.swap(ablocks_);
+    return b;
+}
+
+void Pool::release(const std::vector<void *> &blocks) {
+    for (void *p : blocks) {
+        auto it = size_.find(p);
+        if (it != size_.end()) free_.emplace(it->second, p);
+    }
 }
 
 void Pool::trim() {
@@ -95,6 +135,7 @@ Engine::Engine(int dev, hipStream_t st, size_t cap) : s(st), device(dev), pool_(
 
 Engine::~Engine() {
     (void)hipStreamSynchronize(s);
+    if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
     for (auto &kv : plans_)
         if (kv.second->dev) (void)hipFree(kv.second->dev);
     for (auto &e : ev_) {
@@ -103,8 +144,17 @@ Engine::~Engine() {
     }
 }
 
-// Index (not reference) of a fresh event pair: nested calls may grow ev_.
-size_t Engine::next_pair(int kind) {
+// A fresh event pair (deque storage: nested calls that add pairs keep references valid).
+Engine::EvPair *Engine::next_pair(int kind) {
+    if (cap_pairs_) {  // stream capture: the pair belongs to the graph being captured
+        EvPair e{};
+        TN_HIP(hipEventCreate(&e.a));
+        TN_HIP(hipEventCreate(&e.b));
+        e.kind = kind;
+        e.plan = nullptr;
+        cap_pairs_->push_back(e);
+        return &cap_pairs_->back();
+    }
     if (ev_used_ == ev_.size()) {
         EvPair e{};
         TN_HIP(hipEventCreate(&e.a));
@@ -114,24 +164,116 @@ size_t Engine::next_pair(int kind) {
     EvPair &e = ev_[ev_used_];
     e.kind = kind;
     e.plan = nullptr;
-    return ev_used_++;
+    ++ev_used_;
+    return &e;
+}
+
+void Engine::add_pair_time(const EvPair &e) {
+    float ms = 0.f;
+    TN_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    if (e.kind == 0) ctr.gemm_ms += ms;
+    else if (e.kind == 2) ctr.masked_ms += ms;
+    else ctr.qr_ms += ms;
+    if (e.plan && e.kind != 2) {
+        e.plan->ms += ms;
+        e.plan->calls += 1;
+    }
 }
 
 void Engine::collect_timing() {
     if (ev_used_ == 0) return;
     sync();
-    for (size_t i = 0; i < ev_used_; ++i) {
-        float ms = 0.f;
-        TN_HIP(hipEventElapsedTime(&ms, ev_[i].a, ev_[i].b));
-        if (ev_[i].kind == 0) ctr.gemm_ms += ms;
-        else if (ev_[i].kind == 2) ctr.masked_ms += ms;
-        else ctr.qr_ms += ms;
-        if (ev_[i].plan && ev_[i].kind != 2) {
-            ev_[i].plan->ms += ms;
-            ev_[i].plan->calls += 1;
+    for (size_t i = 0; i < ev_used_; ++i) add_pair_time(ev_[i]);
+    ev_used_ = 0;
+}
+
+namespace {
+Counters count_delta(const Counters &a, const Counters &b) {  // a - b, counts only (no times)
+    Counters d;
+    d.gemm_flops = a.gemm_flops - b.gemm_flops;
+    d.gemm_launches = a.gemm_launches - b.gemm_launches;
+    d.qr_launches = a.qr_launches - b.qr_launches;
+    d.qr_gemm_flops = a.qr_gemm_flops - b.qr_gemm_flops;
+    d.masked_launches = a.masked_launches - b.masked_launches;
+    d.gemm_bytes = a.gemm_bytes - b.gemm_bytes;
+    return d;
+}
+}  // namespace
+
+void Engine::begin_capture(Captured &g) {
+    if (cap_pairs_) throw TnError(ST_INVALID, "nested stream capture");
+    g = Captured();
+    // the null stream cannot be captured: record on a private stream (nothing
+    // runs during the capture) and launch the graph on the handle's stream
+    if (!cap_stream_) TN_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+    user_stream_ = s;
+    const hipError_t e = hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw TnError(ST_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    s = cap_stream_;
+    pool_.begin_arena();
+    cap_ctr0_ = ctr;
+    cap_pairs_ = &g.pairs;
+}
+
+bool Engine::end_capture(Captured &g, bool ok) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap_stream_, &graph);
+    s = user_stream_;
+    cap_pairs_ = nullptr;
+    std::vector<void *> blocks = pool_.end_arena();
+    const Counters d = count_delta(ctr, cap_ctr0_);
+    ctr = cap_ctr0_;  // nothing ran yet: each launch adds the delta
+    if (ok && e == hipSuccess && graph) {
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        if (e == hipSuccess) {
+            g.blocks = std::move(blocks);
+            g.delta = d;
+            return true;
         }
     }
-    ev_used_ = 0;
+    (void)hipGetLastError();
+    if (graph) (void)hipGraphDestroy(graph);
+    g.exec = nullptr;
+    destroy_pairs(g.pairs);
+    pool_.release(blocks);
+    return false;
+}
+
+void Engine::launch(const Captured &g) {
+    TN_HIP(hipGraphLaunch(g.exec, s));
+    ctr.graph_launches += 1;
+    ctr.gemm_flops += g.delta.gemm_flops;
+    ctr.gemm_launches += g.delta.gemm_launches;
+    ctr.qr_launches += g.delta.qr_launches;
+    ctr.qr_gemm_flops += g.delta.qr_gemm_flops;
+    ctr.masked_launches += g.delta.masked_launches;
+    ctr.gemm_bytes += g.delta.gemm_bytes;
+}
+
+void Engine::release(Captured &g) {
+    (void)hipStreamSynchronize(s);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    destroy_pairs(g.pairs);
+    pool_.release(g.blocks);
+    g.blocks.clear();
+}
+
+void Engine::collect_graph_timing(const std::deque<EvPair> &pairs) {
+    for (const EvPair &e : pairs) add_pair_time(e);
+}
+
+void Engine::destroy_pairs(std::deque<EvPair> &pairs) {
+    for (EvPair &e : pairs) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    pairs.clear();
 }
 
 std::string Engine::plan_report(int top) const {
@@ -751,15 +893,15 @@ void Engine::contract(const Op &A, const Op &B, const Op &C, bool accumulate) {
     // contractions inside the orthonormalisation are timed too (their QR-level
     // pair also covers them); their flops are booked separately.  The pair
     // covers the split-BF16 packing of the operands.
-    const size_t ev = timing ? next_pair(masked ? 2 : 0) : NOEV;
-    if (ev != NOEV) {
-        ev_[ev].plan = P;
-        TN_HIP(hipEventRecord(ev_[ev].a, s));
+    EvPair *ev = timing ? next_pair(masked ? 2 : 0) : nullptr;
+    if (ev) {
+        ev->plan = P;
+        TN_HIP(hipEventRecord(ev->a, s));
     }
     void *pka = nullptr, *pkb = nullptr;
     if (P->pack) pack_bf16(g, &pka, &pkb);
     TN_HIP(tnk::launch_gett(g, P->fp32 ? (int)tnk::P_FP32 : prec, cfg, s));
-    if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
+    if (ev) TN_HIP(hipEventRecord(ev->b, s));
     if (part) pool_.put(part);
     if (pka) pool_.put(pka);
     if (pkb) pool_.put(pkb);
@@ -803,10 +945,10 @@ void Engine::qr(const tnk::QrArgs &a) {
         qr_shapes_[k.str()] += 1;
     }
     // inside a wider factorisation the outer call's pair covers this one
-    const size_t ev = (timing && !in_qr_) ? next_pair(1) : NOEV;
-    if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].a, s));
+    EvPair *ev = (timing && !in_qr_) ? next_pair(1) : nullptr;
+    if (ev) TN_HIP(hipEventRecord(ev->a, s));
     TN_HIP(tnk::launch_qr(a, w, s));
-    if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
+    if (ev) TN_HIP(hipEventRecord(ev->b, s));
     if (!in_qr_) ctr.qr_launches += 1;
     pool_.put(w);
 }
@@ -846,7 +988,7 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
     const bool nested = in_qr_;  // a block of a wider orthonormalisation
     set_prec(tnk::P_FP64);
     in_qr_ = true;
-    const size_t ev = (timing && !nested) ? next_pair(1) : NOEV;
+    EvPair *ev = (timing && !nested) ? next_pair(1) : nullptr;
     std::vector<Ten> tmp;
     tmp.reserve(8);  // references into tmp are taken below: no reallocation
     auto cleanup = [&]() {
@@ -856,7 +998,7 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
         set_prec(saved);
     };
     try {
-        if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].a, s));
+        if (ev) TN_HIP(hipEventRecord(ev->a, s));
         if (n <= 64) {
             tmp.push_back(make({Z, m, n}, 16));  // X
             tmp.push_back(make({Z, m, n}, 16));  // Y
@@ -978,7 +1120,7 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
                 TN_HIP(tnk::launch_strided_copy(R->p, 16, (int64_t)n * n, n, 1, a.R, a.r_esz, a.r_bs, a.r_rs, a.r_cs,
                                                 n, n, Z, a.r_conj, s));
         }
-        if (ev != NOEV) TN_HIP(hipEventRecord(ev_[ev].b, s));
+        if (ev) TN_HIP(hipEventRecord(ev->b, s));
     } catch (...) {
         cleanup();
         throw;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <deque>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -68,12 +69,24 @@ class Pool {
     void put(void *p);
     size_t held() const { return held_; }
     void trim();
+    // Arena mode (stream capture): between begin_arena and end_arena every block
+    // handed out -- taken from the free list or newly allocated -- is recorded,
+    // and blocks put back are reused only within the arena.  end_arena returns
+    // them all: they belong to the captured graph, whose replays use the same
+    // addresses, until release() hands them back to the pool.
+    void begin_arena();
+    std::vector<void *> end_arena();
+    void release(const std::vector<void *> &blocks);
 
   private:
     size_t cap_;
     size_t held_ = 0;
     std::multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> size_;
+    bool arena_ = false;
+    std::multimap<size_t, void *> afree_;
+    std::vector<void *> ablocks_;
+    void *take(std::multimap<size_t, void *> &fl, size_t bytes);
 };
 
 struct Plan {
@@ -111,6 +124,8 @@ struct Counters {
     // algorithmic operand bytes of the (unmasked) launches: every element of A
     // and B read once, C written once (read too when accumulating)
     double gemm_bytes = 0;
+    // replays of captured launch graphs (their launches are counted above too)
+    int64_t graph_launches = 0;
     void reset() { *this = Counters(); }
 };
 
@@ -179,6 +194,27 @@ class Engine {
     size_t held() const { return pool_.held(); }
 
     void sync() { TN_HIP(hipStreamSynchronize(s)); }
+
+    // Event pair around one timed launch; kind 0 = contraction, 1 = QR, 2 = masked.
+    struct EvPair { hipEvent_t a, b; int kind; Plan *plan; };
+    // Stream capture of a launch sequence into a graph: the launches issued
+    // between begin_capture and end_capture are recorded (not run), device
+    // memory taken from the pool meanwhile stays with the graph, timing event
+    // pairs are recorded as graph nodes (owned by the graph), and the host-side
+    // counters they added are returned so that each replay can add them again.
+    struct Captured {
+        hipGraphExec_t exec = nullptr;
+        std::vector<void *> blocks;
+        std::deque<EvPair> pairs;
+        Counters delta;
+    };
+    void begin_capture(Captured &g);
+    // Ends the capture; false (and nothing kept) if the capture failed.
+    bool end_capture(Captured &g, bool ok);
+    void launch(const Captured &g);  // one replay (counters and event pairs included)
+    void collect_graph_timing(const std::deque<EvPair> &pairs);  // after the replay has finished
+    void release(Captured &g);  // synchronises, frees the graph, returns its memory to the pool
+    bool capturing() const { return cap_pairs_ != nullptr; }
     // Waits for the stream and adds the elapsed times of the event pairs recorded
     // since the last collection to the counters (timing mode).
     void collect_timing();
@@ -193,10 +229,14 @@ class Engine {
     Pool pool_;
     std::unordered_map<std::string, std::unique_ptr<Plan>> plans_;
     Plan *plan(const Op &A, const Op &B, const Op &C);
-    // event pairs recorded around launches in timing mode: kind 0 = contraction, 1 = QR
-    struct EvPair { hipEvent_t a, b; int kind; Plan *plan; };
-    std::vector<EvPair> ev_;
+    // event pairs recorded around launches in timing mode
+    std::deque<EvPair> ev_;
     size_t ev_used_ = 0;
+    std::deque<EvPair> *cap_pairs_ = nullptr;  // set while capturing
+    hipStream_t cap_stream_ = nullptr, user_stream_ = nullptr;
+    Counters cap_ctr0_;
+    void add_pair_time(const EvPair &e);
+    void destroy_pairs(std::deque<EvPair> &pairs);
     bool in_qr_ = false;  // contractions issued by the QR: flops booked as qr_gemm_flops
     const int *mask_ = nullptr;
     char mask_letter_ = 0;
@@ -209,8 +249,7 @@ class Engine {
     void set_split(Plan *P, int cfg, int ksplit_hint);
     void pack_bf16(tnk::GettArgs &g, void **pa, void **pb);
     void tune(Plan *P, tnk::GettArgs g);
-    static constexpr size_t NOEV = ~size_t(0);
-    size_t next_pair(int kind);
+    EvPair *next_pair(int kind);
 };
 
 }  // namespace tnb

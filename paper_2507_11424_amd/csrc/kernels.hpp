@@ -221,4 +221,30 @@ hipError_t launch_fingerprint(const FingerprintSet &f, unsigned long long *acc, 
 hipError_t launch_logp(const double *amp, const double *mlog, int batch, double *log_p, double *arg,
                        hipStream_t s);
 
+// ---------------------------------------------------------------- belief propagation
+// Embeds a site tensor src[p][u][l][d][r] (complex128) into dst[2][Dm]^4 (cleared).
+hipError_t launch_bp_embed(const void *src, int p, int u, int l, int d, int r, void *dst, int Dm, hipStream_t s);
+// out [4][N][Dm][Dm]: the message each site sends through each leg (0 up,
+// 1 left, 2 down, 3 right); msg [N][4][Dm][Dm]: incoming messages; nbr [N][4]:
+// the neighbour receiving through each leg, -1 without a bond.  Stores the
+// Hermitian part of every sent message, normalised to unit Frobenius norm, as
+// the neighbour's incoming message; dmax [N * 4] scratch; *delta = largest
+// element change (infinity if a message vanished or overflowed).
+hipError_t launch_bp_update(const void *out, void *msg, const int *nbr, int N, int Dm, double *dmax, double *delta,
+                            hipStream_t s);
+// outr [N][Dm][Dm]: the message each site would send to the right (pair closed
+// with the other three messages).  out[0] = log|Z_BP|, out[1] = arg Z_BP with
+// Z_BP = prod_v Z_v / prod_e Z_e; zv [N], ze [N][2] complex scratch.
+hipError_t launch_bp_free_energy(const void *outr, const void *msg, const int *nbr, int N, int Dm, void *zv,
+                                 void *ze, double *out, hipStream_t s);
+// mats[q] (n x n complex128) <- pairs + off[q] (n x n), transposed if trans[q].
+hipError_t launch_gather_mats(const void *pairs, const int64_t *off, const int *trans, int count, int n, void *mats,
+                              hipStream_t s);
+// Eigenvalues of `batch` general complex n x n matrices (overwritten), one
+// lane each: Householder Hessenberg reduction and shifted QR with deflation.
+// lam [batch][n] complex128; eps[q] = 1 - max|lambda| / sum|lambda|; info[q] = 1
+// if the iteration limit was reached.
+constexpr int BP_EIG_NMAX = 256;
+hipError_t launch_eig(void *mats, int n, int batch, void *lam, double *eps, int *info, hipStream_t s);
+
 }  // namespace tnk

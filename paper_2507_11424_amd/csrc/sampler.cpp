@@ -382,188 +382,257 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
         HouseholderScope(Engine &e, bool on) : E(e), saved(e.householder_only) { E.householder_only = saved || on; }
         ~HouseholderScope() { E.householder_only = saved; }
     } hh(E, o.svd_cutoff > 0);
+    // A wave reads and writes its samples through library buffers whose row 0
+    // is the wave's first sample, so that its launch sequence does not depend
+    // on the wave's position: the launches of the second full wave are captured
+    // into a graph (the first one, run directly, creates the contraction plans
+    // and tile choices) and replayed for the following full waves.
+    const int nq = P.nq;
+    double *u_w = uniforms ? reinterpret_cast<double *>(E.raw((size_t)Zw * nq * 8)) : nullptr;
+    uint8_t *bits_w = reinterpret_cast<uint8_t *>(E.raw((size_t)Zw * nq));
+    double *lq_w = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
+    double *lp_w = log_p ? reinterpret_cast<double *>(E.raw((size_t)Zw * 8)) : nullptr;
+    int *cu_w = chi_used ? reinterpret_cast<int *>(E.raw((size_t)Zw * rows * 4)) : nullptr;
+    double *lc_w = o.log_cond ? reinterpret_cast<double *>(E.raw((size_t)Zw * nq * 8)) : nullptr;
+    auto wave = [&](int Z, int64_t w0) {
+        TN_HIP(tnk::launch_fill_f64(mlog, Z, 0.0, E.s));
+        TN_HIP(tnk::launch_fill_i32(flags, Z, 0, E.s));
+        TN_HIP(tnk::launch_fill_f64(lq_w, Z, 0.0, E.s));
+        std::vector<Ten> m(cols);
+        for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
+        if (cu_w) TN_HIP(tnk::launch_chi_used(nullptr, 0, Z, 1, cu_w, rows, E.s));
+        const int rows_run = o.rows_limit > 0 ? std::min(rows, o.rows_limit) : rows;
+        if (rows_run < rows && lp_w) TN_HIP(tnk::launch_fill_f64(lp_w, Z, NAN, E.s));
+        for (int r = 0; r < rows_run; ++r) {
+            const DMps &Bb = B.below[r];
+            // sites that take the transfer-matrix route, and their matrices
+            std::vector<int> useT(cols, 0);
+            std::vector<Ten> Ts(cols), T0(cols), T1(cols);
+            for (int c = 0; c < cols; ++c) {
+                const SiteRef &a = V.at(r, c);
+                if (!transfer_pays(a, Bb.site[c], m[c])) continue;
+                useT[c] = 1;
+                Ts[c] = transfer(E, a, Bb.site[c], -1);
+                if (a.dim(0) == 2) {
+                    T0[c] = transfer(E, a, Bb.site[c], 0);
+                    T1[c] = transfer(E, a, Bb.site[c], 1);
+                }
+            }
+            // Environments are rescaled to unit norm every ENV_RENORM sites only
+            // (probabilities are ratios; the stride keeps them far from under-
+            // and overflow).  R[c] is stored divided by exp(lnR[c][z]).
+            std::vector<Ten> R(cols + 1);
+            R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
+            for (int c = cols - 1; c >= 1; --c) {
+                R[c] = useT[c] ? env_right_T(E, R[c + 1], m[c], Ts[c])
+                               : env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
+                const int64_t per = R[c].numel() / Z;
+                if ((cols - c) % ENV_RENORM == 0 || c == 1)
+                    E.normalise(R[c].p, R[c].esz, per, Z, per, lnR + (size_t)c * Zw, false, nullptr);
+                else
+                    TN_HIP(tnk::launch_fill_f64(lnR + (size_t)c * Zw, Z, 0.0, E.s));
+            }
+            Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
+            for (int c = 0; c < cols; ++c) {
+                const SiteRef &a = V.at(r, c);
+                int *xs = xsel + (size_t)c * Zw;
+                if (a.dim(0) == 1) {
+                    Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left_traced(E, Lc, m[c], a, Bb.site[c]);
+                    E.drop(Lc);
+                    Lc = L2;
+                    if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
+                    TN_HIP(tnk::launch_fill_i32(xs, Z, 0, E.s));
+                    continue;
+                }
+                // P~(f) = <L_c . site(s=f), R_{c+1}> for the favoured bit f.  For
+                // c >= 1 the traced right environment gives P~(0) + P~(1) =
+                // |R_c| <L_c, R_c>, so the draw takes the other P~ as the
+                // difference, except for samples where that difference is
+                // below a precision-dependent fraction of the total (its
+                // rounding would dominate): those contract the projection
+                // directly before the draw.  After the draw the other bit's
+                // step runs only for the samples that drew it (the others'
+                // tiles are skipped), and their log q takes the conditional
+                // from that direct projection.  Site 0 computes both.
+                const int f = favour[(size_t)r * cols + c];
+                auto rest_step = [&](const Ten &t1, int s) {
+                    return useT[c] ? left_rest_T(E, t1, m[c], s ? T1[c] : T0[c])
+                                   : left_rest(E, t1, m[c], a, Bb.site[c], s);
+                };
+                double *ptf = pt + (f ? 2 * Zw : 0), *pto = pt + (f ? 0 : 2 * Zw);
+                Ten t1 = left_t1(E, Lc, m[c], useT[c] != 0);
+                Ten Lf = rest_step(t1, f);
+                const int64_t per = Lf.numel() / Z;
+                E.dot(Lf.p, R[c + 1].p, Lf.esz, per, Z, per, ptf);
+                Ten Lo;
+                const bool rest = c >= 1;
+                if (rest) {
+                    const int64_t perc = Lc.numel() / Z;
+                    E.dot(Lc.p, R[c].p, Lc.esz, perc, Z, perc, ptot);
+                    TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, ptf, pto, Z, diff_thr, need,
+                                                     E.s));
+                    // samples whose other-bit P~ is too small a difference to
+                    // trust: contract that projection directly (masked to them)
+                    E.set_mask(need, 'z', 0);
+                    Ten Ln;
+                    try {
+                        Ln = rest_step(t1, 1 - f);
+                    } catch (...) {
+                        E.clear_mask();
+                        throw;
+                    }
+                    E.clear_mask();
+                    E.dot(Ln.p, R[c + 1].p, Ln.esz, per, Z, per, pto, need, 0);
+                    E.drop(Ln);
+                } else {
+                    Lo = rest_step(t1, 1 - f);
+                    E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, pto);
+                }
+                tnk::DrawArgs d{};
+                d.batch = Z;
+                d.pt0 = pt;
+                d.pt1 = pt + 2 * Zw;
+                d.uniforms = u_w;
+                d.u_row0 = 0;
+                d.n_qubits = P.nq;
+                d.qubit = P.site_index[(size_t)r * cols + c];
+                d.seed = o.seed;
+                d.sample_index = sidx;
+                d.bits = bits_w;
+                d.bits_row0 = 0;
+                d.log_q = lq_w;
+                d.xsel = xs;
+                d.flags = flags;
+                d.log_cond = lc_w;
+                TN_HIP(tnk::launch_draw(d, E.s));
+                if (rest) {
+                    E.set_mask(xs, 'z', f);  // skip the samples that drew f
+                    try {
+                        Lo = rest_step(t1, 1 - f);
+                    } catch (...) {
+                        E.clear_mask();
+                        throw;
+                    }
+                    E.clear_mask();
+                    // the drawn bit's conditional from the direct projection
+                    // (log q never keeps the difference's rounding)
+                    E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, ptd, xs, f);
+                    TN_HIP(tnk::launch_fix_other(ptf, pto, ptd, xs, 1 - f, Z, lq_w, lc_w, 0, P.nq,
+                                                 d.qubit, flags, E.s));
+                }
+                E.drop(t1);
+                // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
+                const Ten &L0 = f ? Lo : Lf, &L1 = f ? Lf : Lo;
+                E.drop(Lc);
+                Lc = E.make(L0.d);
+                TN_HIP(tnk::launch_select2(L0.p, L1.p, L0.esz, per, per, xs, Z, Lc.p, E.s));
+                E.drop(Lf);
+                E.drop(Lo);
+                if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
+            }
+            E.drop(Lc);
+            for (auto &x : R)
+                if (x.p) E.drop(x);
+            for (int c = 0; c < cols; ++c)
+                for (Ten *t : {&Ts[c], &T0[c], &T1[c]})
+                    if (t->p) E.drop(*t);
+            // projected row X_c[z] = A_c[x_c(z)], dims [z, u, h, d, H]
+            std::vector<Ten> X(cols);
+            for (int c = 0; c < cols; ++c) {
+                const SiteRef &a = V.at(r, c);
+                X[c] = E.make({Z, a.dim(1), a.dim(2), a.dim(3), a.dim(4)});
+                const int64_t per = X[c].numel() / Z;
+                TN_HIP(tnk::launch_select_copy(a.t->p, a.t->esz, per, per, 0, xsel + (size_t)c * Zw, Z, X[c].p,
+                                               per, E.s));
+            }
+            if (r + 1 == rows_run && rows_run < rows) {
+                // stopped early (test hook): no fit for rows that are not sampled
+            } else if (r + 1 < rows) {
+                std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
+                for (auto &x : m) E.drop(x);
+                m = mn;
+                if (o.svd_cutoff > 0) truncate_cutoff(E, m, o, kbuf);
+                if (cu_w) {
+                    int width = 1;
+                    for (int c = 0; c + 1 < cols; ++c) width = std::max(width, m[c].d[3]);
+                    TN_HIP(tnk::launch_chi_used(o.svd_cutoff > 0 ? kbuf : nullptr, cols - 1, Z, width,
+                                                cu_w + r + 1, rows, E.s));
+                }
+            } else if (lp_w) {
+                last_row_amplitude(E, m, X, mlog, amp, lp_w, nullptr);
+            }
+            for (auto &x : X) E.drop(x);
+            if (progress_enabled()) {
+                E.sync();
+                std::fprintf(stderr, "tn: samples %lld-%lld row %d done\n", (long long)(first + w0),
+                             (long long)(first + w0 + Z - 1), r);
+                std::fflush(stderr);
+            }
+        }
+        for (auto &x : m) E.drop(x);
+    };
+    Engine::Captured graph;
+    bool have_graph = false;
+    // per-launch event timing needs launches issued from the host: timed calls
+    // (and progress reports, which synchronise per row) run every wave directly
+    bool graphs_ok = o.graphs && !E.timing && !progress_enabled();
+    int full_waves = 0;
+    auto release_all = [&]() {
+        if (have_graph) E.release(graph);
+        have_graph = false;
+        E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
+        E.unraw(ptot); E.unraw(lnR); E.unraw(ptd); E.unraw(need); E.unraw(bits_w); E.unraw(lq_w);
+        for (void *q : {(void *)kbuf, (void *)u_w, (void *)lp_w, (void *)cu_w, (void *)lc_w})
+            if (q) E.unraw(q);
+    };
     try {
         for (int64_t w0 = 0; w0 < n; w0 += Zw) {
             const int Z = (int)std::min<int64_t>(Zw, n - w0);
             for (int z = 0; z < Z; ++z) hidx[z] = first + (uint64_t)(w0 + z);
             TN_HIP(hipMemcpyAsync(sidx, hidx.data(), (size_t)Z * 8, hipMemcpyHostToDevice, E.s));
-            TN_HIP(tnk::launch_fill_f64(mlog, Z, 0.0, E.s));
-            TN_HIP(tnk::launch_fill_i32(flags, Z, 0, E.s));
-            TN_HIP(tnk::launch_fill_f64(log_q + w0, Z, 0.0, E.s));
-            std::vector<Ten> m(cols);
-            for (int c = 0; c < cols; ++c) m[c] = ones(E, {Z, 1, V.at(0, c).dim(1), 1});
-            if (chi_used) TN_HIP(tnk::launch_chi_used(nullptr, 0, Z, 1, chi_used + w0 * rows, rows, E.s));
-            const int rows_run = o.rows_limit > 0 ? std::min(rows, o.rows_limit) : rows;
-            if (rows_run < rows && log_p) TN_HIP(tnk::launch_fill_f64(log_p + w0, Z, NAN, E.s));
-            for (int r = 0; r < rows_run; ++r) {
-                const DMps &Bb = B.below[r];
-                // sites that take the transfer-matrix route, and their matrices
-                std::vector<int> useT(cols, 0);
-                std::vector<Ten> Ts(cols), T0(cols), T1(cols);
-                for (int c = 0; c < cols; ++c) {
-                    const SiteRef &a = V.at(r, c);
-                    if (!transfer_pays(a, Bb.site[c], m[c])) continue;
-                    useT[c] = 1;
-                    Ts[c] = transfer(E, a, Bb.site[c], -1);
-                    if (a.dim(0) == 2) {
-                        T0[c] = transfer(E, a, Bb.site[c], 0);
-                        T1[c] = transfer(E, a, Bb.site[c], 1);
+            if (u_w)
+                TN_HIP(hipMemcpyAsync(u_w, uniforms + w0 * nq, (size_t)Z * nq * 8, hipMemcpyDeviceToDevice, E.s));
+            if (lc_w)
+                TN_HIP(hipMemcpyAsync(lc_w, o.log_cond + w0 * nq, (size_t)Z * nq * 8, hipMemcpyDeviceToDevice, E.s));
+            bool replayed = false;
+            if (Z == Zw && graphs_ok && (have_graph || full_waves >= 1)) {
+                if (!have_graph) {
+                    bool ok = true;
+                    try {
+                        E.begin_capture(graph);
+                    } catch (const TnError &) {
+                        ok = false;
                     }
-                }
-                // Environments are rescaled to unit norm every ENV_RENORM sites only
-                // (probabilities are ratios; the stride keeps them far from under-
-                // and overflow).  R[c] is stored divided by exp(lnR[c][z]).
-                std::vector<Ten> R(cols + 1);
-                R[cols] = ones(E, {Z, 1, 1, 1, 1, 1});
-                for (int c = cols - 1; c >= 1; --c) {
-                    R[c] = useT[c] ? env_right_T(E, R[c + 1], m[c], Ts[c])
-                                   : env_right(E, R[c + 1], m[c], V.at(r, c), Bb.site[c]);
-                    const int64_t per = R[c].numel() / Z;
-                    if ((cols - c) % ENV_RENORM == 0 || c == 1)
-                        E.normalise(R[c].p, R[c].esz, per, Z, per, lnR + (size_t)c * Zw, false, nullptr);
-                    else
-                        TN_HIP(tnk::launch_fill_f64(lnR + (size_t)c * Zw, Z, 0.0, E.s));
-                }
-                Ten Lc = ones(E, {Z, 1, 1, 1, 1, 1});
-                for (int c = 0; c < cols; ++c) {
-                    const SiteRef &a = V.at(r, c);
-                    int *xs = xsel + (size_t)c * Zw;
-                    if (a.dim(0) == 1) {
-                        Ten L2 = useT[c] ? env_left_T(E, Lc, m[c], Ts[c]) : env_left_traced(E, Lc, m[c], a, Bb.site[c]);
-                        E.drop(Lc);
-                        Lc = L2;
-                        if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
-                        TN_HIP(tnk::launch_fill_i32(xs, Z, 0, E.s));
-                        continue;
-                    }
-                    // P~(f) = <L_c . site(s=f), R_{c+1}> for the favoured bit f.  For
-                    // c >= 1 the traced right environment gives P~(0) + P~(1) =
-                    // |R_c| <L_c, R_c>, so the draw takes the other P~ as the
-                    // difference, except for samples where that difference is
-                    // below a precision-dependent fraction of the total (its
-                    // rounding would dominate): those contract the projection
-                    // directly before the draw.  After the draw the other bit's
-                    // step runs only for the samples that drew it (the others'
-                    // tiles are skipped), and their log q takes the conditional
-                    // from that direct projection.  Site 0 computes both.
-                    const int f = favour[(size_t)r * cols + c];
-                    auto rest_step = [&](const Ten &t1, int s) {
-                        return useT[c] ? left_rest_T(E, t1, m[c], s ? T1[c] : T0[c])
-                                       : left_rest(E, t1, m[c], a, Bb.site[c], s);
-                    };
-                    double *ptf = pt + (f ? 2 * Zw : 0), *pto = pt + (f ? 0 : 2 * Zw);
-                    Ten t1 = left_t1(E, Lc, m[c], useT[c] != 0);
-                    Ten Lf = rest_step(t1, f);
-                    const int64_t per = Lf.numel() / Z;
-                    E.dot(Lf.p, R[c + 1].p, Lf.esz, per, Z, per, ptf);
-                    Ten Lo;
-                    const bool rest = c >= 1;
-                    if (rest) {
-                        const int64_t perc = Lc.numel() / Z;
-                        E.dot(Lc.p, R[c].p, Lc.esz, perc, Z, perc, ptot);
-                        TN_HIP(tnk::launch_marginal_rest(ptot, lnR + (size_t)c * Zw, ptf, pto, Z, diff_thr, need,
-                                                         E.s));
-                        // samples whose other-bit P~ is too small a difference to
-                        // trust: contract that projection directly (masked to them)
-                        E.set_mask(need, 'z', 0);
-                        Ten Ln;
+                    if (ok) {
                         try {
-                            Ln = rest_step(t1, 1 - f);
+                            wave(Z, w0);
                         } catch (...) {
-                            E.clear_mask();
-                            throw;
+                            ok = false;
                         }
-                        E.clear_mask();
-                        E.dot(Ln.p, R[c + 1].p, Ln.esz, per, Z, per, pto, need, 0);
-                        E.drop(Ln);
-                    } else {
-                        Lo = rest_step(t1, 1 - f);
-                        E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, pto);
+                        have_graph = E.end_capture(graph, ok);
                     }
-                    tnk::DrawArgs d{};
-                    d.batch = Z;
-                    d.pt0 = pt;
-                    d.pt1 = pt + 2 * Zw;
-                    d.uniforms = uniforms;
-                    d.u_row0 = w0;
-                    d.n_qubits = P.nq;
-                    d.qubit = P.site_index[(size_t)r * cols + c];
-                    d.seed = o.seed;
-                    d.sample_index = sidx;
-                    d.bits = bits;
-                    d.bits_row0 = w0;
-                    d.log_q = log_q + w0;
-                    d.xsel = xs;
-                    d.flags = flags;
-                    d.log_cond = o.log_cond;
-                    TN_HIP(tnk::launch_draw(d, E.s));
-                    if (rest) {
-                        E.set_mask(xs, 'z', f);  // skip the samples that drew f
-                        try {
-                            Lo = rest_step(t1, 1 - f);
-                        } catch (...) {
-                            E.clear_mask();
-                            throw;
-                        }
-                        E.clear_mask();
-                        // the drawn bit's conditional from the direct projection
-                        // (log q never keeps the difference's rounding)
-                        E.dot(Lo.p, R[c + 1].p, Lo.esz, per, Z, per, ptd, xs, f);
-                        TN_HIP(tnk::launch_fix_other(ptf, pto, ptd, xs, 1 - f, Z, log_q + w0, o.log_cond, w0, P.nq,
-                                                     d.qubit, flags, E.s));
-                    }
-                    E.drop(t1);
-                    // keep the environment of the drawn bit: Lc[z] = (x_z ? L1 : L0)[z]
-                    const Ten &L0 = f ? Lo : Lf, &L1 = f ? Lf : Lo;
-                    E.drop(Lc);
-                    Lc = E.make(L0.d);
-                    TN_HIP(tnk::launch_select2(L0.p, L1.p, L0.esz, per, per, xs, Z, Lc.p, E.s));
-                    E.drop(Lf);
-                    E.drop(Lo);
-                    if ((c + 1) % ENV_RENORM == 0) unit(E, Lc, Z);
+                    if (!have_graph) graphs_ok = false;  // run this and later waves directly
                 }
-                E.drop(Lc);
-                for (auto &x : R)
-                    if (x.p) E.drop(x);
-                for (int c = 0; c < cols; ++c)
-                    for (Ten *t : {&Ts[c], &T0[c], &T1[c]})
-                        if (t->p) E.drop(*t);
-                // projected row X_c[z] = A_c[x_c(z)], dims [z, u, h, d, H]
-                std::vector<Ten> X(cols);
-                for (int c = 0; c < cols; ++c) {
-                    const SiteRef &a = V.at(r, c);
-                    X[c] = E.make({Z, a.dim(1), a.dim(2), a.dim(3), a.dim(4)});
-                    const int64_t per = X[c].numel() / Z;
-                    TN_HIP(tnk::launch_select_copy(a.t->p, a.t->esz, per, per, 0, xsel + (size_t)c * Zw, Z, X[c].p,
-                                                   per, E.s));
+                if (have_graph) {
+                    E.launch(graph);
+                    replayed = true;
+                } else {
+                    wave(Z, w0);
                 }
-                if (r + 1 == rows_run && rows_run < rows) {
-                    // stopped early (test hook): no fit for rows that are not sampled
-                } else if (r + 1 < rows) {
-                    std::vector<Ten> mn = fit_single(E, m, X, o, r, sidx, mlog);
-                    for (auto &x : m) E.drop(x);
-                    m = mn;
-                    if (o.svd_cutoff > 0) truncate_cutoff(E, m, o, kbuf);
-                    if (chi_used) {
-                        int width = 1;
-                        for (int c = 0; c + 1 < cols; ++c) width = std::max(width, m[c].d[3]);
-                        TN_HIP(tnk::launch_chi_used(o.svd_cutoff > 0 ? kbuf : nullptr, cols - 1, Z, width,
-                                                    chi_used + w0 * rows + r + 1, rows, E.s));
-                    }
-                } else if (log_p) {
-                    last_row_amplitude(E, m, X, mlog, amp, log_p + w0, nullptr);
-                }
-                for (auto &x : X) E.drop(x);
-                if (progress_enabled()) {
-                    E.sync();
-                    std::fprintf(stderr, "tn: samples %lld-%lld row %d done\n", (long long)(first + w0),
-                                 (long long)(first + w0 + Z - 1), r);
-                    std::fflush(stderr);
-                }
+            } else {
+                wave(Z, w0);
             }
-            for (auto &x : m) E.drop(x);
+            if (Z == Zw) ++full_waves;
+            TN_HIP(hipMemcpyAsync(bits + w0 * nq, bits_w, (size_t)Z * nq, hipMemcpyDeviceToDevice, E.s));
+            TN_HIP(hipMemcpyAsync(log_q + w0, lq_w, (size_t)Z * 8, hipMemcpyDeviceToDevice, E.s));
+            if (lp_w) TN_HIP(hipMemcpyAsync(log_p + w0, lp_w, (size_t)Z * 8, hipMemcpyDeviceToDevice, E.s));
+            if (cu_w)
+                TN_HIP(hipMemcpyAsync(chi_used + w0 * rows, cu_w, (size_t)Z * rows * 4, hipMemcpyDeviceToDevice, E.s));
+            if (lc_w)
+                TN_HIP(hipMemcpyAsync(o.log_cond + w0 * nq, lc_w, (size_t)Z * nq * 8, hipMemcpyDeviceToDevice, E.s));
             TN_HIP(hipMemcpyAsync(hflags.data(), flags, (size_t)Z * 4, hipMemcpyDeviceToHost, E.s));
             E.sync();
+            if (replayed && E.timing) E.collect_graph_timing(graph.pairs);
             for (int z = 0; z < Z; ++z)
                 if (hflags[z])
                     throw TnError(ST_NUMERIC, "sample " + std::to_string(first + w0 + z) +
@@ -571,14 +640,10 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
                                                                    : ": environment vanished or overflowed"));
         }
     } catch (...) {
-        E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
-        E.unraw(ptot); E.unraw(lnR); E.unraw(ptd); E.unraw(need);
-        if (kbuf) E.unraw(kbuf);
+        release_all();
         throw;
     }
-    E.unraw(sidx); E.unraw(mlog); E.unraw(pt); E.unraw(flags); E.unraw(xsel); E.unraw(amp);
-    E.unraw(ptot); E.unraw(lnR); E.unraw(ptd); E.unraw(need);
-    if (kbuf) E.unraw(kbuf);
+    release_all();
 }
 
 void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first, int64_t n, const uint8_t *bits,

@@ -91,6 +91,8 @@ struct SampleOpts {
     // [n][N] doubles) receives every drawn qubit's log P(x_q | earlier qubits)
     int rows_limit = 0;
     double *log_cond = nullptr;
+    // replay full waves after the second from a captured graph (0: run every wave directly)
+    int graphs = 1;
 };
 
 // chi_used (optional, device [n][rows] int32): largest kept bond of the
@@ -104,5 +106,19 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
 // stream (tag o.init_tag) of the fits' initial guesses.
 void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first, int64_t n, const uint8_t *bits,
                double *log_p, double *arg);
+
+// Belief propagation on the norm network and the loop BP error (FP64).
+struct BpOpts {
+    int max_sweeps = 1000;
+    double tol = 1e-13;
+    bool loops = true;          // also the loop BP error of every primitive loop
+    void *messages = nullptr;   // optional device copy of the final messages [N][4][Dm][Dm]
+};
+struct BpResult {
+    double log_abs = 0, arg = 0, delta = 0, eps_mean = 0;
+    int sweeps = 0, eig_info = 0;
+    std::vector<double> eps;    // per primitive loop, ordered by the loop's first site
+};
+void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res);
 
 }  // namespace tnb

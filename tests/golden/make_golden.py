@@ -8,6 +8,7 @@ Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
     python tests/golden/make_golden.py c2_env        # 8x8 D=4 environments at chi = 32
     python tests/golden/make_golden.py c3_rows       # first 4 sampled rows at chi_x = 64 (~1 h)
     python tests/golden/make_golden.py c3_env        # c3 environments at chi = 64 (~40 min)
+    python tests/golden/make_golden.py c3_bp         # c3 belief propagation and loop errors (~1 min)
 """
 import json
 import math
@@ -113,6 +114,22 @@ def c3_env(chi=64):
     print({k: v for k, v in out.items() if k in ("config", "chi", "oracle_seconds")})
 
 
+def c3_bp():
+    """Belief propagation on the benchmark lattice's norm network: log Z_BP and
+    the loop BP error of each of its 55 six-site loops."""
+    from oracle import bp as obp
+    lat, T, cfg = make_config("c3")
+    t0 = time.time()
+    M, sweeps, delta = obp.bp_messages(T)
+    lz, ph = obp.bp_log_norm(T, M)
+    mean, eps, spectra, loops = obp.loop_bp_error(T, M)
+    out = dict(config="c3", sweeps=sweeps, last_change=delta, log_abs_Z_bp=lz, arg_Z_bp=ph, eps=mean,
+               eps_loops=[float(e) for e in eps], loop_first_sites=[[lp[0][0], lp[0][1]] for lp in loops],
+               oracle_seconds=time.time() - t0, command="python tests/golden/make_golden.py c3_bp")
+    json.dump(out, open(os.path.join(HERE, "c3_bp.json"), "w"), indent=1)
+    print({k: v for k, v in out.items() if k not in ("eps_loops", "loop_first_sites")})
+
+
 if __name__ == "__main__":
     {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env, "c3_rows": c3_rows,
-     "c3_env": c3_env}[sys.argv[1]]()
+     "c3_env": c3_env, "c3_bp": c3_bp}[sys.argv[1]]()
