@@ -19,7 +19,10 @@ Plain, slow, obviously correct NumPy (complex128) following Rudolph & Tindall,
                       of <x|psi>, the norm estimate E_q[p/q], the sample KLD
                       and importance-sampled <Z> (Methods, sampling; Eq. kld);
 * ``philox``       -- Philox4x64-10 (Salmon et al. 2011) for random initial
-                      guesses and draws.
+                      guesses and draws;
+* ``bp``           -- belief propagation on the norm network, the BP norm
+                      estimate and the loop BP error (Methods, Eqs. avBPError
+                      and loopBPerror; Appendix, message update).
 
 Pins (tests marked ``not gpu``): exact statevectors on lattices of <= 16
 qubits, brute-force summation over bond assignments, NumPy's own Philox,
@@ -34,3 +37,4 @@ from .boundary import boundary_set, norm, fit_double, plan_bonds, flip_vertical 
 from .sampler import sample, sample_one, fit_single, SamplingError  # noqa: F401
 from .environments import environments, z_expectation  # noqa: F401
 from .verify import amplitude, amplitudes, sample_stats  # noqa: F401
+from .bp import bp_messages, bp_log_norm, primitive_loops, loop_bp_error  # noqa: F401
