@@ -389,12 +389,15 @@ void sample(Engine &E, const PepsDev &P, const BoundarySet &B, const SampleOpts 
     // and tile choices) and replayed for the following full waves.
     const int nq = P.nq;
     double *u_w = uniforms ? reinterpret_cast<double *>(E.raw((size_t)Zw * nq * 8)) : nullptr;
-    uint8_t *bits_w = reinterpret_cast<uint8_t *>(E.raw((size_t)Zw * nq));
+    const int64_t bits_words = ((int64_t)Zw * nq + 3) / 4;  // cleared as int32 words
+    uint8_t *bits_w = reinterpret_cast<uint8_t *>(E.raw((size_t)bits_words * 4));
     double *lq_w = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
     double *lp_w = log_p ? reinterpret_cast<double *>(E.raw((size_t)Zw * 8)) : nullptr;
     int *cu_w = chi_used ? reinterpret_cast<int *>(E.raw((size_t)Zw * rows * 4)) : nullptr;
     double *lc_w = o.log_cond ? reinterpret_cast<double *>(E.raw((size_t)Zw * nq * 8)) : nullptr;
     auto wave = [&](int Z, int64_t w0) {
+        // bits of qubits that are not drawn (rows past a rows limit) read 0
+        TN_HIP(tnk::launch_fill_i32(reinterpret_cast<int *>(bits_w), ((int64_t)Z * nq + 3) / 4, 0, E.s));
         TN_HIP(tnk::launch_fill_f64(mlog, Z, 0.0, E.s));
         TN_HIP(tnk::launch_fill_i32(flags, Z, 0, E.s));
         TN_HIP(tnk::launch_fill_f64(lq_w, Z, 0.0, E.s));
