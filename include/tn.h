@@ -314,7 +314,10 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  *   matrices of element size esz (16 or 8 bytes): Q is m x k, R (optional,
  *   NULL = not formed) is k x n, k = min(m, n).  method 0: Householder;
  *   method 1: the fit's shifted CholeskyQR3 (m >= n, n <= 64; Householder
- *   otherwise), R = R_3 R_2 R_1.  Enqueued on the handle's stream.
+ *   otherwise), R = R_3 R_2 R_1.  method 2: CholeskyQR3 of the LQ moves, Q
+ *   only (R must be NULL, m >= n): A and Q hold the conjugate transposes
+ *   (n x m, row-major), so the rows of Q are an orthonormal basis of the rows
+ *   of A.  Enqueued on the handle's stream.
  * tn_test_svd: the sampler's SVD truncation step on `batch` row-major n x n
  *   complex128 DEVICE matrices R (n <= 128): U (n x n) and SV (n x n), element
  *   size esz (16 or 8), with R ~ U SV; columns of U and rows of SV past the

@@ -438,8 +438,12 @@ class Handle:
 
     def test_qr(self, A, Q, R, method: str | None = None):
         """method "householder" or "cholesky" (default: Householder when R is
-        given, CholeskyQR3 otherwise)."""
+        given, CholeskyQR3 otherwise); "cholesky_lq": A and Q are n x m (wide),
+        the rows of Q an orthonormal basis of the rows of A, read and written
+        through conjugate-transposed strides as in the fit's LQ moves."""
         m, n = A.shape[-2], A.shape[-1]
+        if method == "cholesky_lq":
+            m, n = n, m
         batch = int(np.prod(A.shape[:-2])) if A.dim() > 2 else 1
         esz = 16 if A.element_size() == 16 else 8
         if method is None:
@@ -447,4 +451,4 @@ class Handle:
         self._check(lib().tn_test_qr(self.h, m, n, batch, esz, ctypes.c_void_p(A.data_ptr()),
                                      ctypes.c_void_p(Q.data_ptr()),
                                      ctypes.c_void_p(R.data_ptr()) if R is not None else None,
-                                     0 if method == "householder" else 1))
+                                     {"householder": 0, "cholesky": 1, "cholesky_lq": 2}[method]))

@@ -599,6 +599,14 @@ tn_status tn_test_qr(tn_handle *h, int m, int n, int batch, int esz, const void 
         a.A = A; a.a_esz = esz; a.a_bs = (int64_t)m * n; a.a_rs = n; a.a_cs = 1;
         a.Q = Q; a.q_esz = esz; a.q_bs = (int64_t)m * k; a.q_rs = k; a.q_cs = 1;
         a.R = R; a.r_esz = esz; a.r_bs = (int64_t)k * n; a.r_rs = n; a.r_cs = 1;
+        if (method == 2) {
+            // LQ layout: A holds the conjugate transpose (batch x n x m), Q is
+            // written the same way (rows orthonormal), as the fit's LQ moves do
+            if (R || m < n) throw TnError(ST_INVALID, "tn_test_qr: the LQ layout takes no R and needs m >= n");
+            a.a_rs = 1; a.a_cs = m; a.a_conj = 1;
+            a.q_rs = 1; a.q_cs = m; a.q_conj = 1;
+            a.R = nullptr;
+        }
         if (method == 0) h->E->qr(a);
         else h->E->orthonormalise(a);
         return TN_OK;

@@ -1000,31 +1000,54 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
     try {
         if (ev) TN_HIP(hipEventRecord(ev->a, s));
         if (n <= 64) {
-            tmp.push_back(make({Z, m, n}, 16));  // X
-            tmp.push_back(make({Z, m, n}, 16));  // Y
-            tmp.push_back(make({Z, n, n}, 16));  // G
-            tmp.push_back(make({Z, n, n}, 16));  // R^{-1}
-            Ten *X = &tmp[0], *Y = &tmp[1], &G = tmp[2], &Ri = tmp[3];
-            // with R requested: the pass factors R_1, R_2, R_3 (A = Q R_3 R_2 R_1)
+            // Three CholeskyQR passes (the first shifted), each one launch over
+            // row blocks (rows times the previous inverse factor, their partial
+            // Gram matrices), one ordered sum of the partials and one
+            // factorisation; a last row launch writes Q = X_2 R_3^{-1}.
+            const int rb = tnk::cqr_rows_per_block(m);
+            const int nblk = (m + rb - 1) / rb;
+            tmp.push_back(make({Z, m, n}, 16));        // X_1 = A R_1^{-1}
+            tmp.push_back(make({Z, m, n}, 16));        // X_2 = X_1 R_2^{-1}
+            tmp.push_back(make({Z, nblk, n, n}, 16));  // partial Gram matrices
+            tmp.push_back(make({Z, n, n}, 16));        // R^{-1} of the current pass
+            tmp.push_back(make({Z, n, n}, 16));        // Gram matrix of the current pass
+            Ten &X1 = tmp[0], &X2 = tmp[1], &Pg = tmp[2], &Ri = tmp[3], &G = tmp[4];
+            // with R requested: the passes factor R_1, R_2, R_3 (A = Q R_3 R_2 R_1)
             const size_t r0 = tmp.size();
             if (a.R)
                 for (int i = 0; i < 3; ++i) tmp.push_back(make({Z, n, n}, 16));
-            TN_HIP(tnk::launch_strided_copy(a.A, a.a_esz, a.a_bs, a.a_rs, a.a_cs, X->p, 16, (int64_t)m * n, n, 1, m, n,
-                                            Z, a.a_conj, s));
             const double u = 1.1102230246251565e-16;
-            for (int pass = 0; pass < 3; ++pass) {
-                contract(op(*X, "bij", true), op(*X, "bik"), op(G, "bjk"));
+            for (int pass = 0; pass <= 3; ++pass) {
+                tnk::CqrPass c{};
+                c.m = m; c.n = n; c.batch = Z; c.rb = rb;
+                if (pass < 2) {
+                    c.src = a.A; c.s_esz = a.a_esz; c.s_bs = a.a_bs; c.s_rs = a.a_rs; c.s_cs = a.a_cs;
+                    c.s_conj = a.a_conj;
+                } else {
+                    const Ten &Xs = pass == 2 ? X1 : X2;
+                    c.src = Xs.p; c.s_esz = 16; c.s_bs = (int64_t)m * n; c.s_rs = n; c.s_cs = 1; c.s_conj = 0;
+                }
+                c.Ri = pass > 0 ? reinterpret_cast<const double *>(Ri.p) : nullptr;
+                if (pass == 1) c.X = reinterpret_cast<double *>(X1.p);
+                if (pass == 2) c.X = reinterpret_cast<double *>(X2.p);
+                if (pass == 3) {
+                    c.dst = a.Q; c.d_esz = a.q_esz; c.d_bs = a.q_bs; c.d_rs = a.q_rs; c.d_cs = a.q_cs;
+                    c.d_conj = a.q_conj;
+                } else {
+                    c.part = reinterpret_cast<double *>(Pg.p);
+                }
+                TN_HIP(tnk::launch_cqr_pass(c, s));
+                if (pass == 3) break;
                 // shift relative to tr(G)/n; tr(G) bounds ||A||_2^2
                 const double shift = pass == 0 ? 11.0 * ((double)m * n + (double)n * (n + 1)) * u * n : 0.0;
                 const double clamp = pass == 0 ? 1e-300 : 1e-14;
+                TN_HIP(tnk::launch_sum_parts(reinterpret_cast<const double *>(Pg.p), nblk, n, Z,
+                                             reinterpret_cast<double *>(G.p), s));
                 TN_HIP(tnk::launch_chol_inv(reinterpret_cast<const double *>(G.p), n, Z, shift, clamp,
                                             reinterpret_cast<double *>(Ri.p),
-                                            a.R ? reinterpret_cast<double *>(tmp[r0 + pass].p) : nullptr, nullptr, s));
-                contract(op(*X, "bij"), op(Ri, "bjk"), op(*Y, "bik"));
-                std::swap(X, Y);
+                                            a.R ? reinterpret_cast<double *>(tmp[r0 + pass].p) : nullptr, nullptr,
+                                            s));
             }
-            TN_HIP(tnk::launch_strided_copy(X->p, 16, (int64_t)m * n, n, 1, a.Q, a.q_esz, a.q_bs, a.q_rs, a.q_cs, m, n,
-                                            Z, a.q_conj, s));
             if (a.R) {
                 contract(op(tmp[r0 + 2], "bij"), op(tmp[r0 + 1], "bjk"), op(G, "bik"));
                 contract(op(G, "bij"), op(tmp[r0], "bjk"), op(Ri, "bik"));
@@ -1112,6 +1135,23 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
                     }
                 } else {
                     orthonormalise(b);
+                    if (j0 > 0 && !R) {
+                        // the block's factor scales what the projection left of
+                        // the finished blocks in it by up to its condition number:
+                        // project once more and orthonormalise again (Q only;
+                        // with R the inputs are well conditioned)
+                        const Op Qp = view(qp, "bij", {Z, m, j0}, {bs, n, 1});
+                        const Op Qpc = view(qp, "bij", {Z, m, j0}, {bs, n, 1}, true);
+                        const Op Qj = view(qp + (int64_t)j0 * 16, "bik", {Z, m, nb}, {bs, n, 1});
+                        Ten W = make({Z, j0, nb}, 16);
+                        contract(Qpc, Qj, op(W, "bjk"));
+                        TN_HIP(tnk::launch_scale(W.p, W.numel(), -1.0, 0.0, s));
+                        contract(Qp, op(W, "bjk"), Qj, true);
+                        drop(W);
+                        tnk::QrArgs c2 = b;
+                        c2.A = qp + (int64_t)j0 * 16;  // in place: read before Q is written
+                        orthonormalise(c2);
+                    }
                 }
             }
             TN_HIP(tnk::launch_strided_copy(Q.p, 16, bs, n, 1, a.Q, a.q_esz, a.q_bs, a.q_rs, a.q_cs, m, n, Z, a.q_conj,

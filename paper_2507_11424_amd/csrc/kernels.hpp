@@ -94,6 +94,23 @@ hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
 // workgroup per matrix; n <= 64.
 hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, double clamp, double *Rinv, double *Rf,
                            int *flags, hipStream_t s);
+// One CholeskyQR pass over row blocks of p.rb rows (see k_cqr_rows): rows of
+// the batch x m x n (n <= 64) source, times the previous pass's inverse factor
+// Ri when given, written to X (contiguous complex128) and/or dst (strided), and
+// the partial Gram matrices of the blocks written to part
+// ([batch][ceil(m / rb)][n][n], complex128) when given.
+struct CqrPass {
+    int m, n, batch, rb;
+    const void *src; int s_esz; int64_t s_bs, s_rs, s_cs; int s_conj;
+    const double *Ri;
+    double *X;
+    void *dst; int d_esz; int64_t d_bs, d_rs, d_cs; int d_conj;
+    double *part;
+};
+int cqr_rows_per_block(int m);
+// G[b] = sum over p of parts[b][p] (complex128, n x n each), in a fixed order.
+hipError_t launch_sum_parts(const double *parts, int nparts, int n, int batch, double *G, hipStream_t s);
+hipError_t launch_cqr_pass(const CqrPass &p, hipStream_t s);
 // Batched SVD truncation (one-sided Jacobi, FP64): R [batch][n][n] complex128
 // (row-major) = U diag(sigma) V^H with sigma descending; keeps the fewest k
 // values whose discarded weight sum_{j>=k} sigma_j^2 is at most cutoff times

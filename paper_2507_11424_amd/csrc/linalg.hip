@@ -11,6 +11,7 @@
 // factorisation in global memory.
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -18,6 +19,9 @@ namespace tnk {
 namespace {
 
 constexpr int QR_NT = 256;
+constexpr int CQR_ROWS = 32;  // rows of a CholeskyQR pass staged in LDS at a time
+constexpr int CQR_LD = 65;    // padded LDS row of those passes (complex doubles)
+constexpr int SUM_E = 8;      // entries per workgroup of the partial-sum reduction
 constexpr int QR_LDS = 8192;  // complex doubles held by one workgroup (128 KiB)
 constexpr int QR_G = QR_NT / 64;
 
@@ -389,24 +393,32 @@ __device__ inline void csub_conj_mul(double2 &w, double ax, double ay, double2 c
     w.y = fma(ay, c.x, w.y);
 }
 
-// NMAX rows of CL lanes each (64 x 16 = 1024 threads).
+// NMAX rows of CL lanes each (64 x 16 = 1024 threads).  G holds nparts
+// matrices per batch item ([batch][nparts][n][n]) whose sum is factored.
 template <int NMAX, int CL>
-__global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int n, double shift, double clamp,
-                                                       double2 *Rinv, double2 *Rf, int *flags) {
+__global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int nparts, int n, double shift,
+                                                       double clamp, double2 *Rinv, double2 *Rf, int *flags) {
     constexpr int CT = NMAX * CL;   // threads per matrix
     constexpr int CM = NMAX / CL;   // row elements per lane
     __shared__ double2 PW[2][NMAX];
     __shared__ double2 PE[2][NMAX];
+    __shared__ double PD[2][2];  // pivot (raised to the clamp if below it) and its reciprocal
     __shared__ double red[CT / 64];
     const int b = blockIdx.x, t = threadIdx.x;
-    const double2 *Gb = G + (int64_t)b * n * n;
+    const double2 *Gb = G + (int64_t)b * nparts * n * n;
     const int ti = t / CL, tq = t % CL;
     const bool row = ti < n;
     double2 w[CM], e[CM];
 #pragma unroll
     for (int m = 0; m < CM; ++m) {
         const int j = ti + tq + CL * m;
-        w[m] = (row && j < n) ? Gb[ti * n + j] : make_double2(0.0, 0.0);
+        w[m] = make_double2(0.0, 0.0);
+        if (row && j < n)
+            for (int q = 0; q < nparts; ++q) {  // fixed order: the sum is reproducible
+                const double2 g = Gb[((int64_t)q * n + ti) * n + j];
+                w[m].x += g.x;
+                w[m].y += g.y;
+            }
         const int je = tq + CL * m;
         e[m] = make_double2(row && je == ti ? 1.0 : 0.0, 0.0);
     }
@@ -423,27 +435,34 @@ __global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int n,
     const double scale = tr / n;
     const double sh = shift * scale, cl = clamp * scale;
     if (row && tq == 0) w[0].x += sh;
+    // the owner of a pivot row publishes the row, the pivot and its reciprocal
+    auto publish_pivot = [&](int slot) {
+        double d = w[0].x;
+        if (!(d >= cl)) {
+            if (flags) flags[b] |= 4;
+            d = cl > 0.0 ? cl : 1e-300;
+        }
+        PD[slot][0] = d;
+        PD[slot][1] = 1.0 / d;
+    };
     if (ti == 0) {
 #pragma unroll
         for (int m = 0; m < CM; ++m) {
             const int j = tq + CL * m;
             if (j < n) { PW[0][j] = w[m]; PE[0][j] = e[m]; }
         }
+        if (tq == 0) publish_pivot(0);
     }
     __syncthreads();
     double myrk = 1.0;  // 1 / sqrt of this row's pivot
     for (int k = 0; k < n; ++k) {
         const int pb = k & 1;
-        double d = PW[pb][k].x;
-        if (!(d >= cl)) {
-            if (t == 0 && flags) flags[b] |= 4;
-            d = cl > 0.0 ? cl : 1e-300;
-        }
+        const double d = PD[pb][0];
         if (ti == k) {
             myrk = 1.0 / sqrt(d);
             if (tq == 0) w[0] = make_double2(d, 0.0);  // a raised pivot stays consistent
         } else if (row && ti > k) {
-            const double inv = 1.0 / d;
+            const double inv = PD[pb][1];
             const double2 a = PW[pb][ti];
             const double ax = a.x * inv, ay = a.y * inv;
             double2 cw[CM], ce[CM];
@@ -465,6 +484,7 @@ __global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int n,
                     if (ti + j < n) PW[pb ^ 1][ti + j] = w[m];  // column ti + tq + CL m
                     if (j < n) PE[pb ^ 1][j] = e[m];
                 }
+                if (tq == 0) publish_pivot(pb ^ 1);  // w[0]: the diagonal, final after pivot k
             }
         }
         __syncthreads();
@@ -487,6 +507,163 @@ __global__ void __launch_bounds__(NMAX * CL) k_chol_inv(const double2 *G, int n,
             const int jl = tq + CL * m;
             if (jl < ti) Fb[ti * n + jl] = make_double2(0.0, 0.0);
         }
+    }
+}
+
+// One pass of CholeskyQR over a block of p.rb rows of a (batch x m x n,
+// n <= 64) complex matrix, 256 threads, CQR_ROWS rows staged in LDS at a time:
+// the rows are read through p.src's strides (complex64 or complex128,
+// conjugated if asked), multiplied by the inverse factor p.Ri of the previous
+// pass when given (Y = X Ri, Ri upper triangular), written to the contiguous
+// complex128 rows p.X and/or through p.dst's strides, and their Gram matrix
+// Y^H Y (upper triangle) is written to p.part[b][block] when p.part is given.
+// Each thread of the Gram owns a 4 x 4 block of it; each thread of the product
+// owns one row and 8 columns of Y.
+__global__ void __launch_bounds__(256) k_cqr_rows(CqrPass p) {
+    __shared__ double2 sRi[64][CQR_LD];
+    __shared__ double2 sA[CQR_ROWS][CQR_LD];
+    __shared__ double2 sY[CQR_ROWS][CQR_LD];
+    const int t = threadIdx.x, b = blockIdx.y, n = p.n;
+    const int r_beg = blockIdx.x * p.rb, r_end = min(p.m, r_beg + p.rb);
+    const bool apply = p.Ri != nullptr;
+    if (apply) {  // all loads issued before the LDS stores (n * n <= 16 * 256)
+        const double2 *Rb = reinterpret_cast<const double2 *>(p.Ri) + (int64_t)b * n * n;
+        double2 rv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + 256 * i;
+            rv[i] = e < n * n ? Rb[e] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + 256 * i;
+            if (e < n * n) sRi[e / n][e % n] = rv[i];
+        }
+    }
+    const int gi = (t >> 4) * 4, gj = (t & 15) * 4;        // Gram block
+    const bool gown = p.part && gi < n && gj < n && gi <= gj + 3;
+    double2 g[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[i][j] = make_double2(0.0, 0.0);
+    const int yr = t >> 3, yc = t & 7;                      // product: row yr, columns yc + 8 q
+    const bool by_col = p.s_cs != 1;                        // source contiguous along rows
+    for (int r0 = r_beg; r0 < r_end; r0 += CQR_ROWS) {
+        const int nr = min(CQR_ROWS, r_end - r0);
+        {   // CQR_ROWS * n <= 8 * 256 elements: all loads issued before the LDS stores
+            double2 av[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = t + 256 * i;
+                const int r = by_col ? e % CQR_ROWS : e / n, c = by_col ? e / CQR_ROWS : e % n;
+                av[i] = (e < CQR_ROWS * n && r < nr)
+                            ? ld_c(p.src, p.s_esz, (int64_t)b * p.s_bs + (int64_t)(r0 + r) * p.s_rs +
+                                                       (int64_t)c * p.s_cs, p.s_conj)
+                            : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = t + 256 * i;
+                const int r = by_col ? e % CQR_ROWS : e / n, c = by_col ? e / CQR_ROWS : e % n;
+                if (e < CQR_ROWS * n) sA[r][c] = av[i];
+            }
+        }
+        __syncthreads();
+        double2 (*Y)[CQR_LD] = sA;
+        if (apply) {
+            double2 y[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) y[q] = make_double2(0.0, 0.0);
+#pragma unroll 8
+            for (int k = 0; k < n; ++k) {
+                const double2 a = sA[yr][k];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = yc + 8 * q;
+                    if (j < n && k <= j) {
+                        const double2 r = sRi[k][j];
+                        y[q].x = fma(a.x, r.x, fma(-a.y, r.y, y[q].x));
+                        y[q].y = fma(a.x, r.y, fma(a.y, r.x, y[q].y));
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = yc + 8 * q;
+                if (j < n) sY[yr][j] = y[q];
+            }
+            __syncthreads();
+            Y = sY;
+        }
+        if (p.X)
+            for (int e = t; e < nr * n; e += 256) {
+                const int r = e / n, c = e % n;
+                reinterpret_cast<double2 *>(p.X)[((int64_t)b * p.m + r0 + r) * n + c] = Y[r][c];
+            }
+        if (p.dst)
+            for (int e = t; e < nr * n; e += 256) {
+                int r, c;
+                if (p.d_cs != 1) { c = e / nr; r = e % nr; }
+                else { r = e / n; c = e % n; }
+                st_c(p.dst, p.d_esz, (int64_t)b * p.d_bs + (int64_t)(r0 + r) * p.d_rs + (int64_t)c * p.d_cs, Y[r][c],
+                     p.d_conj);
+            }
+        if (gown)
+            for (int r = 0; r < nr; ++r) {
+                double2 xi[4], xj[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    xi[i] = Y[r][gi + i < n ? gi + i : 0];
+                    xj[i] = Y[r][gj + i < n ? gj + i : 0];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {  // conj(x_i) x_j
+                        g[i][j].x = fma(xi[i].x, xj[j].x, fma(xi[i].y, xj[j].y, g[i][j].x));
+                        g[i][j].y = fma(xi[i].x, xj[j].y, fma(-xi[i].y, xj[j].x, g[i][j].y));
+                    }
+            }
+        __syncthreads();
+    }
+    if (gown) {
+        double2 *P = reinterpret_cast<double2 *>(p.part) + ((int64_t)b * gridDim.x + blockIdx.x) * n * n;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (gi + i < n && gj + j < n) P[(gi + i) * n + gj + j] = g[i][j];
+    }
+}
+
+// G[b][e] = sum over p of parts[b][p][e] (e < nn), in a fixed order: 256
+// threads per SUM_E entries, each of the 256 / SUM_E slices sums the parts
+// p = slice, slice + slices, ... in order, then the slices are added in order.
+__global__ void __launch_bounds__(256) k_sum_parts(const double2 *parts, int nparts, int nn, double2 *G) {
+    constexpr int SL = 256 / SUM_E;
+    __shared__ double2 red[SL][SUM_E];
+    const int t = threadIdx.x, b = blockIdx.y;
+    const int el = t % SUM_E, sl = t / SUM_E;
+    const int e = blockIdx.x * SUM_E + el;
+    double2 acc = make_double2(0.0, 0.0);
+    if (e < nn) {
+        const double2 *P = parts + (int64_t)b * nparts * nn + e;
+        for (int q = sl; q < nparts; q += SL) {
+            const double2 v = P[(int64_t)q * nn];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+    }
+    red[sl][el] = acc;
+    __syncthreads();
+    if (sl == 0 && e < nn) {
+        double2 r = red[0][el];
+        for (int q = 1; q < SL; ++q) {
+            r.x += red[q][el].x;
+            r.y += red[q][el].y;
+        }
+        G[(int64_t)b * nn + e] = r;
     }
 }
 
@@ -518,7 +695,32 @@ hipError_t launch_chol_inv(const double *G, int n, int batch, double shift, doub
     if (n > 64 || n < 1) return hipErrorInvalidValue;
     const double2 *g = reinterpret_cast<const double2 *>(G);
     double2 *ri = reinterpret_cast<double2 *>(Rinv), *rf = reinterpret_cast<double2 *>(Rf);
-    hipLaunchKernelGGL((k_chol_inv<64, 16>), dim3(batch), dim3(1024), 0, s, g, n, shift, clamp, ri, rf, flags);
+    hipLaunchKernelGGL((k_chol_inv<64, 16>), dim3(batch), dim3(1024), 0, s, g, 1, n, shift, clamp, ri, rf, flags);
+    return hipGetLastError();
+}
+
+int cqr_rows_per_block(int m) {
+    // one staged chunk per workgroup (the passes are latency-bound: more
+    // workgroups, each with a short chain), at most 1024 blocks per matrix
+    const int per = (m + 1023) / 1024;
+    return std::max(CQR_ROWS, (per + CQR_ROWS - 1) / CQR_ROWS * CQR_ROWS);
+}
+
+hipError_t launch_sum_parts(const double *parts, int nparts, int n, int batch, double *G, hipStream_t s) {
+    if (n < 1 || nparts < 1 || batch < 1) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    const int nn = n * n;
+    hipLaunchKernelGGL(k_sum_parts, dim3((nn + SUM_E - 1) / SUM_E, batch), dim3(256), 0, s,
+                       reinterpret_cast<const double2 *>(parts), nparts, nn, reinterpret_cast<double2 *>(G));
+    return hipGetLastError();
+}
+
+hipError_t launch_cqr_pass(const CqrPass &p, hipStream_t s) {
+    if (p.m <= 0 || p.batch <= 0) return hipSuccess;
+    if (p.n < 1 || p.n > 64 || p.rb < CQR_ROWS || p.rb % CQR_ROWS) return hipErrorInvalidValue;
+    if (p.batch > 65535) return hipErrorInvalidValue;
+    const int nblk = (p.m + p.rb - 1) / p.rb;
+    hipLaunchKernelGGL(k_cqr_rows, dim3(nblk, p.batch), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -270,6 +270,30 @@ def test_orthonormalise(handle, m, n, batch, esz, cond):
         assert np.abs(proj - A[b]).max() < tol * 10 * np.abs(A[b]).max()
 
 
+@pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (512, 64, 16), (700, 33, 2), (37, 5, 3), (4097, 64, 1)])
+@pytest.mark.parametrize("esz", [16, 8])
+def test_orthonormalise_lq_layout(handle, m, n, batch, esz):
+    """The LQ moves' CholeskyQR3: the input is read and Q written through
+    conjugate-transposed strides (rows of the n x m operand), m past several
+    row blocks and a ragged last block."""
+    import torch
+    rng = np.random.default_rng(m * 3 + n)
+    B = _rand(rng, (batch, n, m))
+    if esz == 8:
+        B = B.astype(np.complex64).astype(np.complex128)
+    td = torch.complex128 if esz == 16 else torch.complex64
+    dB = torch.from_numpy(B).to("cuda", td)
+    dQ = torch.zeros((batch, n, m), dtype=td, device="cuda")
+    handle.test_qr(dB, dQ, None, method="cholesky_lq")
+    torch.cuda.synchronize()
+    Q = dQ.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if esz == 16 else 1e-5
+    for b in range(batch):
+        assert np.abs(Q[b] @ Q[b].conj().T - np.eye(n)).max() < tol * 10
+        proj = (B[b] @ Q[b].conj().T) @ Q[b]
+        assert np.abs(proj - B[b]).max() < tol * 10 * np.abs(B[b]).max()
+
+
 @pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (64, 64, 3), (512, 8, 4), (700, 33, 2), (8192, 128, 1),
                                        (300, 200, 2)])
 def test_cholesky_qr_with_r(handle, m, n, batch):
