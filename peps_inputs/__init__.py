@@ -24,7 +24,24 @@ Lattices:
   bridge qubits of a heavy-hex lattice merged into their neighbours;
 * ``rotated_square``: 105-qubit 45-degree-rotated square lattice shaped like
   the Willow chip (10 staggered rows of 11/10 qubits), mapped into a 15 x 15
-  grid by (r, x) -> (u, v) = ((r + x) / 2, (x - r) / 2 + 4).
+  grid by (r, x) -> (u, v) = ((r + x) / 2, (x - r) / 2 + 4): the partitions
+  are the chip's diagonal cuts;
+* ``heavy_hex``: heavy-hex lattice with its degree-2 bridge qubits as sites of
+  their own: chains of qubits on the even grid rows, one bridge qubit every
+  ``period`` columns on the odd rows between them (columns offset by half a
+  period on alternate bridge rows), bonded to the chain qubits above and below;
+  the other positions of the bridge rows are dummies.  Its hexagons have 12
+  qubits (2 bridges and 5 qubits of each chain);
+* ``staggered``: a rotated square lattice (chip rows r with x = r mod 2,
+  r mod 2 + 2, ..; neighbours (r +- 1, x +- 1)) partitioned into its staggered
+  rows, the chip row r being grid row r and x the grid column.  A qubit's two
+  down-diagonal bonds are fused into one down leg (index a * D_b + b, a the
+  bond to (r + 1, x - 1), b the one to (r + 1, x + 1)); the grid position
+  below it, (r + 1, x), holds a *junction*: a fixed tensor without a qubit that
+  splits that leg into its left (a) and right (b) legs, J[0][a * D_b + b][a][0][b]
+  = 1.  The qubit (r + 1, x - 1) then reaches (r, x) through its right leg, and
+  (r + 1, x + 1) through its left leg.  A row's MPO therefore alternates
+  qubits and junctions (a staircase of diagonal bonds in grid form).
 
 Tensor recipes (synthetic stand-ins for circuit-evolved states, which the paper
 does not publish):
@@ -46,7 +63,8 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "Lattice", "square_lattice", "brick_lattice", "rotated_square_lattice",
+    "Lattice", "square_lattice", "brick_lattice", "rotated_square_lattice", "heavy_hex_lattice",
+    "staggered_lattice", "staggered_sites", "junction_tensor",
     "site_dims", "random_peps", "make_config", "CONFIGS", "sample_uniforms",
     "flatten_peps",
 ]
@@ -56,10 +74,12 @@ __all__ = [
 class Lattice:
     """A planar lattice embedded in a rows x cols grid.
 
-    phys[r][c]       : 2 for a qubit, 1 for a dummy grid position.
+    phys[r][c]       : 2 for a qubit, 1 for a grid position without one.
     dim_h[r][c]      : bond dimension between (r, c) and (r, c+1); 1 = absent.
     dim_v[r][c]      : bond dimension between (r, c) and (r+1, c); 1 = absent.
-    site_index[r][c] : position of the qubit in a bitstring, -1 for dummies.
+    site_index[r][c] : position of the qubit in a bitstring, -1 for non-qubits.
+    junction[r][c]   : True where a non-qubit position holds a junction tensor
+                       (``staggered`` lattices); other non-qubits are dummies.
     """
     name: str
     rows: int
@@ -68,13 +88,18 @@ class Lattice:
     dim_h: np.ndarray
     dim_v: np.ndarray
     site_index: np.ndarray
+    junction: Optional[np.ndarray] = None
     n_qubits: int = field(init=False)
 
     def __post_init__(self):
         self.n_qubits = int((self.site_index >= 0).sum())
+        if self.junction is None:
+            self.junction = np.zeros((self.rows, self.cols), dtype=bool)
 
     def transposed(self) -> "Lattice":
         """The same lattice with rows and columns exchanged."""
+        if self.junction.any():
+            raise ValueError("a lattice with junctions has a fixed leg layout and is not transposed")
         return Lattice(self.name + "^T", self.cols, self.rows, self.phys.T.copy(),
                        self.dim_v.T.copy(), self.dim_h.T.copy(), self.site_index.T.copy())
 
@@ -138,6 +163,77 @@ def rotated_square_lattice(D: int, chip_rows: int = 10, xmax: int = 20) -> Latti
     return lat
 
 
+def heavy_hex_lattice(chains: int, length: int, D: int, period: int = 4) -> Lattice:
+    """Heavy-hex lattice with degree-2 bridge sites: ``chains`` chains of
+    ``length`` qubits on grid rows 0, 2, .., 2 (chains - 1); on grid row
+    2 i + 1 a bridge qubit at every column c with c % period == offset_i
+    (offset_i = 0 for even i, period // 2 for odd i), bonded to (2 i, c) and
+    (2 i + 2, c).  Chain qubits have degree <= 3, bridges degree 2."""
+    rows, cols = 2 * chains - 1, length
+    phys = np.ones((rows, cols), dtype=np.int32)
+    dim_h = np.ones((rows, max(cols - 1, 0)), dtype=np.int32)
+    dim_v = np.ones((max(rows - 1, 0), cols), dtype=np.int32)
+    for i in range(chains):
+        phys[2 * i, :] = 2
+        dim_h[2 * i, :] = D
+    for i in range(chains - 1):
+        off = 0 if i % 2 == 0 else period // 2
+        for c in range(cols):
+            if c % period == off:
+                phys[2 * i + 1, c] = 2
+                dim_v[2 * i, c] = D
+                dim_v[2 * i + 1, c] = D
+    return Lattice(f"heavyhex{chains}x{length}_D{D}", rows, cols, phys, dim_h, dim_v, _index_sites(phys))
+
+
+def staggered_sites(chip_rows: int, xmax: int):
+    """Qubit positions (r, x) of a rotated square lattice: x = r % 2,
+    r % 2 + 2, .. <= xmax in chip row r."""
+    return [(r, x) for r in range(chip_rows) for x in range(r % 2, xmax + 1, 2)]
+
+
+def staggered_lattice(D: int, chip_rows: int = 10, xmax: int = 20) -> Lattice:
+    """The rotated square lattice of ``staggered_sites`` partitioned into its
+    chip rows, with junctions below the qubits (see the module docstring).  The
+    defaults give the 105-qubit chip in a 10 x 21 grid."""
+    occ = set(staggered_sites(chip_rows, xmax))
+    rows, cols = chip_rows, xmax + 1
+
+    def diag(r, x, dx):  # dimension of the bond from (r, x) to (r + 1, x + dx)
+        return D if (r, x) in occ and (r + 1, x + dx) in occ else 1
+
+    phys = np.ones((rows, cols), dtype=np.int32)
+    junction = np.zeros((rows, cols), dtype=bool)
+    dim_h = np.ones((rows, max(cols - 1, 0)), dtype=np.int32)
+    dim_v = np.ones((max(rows - 1, 0), cols), dtype=np.int32)
+    for (r, x) in occ:
+        phys[r, x] = 2
+        a, b = diag(r, x, -1), diag(r, x, +1)
+        if r + 1 < rows and a * b > 1:
+            dim_v[r, x] = a * b
+            junction[r + 1, x] = True
+            if x - 1 >= 0:
+                dim_h[r + 1, x - 1] = a   # (r + 1, x - 1) -- junction (r + 1, x)
+            if x + 1 < cols:
+                dim_h[r + 1, x] = b       # junction (r + 1, x) -- (r + 1, x + 1)
+    lat = Lattice(f"stag{len(occ)}_D{D}", rows, cols, phys, dim_h, dim_v, _index_sites(phys), junction)
+    if (chip_rows, xmax) == (10, 20):
+        assert lat.n_qubits == 105
+    return lat
+
+
+def junction_tensor(lat: Lattice, r: int, c: int) -> np.ndarray:
+    """J[0][a * D_b + b][a][0][b] = 1: the junction at (r, c) splitting its up
+    leg into its left and right legs."""
+    p, du, dl, dd, dr = site_dims(lat, r, c)
+    assert p == 1 and dd == 1 and du == dl * dr
+    t = np.zeros((1, du, dl, 1, dr), dtype=np.complex128)
+    for a in range(dl):
+        for b in range(dr):
+            t[0, a * dr + b, a, 0, b] = 1.0
+    return t
+
+
 def site_dims(lat: Lattice, r: int, c: int):
     """(p, Du, Dl, Dd, Dr) of grid position (r, c)."""
     p = int(lat.phys[r, c])
@@ -164,6 +260,9 @@ def random_peps(lat: Lattice, recipe: str, eps: float, seed: int,
         row = []
         for c in range(lat.cols):
             p, du, dl, dd, dr = site_dims(lat, r, c)
+            if lat.junction[r, c]:
+                row.append(junction_tensor(lat, r, c).astype(dtype))
+                continue
             if p == 1:
                 # dummy: every leg is dimension 1 because every bond touching it is absent
                 t = np.ones((1, du, dl, dd, dr), dtype=np.complex128)
@@ -230,6 +329,10 @@ def build_lattice(spec) -> Lattice:
         return brick_lattice(rows, cols, D)
     if kind == "rotsq":
         return rotated_square_lattice(D)
+    if kind == "heavyhex":
+        return heavy_hex_lattice(rows, cols, D)
+    if kind == "stag":
+        return staggered_lattice(D)
     raise ValueError(kind)
 
 

@@ -6,7 +6,11 @@
 * exact statevectors (the definition of the state) for the norm, one-site
   density matrices, <ZZ>, and per-sample q(x) = |psi(x)|^2 / Z at exact bond;
 * the product-state closed form (D = 1) and the single-row case (an MPS,
-  perfect sampling).
+  perfect sampling);
+* for the staggered-row partition of the rotated square lattice (qubits with
+  fused down-diagonal legs and junction tensors in the grid), the state of the
+  native diagonal network, contracted directly with one tensor per qubit and
+  one index per diagonal bond.
 """
 import itertools
 import math
@@ -15,7 +19,8 @@ import numpy as np
 import pytest
 
 from peps_inputs import (square_lattice, brick_lattice, random_peps, Lattice, site_dims,
-                         rotated_square_lattice, make_config)
+                         rotated_square_lattice, make_config, heavy_hex_lattice, staggered_lattice,
+                         staggered_sites)
 from oracle import philox
 from oracle.statevector import statevector, brute_force_amplitude
 from oracle.boundary import norm, boundary_set, plan_bonds
@@ -121,6 +126,10 @@ EXACT_CASES = [
     ("c1", None, None, None, None, 16),
     # rotated square patch: 10 qubits in a 4x4 embedding with dummy sites
     ("rotsq10D2", lambda: rotated_square_lattice(2, 4, 4), "haar", 0.5, 24, 64),
+    # heavy-hex with bridge sites: 3 chains of 5 and 3 bridges (18 qubits)
+    ("heavyhex3x5D2", lambda: heavy_hex_lattice(3, 5, 2), "haar", 0.5, 25, 64),
+    # the same 10-qubit rotated square in staggered rows (junctions, fused legs)
+    ("stag10D2", lambda: staggered_lattice(2, 4, 4), "haar", 0.5, 26, 256),
 ]
 
 
@@ -156,7 +165,7 @@ def test_c1_bond_16_is_exact():
     assert any(i["mode"] == "fit" for i in info8[:-1])
 
 
-@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2"])
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2", "heavyhex3x5D2", "stag10D2"])
 def test_environments_exact(name):
     lat, T, chi = _case(name)
     psi = statevector(T, lat.site_index)
@@ -189,7 +198,7 @@ def test_environments_exact(name):
                 assert np.abs(np.array(p2) - env["p2_v"][r, c]).max() < 1e-12
 
 
-@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1", "rotsq10D2"])
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1", "rotsq10D2", "heavyhex3x5D2", "stag10D2"])
 @pytest.mark.parametrize("force_fit", [False, True])
 def test_sampler_exact_q_equals_p_over_Z(name, force_fit):
     lat, T, chi = _case(name)
@@ -255,7 +264,7 @@ def test_plan_bonds_consistency():
     assert t == [2, 3, 2]
 
 
-@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2"])
+@pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "rotsq10D2", "heavyhex3x5D2", "stag10D2"])
 @pytest.mark.parametrize("rows_limit", [1, 2])
 def test_sampler_partial_rows_and_conditionals_exact(name, rows_limit):
     """At exact bond, the per-qubit conditionals are ratios of statevector
@@ -286,3 +295,96 @@ def test_sampler_partial_rows_and_conditionals_exact(name, rows_limit):
         assert np.all(np.isnan(lc[i, [q for q in range(n_q) if q not in done]]))
         assert not np.any(bits[i, [q for q in range(n_q) if q not in done]])
         assert math.isnan(lp[i])
+
+
+# --------------------------------------------------------------------------- new partitions
+
+def test_heavy_hex_geometry():
+    """Chain qubits have degree <= 3, bridges degree 2; every hexagon of the
+    3 x 9 patch has 12 qubits: 2 bridges and 5 qubits of each chain."""
+    lat = heavy_hex_lattice(3, 9, 2)
+    deg = np.zeros((lat.rows, lat.cols), int)
+    deg[:, :-1] += lat.dim_h > 1
+    deg[:, 1:] += lat.dim_h > 1
+    deg[:-1, :] += lat.dim_v > 1
+    deg[1:, :] += lat.dim_v > 1
+    chain = lat.phys.copy() == 2
+    chain[1::2, :] = False
+    bridge = (lat.phys == 2) & ~chain
+    assert deg[chain].max() == 3 and set(deg[bridge].tolist()) == {2}
+    assert deg[lat.phys == 1].max() == 0
+    assert bridge.sum() == 3 + 2 and lat.n_qubits == 27 + 5
+    # bonds: 8 per chain, 2 per bridge; a planar graph with V - E + F = 2 has
+    # E - V + 1 bounded faces: here 4 hexagons of 12 edges (+ the outer face)
+    V, E = lat.n_qubits, 3 * 8 + 2 * 5
+    assert E - V + 1 == 3
+
+
+def _native_state(lat, T, D):
+    """The state of the staggered lattice contracted as its native network:
+    qubit (r, x) with legs (p, ul, ur, dl, dr), one index per diagonal bond,
+    read off the grid tensors (left leg = up-left bond, right leg = up-right
+    bond, down leg = the fused pair of down bonds) without the junctions."""
+    occ = {(r, x) for r in range(lat.rows) for x in range(lat.cols) if lat.phys[r, x] == 2}
+    letters = iter("abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ")
+    bond = {}
+
+    def lab(u, v):
+        key = (min(u, v), max(u, v))
+        if key not in bond:
+            bond[key] = next(letters)
+        return bond[key]
+
+    ops, terms, out = [], [], []
+    for (r, x) in sorted(occ, key=lambda q: lat.site_index[q]):
+        t = T[r][x]
+        p, du, dl, dd, dr = t.shape
+        assert du == 1
+        ul, ur = (r - 1, x - 1), (r - 1, x + 1)
+        dlq, drq = (r + 1, x - 1), (r + 1, x + 1)
+        a = D if dlq in occ else 1
+        b = D if drq in occ else 1
+        nat = t.reshape(p, dl, a, b, dr)          # (p, ul, dl, dr, ur) after unfusing
+        legs, sub = [], ["P%d" % lat.site_index[r, x]]
+        names = []
+        for nb, ext in ((ul, dl), (dlq, a), (drq, b), (ur, dr)):
+            if nb in occ:
+                names.append(lab((r, x), nb))
+            else:
+                assert ext == 1
+                names.append(None)
+        keep = [i + 1 for i, nm in enumerate(names) if nm is not None]
+        sl = tuple(slice(None) if (i == 0 or i in keep) else 0 for i in range(5))
+        ops.append(nat[sl])
+        terms.append([nm for nm in names if nm is not None])
+    phys_letters = [next(letters) for _ in ops]
+    expr = ",".join(pl + "".join(tm) for pl, tm in zip(phys_letters, terms)) + "->" + "".join(phys_letters)
+    return np.einsum(expr, *ops, optimize=True)
+
+
+@pytest.mark.parametrize("shape", [(3, 4), (4, 4), (4, 6)])
+def test_staggered_embedding_matches_native_network(shape):
+    """The grid embedding (fused legs + junction tensors) holds the same state
+    as the native diagonal network; the staggered 10-qubit patch and the
+    45-degree embedding of the same lattice hold the same norm at exact bond."""
+    rows, xmax = shape
+    lat = staggered_lattice(2, rows, xmax)
+    assert lat.n_qubits == len(staggered_sites(rows, xmax))
+    T = random_peps(lat, "haar", 0.6, 40 + rows + xmax)
+    psi_grid = statevector(T, lat.site_index)
+    psi_nat = _native_state(lat, T, 2)
+    assert np.abs(psi_grid - psi_nat).max() < 1e-13 * max(1.0, np.abs(psi_nat).max())
+    lz, _ = norm(T, 256)
+    assert abs(lz - math.log(np.sum(np.abs(psi_nat) ** 2))) < 1e-11
+
+
+def test_staggered_geometry_105():
+    lat = staggered_lattice(8)
+    assert (lat.rows, lat.cols, lat.n_qubits) == (10, 21, 105)
+    # 180 diagonal bonds: each appears once as a fused down leg and once as a
+    # junction leg (left or right)
+    fused = lat.dim_v[lat.dim_v > 1]
+    assert sum(int(round(math.log(int(v), 8))) for v in fused) == 180
+    assert (lat.dim_h > 1).sum() == 180
+    # one junction below every qubit of chip rows 0..8 (5 rows of 11, 4 of 10)
+    assert lat.junction.sum() == 5 * 11 + 4 * 10
