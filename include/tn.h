@@ -40,8 +40,11 @@
  *
  * Site tensor layout: complex, interleaved (re, im), row-major with index order
  * [p][u][l][d][r] (physical, up, left, down, right).  A bond that is absent or
- * leaves the grid has dimension 1; a grid position without a qubit is a dummy
- * site with p = 1.
+ * leaves the grid has dimension 1; a grid position without a qubit has p = 1:
+ * a dummy (every bond 1, the tensor is a scalar) or a tensor without a
+ * physical index that carries bonds, such as the junction of a staggered-row
+ * partition that splits a fused pair of diagonal bonds into its left and right
+ * legs.
  */
 #ifndef TN_H
 #define TN_H
@@ -81,10 +84,10 @@ typedef enum {
  * the rows (Methods: partitions forming a line). */
 typedef struct {
     int32_t rows, cols;
-    const int32_t *phys;        /* host [rows*cols]: 2 for a qubit, 1 for a dummy        */
+    const int32_t *phys;        /* host [rows*cols]: 2 for a qubit, 1 for a non-qubit    */
     const int32_t *dim_h;       /* host [rows*(cols-1)]: bond (r,c)-(r,c+1), >= 1        */
     const int32_t *dim_v;       /* host [(rows-1)*cols]: bond (r,c)-(r+1,c), >= 1        */
-    const int32_t *site_index;  /* host [rows*cols]: bit position of the qubit, -1 dummy */
+    const int32_t *site_index;  /* host [rows*cols]: bit position of the qubit, -1 else  */
     tn_dtype dtype;             /* element type of every site tensor                     */
     const void *const *site;    /* host array [rows*cols] of DEVICE pointers, layout above */
 } tn_peps;

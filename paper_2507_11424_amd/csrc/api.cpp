@@ -99,7 +99,7 @@ void validate(const tn_peps *p, const tn_opts *o) {
             seen[q] = 1;
             ++nq;
         } else if (p->site_index[i] != -1) {
-            throw TnError(ST_SHAPE, "dummy sites must have site_index -1");
+            throw TnError(ST_SHAPE, "non-qubit sites (phys 1) must have site_index -1");
         }
     }
     for (int q = 0; q < nq; ++q)
@@ -127,8 +127,6 @@ PepsDev stage(Engine &E, const tn_peps *p) {
             const int d = r + 1 < p->rows ? p->dim_v[r * p->cols + c] : 1;
             const int l = c > 0 ? p->dim_h[r * (p->cols - 1) + c - 1] : 1;
             const int rr = c + 1 < p->cols ? p->dim_h[r * (p->cols - 1) + c] : 1;
-            if (p->phys[i] == 1 && (u != 1 || d != 1 || l != 1 || rr != 1))
-                throw TnError(ST_SHAPE, "a dummy site must have only dimension-1 bonds");
             Ten t = E.make({p->phys[i], u, l, d, rr});
             TN_HIP(tnk::launch_convert(p->site[i], src_esz, t.p, t.esz, t.numel(), E.s));
             P.site.push_back(t);

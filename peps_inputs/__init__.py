@@ -318,6 +318,12 @@ CONFIGS = {
                  dtype="c64", chi=256, chi_x=16, n_samples=8192),
     "c5hh": dict(lattice=("brick", 12, 12, 16), recipe="haar", eps=0.2, seed=1006,
                  dtype="c64", chi=256, chi_x=16, n_samples=8192),
+    # heavy-hex with its bridge qubits as sites: 7 chains of 15 and 24 bridges (129 qubits)
+    "hhx": dict(lattice=("heavyhex", 7, 15, 8), recipe="haar", eps=0.2, seed=1007,
+                dtype="c64", chi=64, chi_x=64, n_samples=64),
+    # the 105-qubit rotated square partitioned into its staggered rows (junctions)
+    "stag": dict(lattice=("stag", 0, 0, 4), recipe="haar", eps=0.2, seed=1008,
+                 dtype="c64", chi=64, chi_x=32, n_samples=64),
 }
 
 
