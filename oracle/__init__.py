@@ -22,7 +22,10 @@ Plain, slow, obviously correct NumPy (complex128) following Rudolph & Tindall,
                       guesses and draws;
 * ``bp``           -- belief propagation on the norm network, the BP norm
                       estimate and the loop BP error (Methods, Eqs. avBPError
-                      and loopBPerror; Appendix, message update).
+                      and loopBPerror; Appendix, message update);
+* ``circuit``      -- two-qubit gates by BP-gauged simple update, the gate
+                      error and the fidelity estimate (Methods, circuit
+                      simulation, Eqs. error_per_gate and total_fidelity).
 
 Pins (tests marked ``not gpu``): exact statevectors on lattices of <= 16
 qubits, brute-force summation over bond assignments, NumPy's own Philox,
@@ -38,3 +41,4 @@ from .sampler import sample, sample_one, fit_single, SamplingError  # noqa: F401
 from .environments import environments, z_expectation  # noqa: F401
 from .verify import amplitude, amplitudes, sample_stats  # noqa: F401
 from .bp import bp_messages, bp_log_norm, primitive_loops, loop_bp_error  # noqa: F401
+from .circuit import simple_update, apply_gate, message_roots  # noqa: F401
