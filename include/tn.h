@@ -224,6 +224,36 @@ tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, d
                 int *sweeps, double *last_change, double *eps_mean, double *eps_loops, int eps_capacity,
                 int *n_loops, void *messages);
 
+/* Circuit simulation by BP-gauged simple update (Methods, "Quantum Circuit
+ * Simulation", Eqs. error_per_gate and total_fidelity; Appendix, "Applying
+ * Gates to a Tensor Network State").  Applies n_gates two-qubit gates, in list
+ * order, to the state `peps` and writes the result to site_out (host array
+ * [rows*cols] of DEVICE pointers, each sized and typed like the matching input
+ * site; it may equal the input's to update in place).  Bond dimensions stay
+ * those of the lattice.
+ *   gate_sites  host [n_gates][5] int32: group, r, c, r2, c2 with (r2, c2) =
+ *               (r, c+1) or (r+1, c), both sites qubits.  The BP messages of
+ *               the norm network are recomputed whenever `group` differs from
+ *               the previous gate's (gates of one group must share no qubit).
+ *   gates       host complex128 4 x 4 row-major unitaries in the basis 2a + b,
+ *               a the qubit at (r, c): gate_stride 16 = one matrix per gate,
+ *               0 = one matrix for all.
+ *   bp_max_sweeps, bp_tol  BP schedule (as tn_bp).
+ *   eps         host [n_gates] out: the discarded weight of each gate's
+ *               normalised singular values, sum_{j>=D} s_j^2 / sum_j s_j^2.
+ *   fidelity    host out (may be NULL): prod_i (1 - eps_i).
+ * Per gate: the pair gauged with the square roots of its incoming messages
+ * (pseudo-inverse roots to undo it; message eigenvalues at or below 1e-12 of
+ * the largest taken as 0), reduced by QR, the gate applied, an SVD kept to
+ * min(D, rank) values (rank: above 1e-12 of the largest) split as U S^1/2 and
+ * S^1/2 V^H.  FP64 arithmetic whatever the input type (complex64 results are
+ * rounded once on output).  Bonds up to 32.  Synchronises the stream.
+ * TN_ERR_INVALID for a malformed gate list, TN_ERR_UNSUPPORTED above the bond
+ * limit. */
+tn_status tn_simple_update(tn_handle *h, const tn_peps *peps, void *const *site_out, int n_gates,
+                           const int32_t *gate_sites, const double *gates, int gate_stride, int bp_max_sweeps,
+                           double bp_tol, double *eps, double *fidelity);
+
 /* Sample-quality metrics from per-sample log q and log p (device [n] doubles,
  * natural logs), with w_i = p(x_i)/q(x_i) (Methods, the unbiased norm
  * estimator, Eq. kld and the importance-sampling formula, read in its

@@ -25,7 +25,9 @@ Readings where the paper is silent:
   U diag(sqrt(lambda)) U^H over its eigenvalues lambda > 1e-12 lambda_max, the
   others (rounding of a rank-deficient message, e.g. a product state's) taken
   as 0; the inverse square root keeps 1 / sqrt(lambda) over the same
-  eigenvalues (a pseudo-inverse);
+  eigenvalues (a pseudo-inverse: the gauge round trip projects each leg on the
+  support of its message, which leaves the pair's contraction with its
+  neighbour unchanged);
 * the bond keeps the lattice dimension D: the SVD keeps min(D, rank) values,
   rank = the count of singular values above 1e-12 of the largest; the kept
   factors are U sqrt(S) on the first qubit's side and sqrt(S) V^H on the

@@ -32,7 +32,7 @@ STATUS = {0: "TN_OK", 1: "TN_ERR_INVALID", 2: "TN_ERR_SHAPE", 3: "TN_ERR_OOM", 4
 EXPORTS = ["tn_default_opts", "tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments",
            "tn_sample", "tn_amplitude", "tn_sample_stats", "tn_last_error", "tn_get_counters", "tn_set_timing",
            "tn_set_autotune", "tn_plan_report", "tn_test_contract", "tn_test_qr", "tn_test_svd", "tn_test_set_mask",
-           "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig"]
+           "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig", "tn_simple_update"]
 
 
 class TnError(RuntimeError):
@@ -99,10 +99,12 @@ def lib(path: Optional[str] = None):
     L.tn_bp.argtypes = [vp, ctypes.POINTER(c_peps), ctypes.c_int, ctypes.c_double, dp, dp, ip, dp, dp, dp,
                         ctypes.c_int, ip, vp]
     L.tn_test_eig.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
+    L.tn_simple_update.argtypes = [vp, ctypes.POINTER(c_peps), vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, vp, dp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
               "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats",
-              "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig"):
+              "tn_test_sample_config", "tn_sample_stats_noalloc", "tn_bp", "tn_test_eig", "tn_simple_update"):
         getattr(L, f).restype = ctypes.c_int
     if path is None:
         _lib = L
@@ -320,6 +322,29 @@ class Handle:
         if msgs is not None:
             res["messages"] = msgs
         return res
+
+    def simple_update(self, peps: Peps, gates, G, bp_max_sweeps: int = 1000, bp_tol: float = 1e-13,
+                      in_place: bool = False):
+        """Applies two-qubit gates by BP-gauged simple update (see
+        tn_simple_update).  gates: sequence of (group, r, c, r2, c2); G: one
+        4 x 4 complex matrix for all gates or one per gate.  Returns (Peps of
+        the result, gate errors eps (numpy), fidelity estimate prod(1 - eps));
+        in_place writes the result into peps's own tensors."""
+        import torch
+        gl = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 5))
+        Gm = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
+        stride = 0 if Gm.ndim == 2 else 16
+        if Gm.shape[-2:] != (4, 4) or (stride and Gm.shape[0] != gl.shape[0]):
+            raise ValueError("G: one 4 x 4 matrix, or one per gate")
+        out = peps if in_place else Peps(peps.lattice, [torch.empty_like(t) for t in peps.tensors])
+        ptrs = (ctypes.c_void_p * len(out.tensors))(*[t.data_ptr() for t in out.tensors])
+        eps = np.zeros(gl.shape[0], dtype=np.float64)
+        f = ctypes.c_double()
+        self._check(lib().tn_simple_update(self.h, ctypes.byref(peps.c), ptrs, int(gl.shape[0]),
+                                           gl.ctypes.data_as(ctypes.c_void_p), Gm.ctypes.data_as(ctypes.c_void_p),
+                                           stride, int(bp_max_sweeps), float(bp_tol),
+                                           eps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(f)))
+        return out, eps, f.value
 
     def test_eig(self, A):
         """Eigenvalues (unordered), eps and info of complex128 matrices A

@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtnbmps.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["gett.hip", "linalg.hip", "svd.hip", "small.hip", "bp_kernels.hip", "engine.cpp", "boundary.cpp", "sampler.cpp",
-           "environments.cpp", "bp.cpp", "api.cpp"]
+SOURCES = ["gett.hip", "linalg.hip", "svd.hip", "small.hip", "bp_kernels.hip", "su_kernels.hip", "engine.cpp", "boundary.cpp", "sampler.cpp",
+           "environments.cpp", "bp.cpp", "circuit.cpp", "api.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          # no packed FP32 instructions in device code

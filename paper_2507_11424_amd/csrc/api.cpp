@@ -356,6 +356,64 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
     }
 }
 
+tn_status tn_simple_update(tn_handle *h, const tn_peps *p, void *const *site_out, int n_gates,
+                           const int32_t *gate_sites, const double *gates, int gate_stride, int bp_max_sweeps,
+                           double bp_tol, double *eps, double *fidelity) {
+    try {
+        begin(h, nullptr);
+        tn_opts dflt;
+        tn_default_opts(&dflt);
+        validate(p, &dflt);
+        if (n_gates < 0) throw TnError(ST_INVALID, "n_gates must be >= 0");
+        if (!site_out || (n_gates > 0 && (!gate_sites || !gates || !eps)))
+            throw TnError(ST_INVALID, "null pointer");
+        if (gate_stride != 0 && gate_stride != 16) throw TnError(ST_INVALID, "gate_stride must be 0 or 16");
+        if (bp_max_sweeps < 1 || !(bp_tol >= 0.0)) throw TnError(ST_INVALID, "bp_max_sweeps >= 1 and bp_tol >= 0");
+        const int rows = p->rows, cols = p->cols;
+        std::vector<SuGate> gl((size_t)n_gates);
+        for (int g = 0; g < n_gates; ++g) {
+            const int32_t *q = gate_sites + (size_t)g * 5;
+            SuGate x{q[0], q[1], q[2], q[3], q[4]};
+            const bool h_ok = x.r2 == x.r && x.c2 == x.c + 1, v_ok = x.c2 == x.c && x.r2 == x.r + 1;
+            if (!(h_ok || v_ok) || x.r < 0 || x.c < 0 || x.r2 >= rows || x.c2 >= cols)
+                throw TnError(ST_INVALID, "gate " + std::to_string(g) + ": sites must be (r, c) and (r, c+1) or (r+1, c)");
+            if (p->phys[x.r * cols + x.c] != 2 || p->phys[x.r2 * cols + x.c2] != 2)
+                throw TnError(ST_INVALID, "gate " + std::to_string(g) + ": both sites must hold qubits");
+            gl[(size_t)g] = x;
+        }
+        Engine &E = *h->E;
+        E.set_prec(tnk::P_FP64);
+        PepsDev P = stage(E, p);
+        try {
+            SuOpts so;
+            so.bp_max_sweeps = bp_max_sweeps;
+            so.bp_tol = bp_tol;
+            simple_update(E, P, gl, gates, gate_stride, so, eps);
+            const int dst_esz = p->dtype == TN_C128 ? 16 : 8;
+            for (int i = 0; i < rows * cols; ++i) {
+                const Ten &t = P.site[(size_t)i];
+                if (!site_out[i]) throw TnError(ST_INVALID, "null output site");
+                TN_HIP(tnk::launch_convert(t.p, 16, site_out[i], dst_esz, t.numel(), E.s));
+            }
+            E.sync();
+        } catch (...) {
+            unstage(E, P);
+            throw;
+        }
+        unstage(E, P);
+        if (fidelity) {
+            double f = 1.0;
+            for (int g = 0; g < n_gates; ++g) f *= 1.0 - eps[g];
+            *fidelity = f;
+        }
+        return TN_OK;
+    } catch (const TnError &e) {
+        return fail(h, e);
+    } catch (const std::exception &e) {
+        return fail(h, TnError(ST_HIP, e.what()));
+    }
+}
+
 tn_status tn_bp(tn_handle *h, const tn_peps *p, int max_sweeps, double tol, double *log_abs_Z, double *arg_Z,
                 int *sweeps, double *last_change, double *eps_mean, double *eps_loops, int eps_capacity,
                 int *n_loops, void *messages) {

@@ -118,10 +118,21 @@ hipError_t launch_cqr_pass(const CqrPass &p, hipStream_t s);
 // min(chi_min, rank).  Writes U[b](i, c) = u_c(i) and SV[b](c, l) = sigma_c
 // conj(v_c(l)) for c < k, zero for c >= k (element size esz, 8 or 16), and
 // kout[b] = k.  n <= SVD_NMAX; n > 64 needs svd_trunc_workspace_bytes.
+// chi_max > 0 caps k; disc (optional, [batch]) receives the discarded weight
+// sum_{j>=k} sigma_j^2 / sum_j sigma_j^2.
 constexpr int SVD_NMAX = 128;
 size_t svd_trunc_workspace_bytes(int n, int batch);
 hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, int chi_min, void *U, void *SV, int esz,
-                            int *kout, void *workspace, hipStream_t s);
+                            int *kout, void *workspace, hipStream_t s, int chi_max = 0, double *disc = nullptr);
+// From the SVD factors of Hermitian positive matrices M = U S V^H (the output
+// of launch_svd_trunc: U and SV = S V^H, complex128, batch x n x n, n <= 64):
+// Sq = U S^{1/2} V^H and Sp = U S^{-1/2} V^H over the kept values (zero rows of
+// SV are dropped), the square root and its pseudo-inverse.
+hipError_t launch_msg_roots(const double *U, const double *SV, int n, int batch, double *Sq, double *Sp,
+                            hipStream_t s);
+// U[:, c] *= sqrt(sigma_c), SV[c, :] /= sqrt(sigma_c) with sigma_c = |SV[c, :]|
+// (complex128, batch x n x n): the balanced factors U S^{1/2}, S^{1/2} V^H.
+hipError_t launch_split_sqrt(double *U, double *SV, int n, int batch, hipStream_t s);
 // x *= (re + i im) over n complex128 elements.
 hipError_t launch_scale(void *x, int64_t n, double re, double im, hipStream_t s);
 // out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element

@@ -48,6 +48,8 @@ struct SvdArgs {
     void *U; void *SV; int esz;
     int *kout;
     double2 *ws;
+    int chi_max;    // > 0: at most this many values kept
+    double *disc;   // optional [batch]: discarded weight sum_{j>=k} sigma_j^2 / sum_j sigma_j^2
 };
 
 __device__ inline void store(void *base, int esz, int64_t off, double2 v) {
@@ -181,9 +183,18 @@ __global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
                 }
                 const int lo = a.chi_min < rank ? a.chi_min : rank;
                 if (k < lo) k = lo;
+                if (a.chi_max > 0 && k > a.chi_max) k = a.chi_max;
             }
             kkeep = k;
             a.kout[b] = k;
+            if (a.disc) {
+                double total = 0, tail = 0;
+                for (int j = 0; j < n; ++j) {
+                    total += wsort[j];
+                    if (j >= k) tail += wsort[j];
+                }
+                a.disc[b] = total > 0.0 ? tail / total : 0.0;
+            }
         }
         __syncthreads();
         const int k = kkeep;
@@ -214,7 +225,7 @@ size_t svd_trunc_workspace_bytes(int n, int batch) {
 }
 
 hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, int chi_min, void *U, void *SV, int esz,
-                            int *kout, void *workspace, hipStream_t s) {
+                            int *kout, void *workspace, hipStream_t s, int chi_max, double *disc) {
     if (batch <= 0) return hipSuccess;
     if (n < 1 || n > SVD_NMAX || (esz != 8 && esz != 16)) return hipErrorInvalidValue;
     SvdArgs a;
@@ -222,6 +233,8 @@ hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, in
     a.n = n; a.batch = batch; a.cutoff = cutoff; a.chi_min = chi_min;
     a.U = U; a.SV = SV; a.esz = esz; a.kout = kout;
     a.ws = reinterpret_cast<double2 *>(workspace);
+    a.chi_max = chi_max;
+    a.disc = disc;
     const int grid = batch < SVD_GRID ? batch : SVD_GRID;
     if (n <= SVD_LDS_N) {
         static bool attr = false;

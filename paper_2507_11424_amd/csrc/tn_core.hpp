@@ -121,4 +121,20 @@ struct BpResult {
 };
 void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res);
 
+// Simple-update circuit simulation (FP64).  A gate acts on the qubits at
+// (r, c) and (r2, c2) = (r, c + 1) or (r + 1, c); the BP messages are refreshed
+// whenever `group` changes along the list.
+struct SuGate {
+    int group, r, c, r2, c2;
+};
+struct SuOpts {
+    int bp_max_sweeps = 1000;
+    double bp_tol = 1e-13;
+};
+// P's complex128 site tensors are replaced in place; gmat (host) holds the
+// 4 x 4 complex128 gate matrices, gstride = 16 complex numbers per gate or 0
+// (one matrix for every gate); eps_host [gates] receives the gate errors.
+void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, const double *gmat, int gstride,
+                   const SuOpts &o, double *eps_host);
+
 }  // namespace tnb
