@@ -6,6 +6,8 @@ Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
     python tests/golden/make_golden.py c3_norm       # ~10 min on 8 cores
     python tests/golden/make_golden.py c3_samples    # a few samples at chi_x = 8
     python tests/golden/make_golden.py c2_env        # 8x8 D=4 environments at chi = 32
+    python tests/golden/make_golden.py c2_env64      # the same at chi = 64 (~10 min)
+    python tests/golden/make_golden.py c2_samples64  # 3 samples of c2 at chi = chi_x = 64
     python tests/golden/make_golden.py c3_rows       # first 4 sampled rows at chi_x = 64 (~1 h)
     python tests/golden/make_golden.py c3_env        # c3 environments at chi = 64 (~40 min)
     python tests/golden/make_golden.py c3_bp         # c3 belief propagation and loop errors (~1 min)
@@ -64,9 +66,23 @@ def c2_env(chi=32):
                rho1=enc(e["rho1"]), rho1_shape=list(e["rho1"].shape),
                zz_h=[float(v) for v in e["zz_h"].reshape(-1)], zz_h_shape=list(e["zz_h"].shape),
                zz_v=[float(v) for v in e["zz_v"].reshape(-1)], zz_v_shape=list(e["zz_v"].shape),
-               oracle_seconds=time.time() - t0, command="python tests/golden/make_golden.py c2_env")
-    json.dump(out, open(os.path.join(HERE, "c2_env_chi32.json"), "w"))
+               oracle_seconds=time.time() - t0,
+               command="python tests/golden/make_golden.py " + ("c2_env" if chi == 32 else f"c2_env{chi}"))
+    json.dump(out, open(os.path.join(HERE, f"c2_env_chi{chi}.json"), "w"))
     print({k: v for k, v in out.items() if k in ("config", "chi", "oracle_seconds")})
+
+
+def c2_samples(n=3, chi=64):
+    """Samples of the 8x8 D=4 lattice at chi = chi_x = 64 on stored uniforms."""
+    lat, T, cfg = make_config("c2")
+    t0 = time.time()
+    u = sample_uniforms(53, n, lat.n_qubits)
+    bits, lq, lp = oracle.sample(T, lat.site_index, chi, chi, n, seed=0, first=0, uniforms=u)
+    out = dict(config="c2", chi=chi, chi_x=chi, sweeps=2, init_seed=0, uniforms_seed=53, n=n,
+               bits=bits.tolist(), log_q=lq.tolist(), log_p=lp.tolist(), oracle_seconds=time.time() - t0,
+               command="python tests/golden/make_golden.py c2_samples64")
+    json.dump(out, open(os.path.join(HERE, f"c2_samples_chi{chi}.json"), "w"))
+    print({k: v for k, v in out.items() if k != "bits"})
 
 
 def c3_rows(chi_x=64, rows_limit=4, indices=(0, 17)):
@@ -131,5 +147,5 @@ def c3_bp():
 
 
 if __name__ == "__main__":
-    {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env, "c3_rows": c3_rows,
-     "c3_env": c3_env, "c3_bp": c3_bp}[sys.argv[1]]()
+    {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env, "c2_env64": lambda: c2_env(64),
+     "c2_samples64": c2_samples, "c3_rows": c3_rows, "c3_env": c3_env, "c3_bp": c3_bp}[sys.argv[1]]()

@@ -86,19 +86,21 @@ def test_c3_samples_match_oracle(state, prec, tol):
     assert np.max(np.abs(lp.cpu().numpy() - np.array(SAMP["log_p"]))) < tol
 
 
-C2ENV = json.load(open(os.path.join(HERE, "golden", "c2_env_chi32.json")))
+C2ENV = {chi: json.load(open(os.path.join(HERE, "golden", f"c2_env_chi{chi}.json"))) for chi in (32, 64)}
 
 
-def _c2_ref():
-    rho = np.array([complex(a, b) for a, b in C2ENV["rho1"]]).reshape(C2ENV["rho1_shape"])
-    zzh = np.array(C2ENV["zz_h"]).reshape(C2ENV["zz_h_shape"])
-    zzv = np.array(C2ENV["zz_v"]).reshape(C2ENV["zz_v_shape"])
+def _c2_ref(chi):
+    g = C2ENV[chi]
+    rho = np.array([complex(a, b) for a, b in g["rho1"]]).reshape(g["rho1_shape"])
+    zzh = np.array(g["zz_h"]).reshape(g["zz_h_shape"])
+    zzv = np.array(g["zz_v"]).reshape(g["zz_v_shape"])
     return rho, zzh, zzv
 
 
+@pytest.mark.parametrize("chi", [32, 64])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_c2_environments_match_oracle(prec, tol):
-    """8x8 square lattice, D=4, chi=32: one-site density matrices and
+def test_c2_environments_match_oracle(prec, tol, chi):
+    """8x8 square lattice, D=4, chi = 32 and 64: one-site density matrices and
     nearest-neighbour <ZZ> (horizontal and vertical pairs) against the stored
     FP64 oracle values; FP32 runs on the complex64-rounded tensors (the oracle
     ran on complex128, so the tolerance covers that rounding too)."""
@@ -107,11 +109,11 @@ def test_c2_environments_match_oracle(prec, tol):
     h = tnb.Handle(0)
     try:
         P = tnb.Peps.from_numpy(lat, T, dtype="c128" if prec == "fp64" else "c64")
-        got = h.environments(P, tnb.make_opts(chi=C2ENV["chi"], sweeps=C2ENV["sweeps"],
-                                              init_seed=C2ENV["init_seed"], prec=prec), want_p2=False)
+        got = h.environments(P, tnb.make_opts(chi=C2ENV[chi]["chi"], sweeps=C2ENV[chi]["sweeps"],
+                                              init_seed=C2ENV[chi]["init_seed"], prec=prec), want_p2=False)
     finally:
         h.close()
-    rho, zzh, zzv = _c2_ref()
+    rho, zzh, zzv = _c2_ref(chi)
     e_rho = np.max(np.abs(got["rho1"].cpu().numpy() - rho))
     e_h = np.max(np.abs(got["zz_h"].cpu().numpy() - zzh))
     e_v = np.max(np.abs(got["zz_v"].cpu().numpy() - zzv))
@@ -134,7 +136,7 @@ def test_c2_sample_histograms_within_shot_noise():
         bits = bits.cpu().numpy()
     finally:
         h.close()
-    rho, _, _ = _c2_ref()
+    rho, _, _ = _c2_ref(32)
     tau = 0.5 * math.sqrt(1.0 / n) + math.sqrt(math.log(64 / 1e-3) / (2 * n))
     worst = 0.0
     for r in range(lat.rows):
@@ -170,3 +172,37 @@ def test_c4_full_lattice_small_bond():
     assert np.array_equal(bits.cpu().numpy(), rb)
     assert np.abs(lq.cpu().numpy() - rq).max() < 1e-9
     assert np.abs(lp.cpu().numpy() - rp).max() < 1e-9
+
+
+C2SAMP_FILE = os.path.join(HERE, "golden", "c2_samples_chi64.json")
+C2SAMP = json.load(open(C2SAMP_FILE)) if os.path.exists(C2SAMP_FILE) else None
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 8e-5), ("bf16x6", 8e-5)])
+def test_c2_samples_at_chi_64_match_oracle(prec, tol):
+    """8x8 square lattice, D=4, chi = chi_x = 64 (the configuration's second
+    bond), three samples on stored uniforms: identical bits, log q and log p
+    within tolerance (1e-5 sqrt(N) for the 64 summed conditionals in the
+    reduced-precision modes, which also run on complex64-rounded tensors while
+    the oracle ran on complex128)."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import sample_uniforms
+    if C2SAMP is None:
+        pytest.skip("tests/golden/c2_samples_chi64.json not written (make_golden.py c2_samples64)")
+    lat, T, cfg = make_config("c2")
+    h = tnb.Handle(0)
+    try:
+        P = tnb.Peps.from_numpy(lat, T, dtype="c128" if prec == "fp64" else "c64")
+        o = tnb.make_opts(chi=C2SAMP["chi"], chi_x=C2SAMP["chi_x"], sweeps=C2SAMP["sweeps"],
+                          init_seed=C2SAMP["init_seed"], prec=prec)
+        u = torch.from_numpy(sample_uniforms(C2SAMP["uniforms_seed"], C2SAMP["n"], lat.n_qubits))
+        bits, lq, lp = h.sample(P, o, C2SAMP["n"], uniforms=u)
+        bits, lq, lp = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy()
+    finally:
+        h.close()
+    print(f"{prec}: max |d log q| {np.abs(lq - np.array(C2SAMP['log_q'])).max():.2e}, "
+          f"max |d log p| {np.abs(lp - np.array(C2SAMP['log_p'])).max():.2e}")
+    assert np.array_equal(bits, np.array(C2SAMP["bits"], dtype=np.uint8))
+    assert np.abs(lq - np.array(C2SAMP["log_q"])).max() < tol
+    assert np.abs(lp - np.array(C2SAMP["log_p"])).max() < tol
