@@ -101,11 +101,13 @@ def send(T, M, r, c, leg) -> np.ndarray:
     return _pair(A, (leg,), msgs)
 
 
-def bp_messages(T, max_iter: int = 1000, tol: float = 1e-13):
+def bp_messages(T, max_iter: int = 1000, tol: float = 1e-13, init=None):
     """Parallel BP sweeps to convergence.  Returns (messages, sweeps, last
-    change); messages[(r, c, leg)] is the message into (r, c) through leg."""
+    change); messages[(r, c, leg)] is the message into (r, c) through leg.
+    init: messages to start from (those of a previous state on the same
+    lattice), else identity / sqrt(D) on every bond."""
     rows, cols = len(T), len(T[0])
-    M = initial_messages(T)
+    M = initial_messages(T) if init is None else {k: v.copy() for k, v in init.items()}
     delta = math.inf
     it = 0
     for it in range(1, max_iter + 1):

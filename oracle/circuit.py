@@ -35,7 +35,9 @@ Readings where the paper is silent:
 * eps is the discarded weight over all singular values, sum_{j >= k} s_j^2 /
   sum_j s_j^2 (the rank cut's part is below 1e-24);
 * gates in one group act on disjoint qubits and use the messages computed at
-  the start of the group, in the order of the gate list.
+  the start of the group, in the order of the gate list; each group's BP starts
+  from the converged messages of the group before (the first from identity /
+  sqrt(D)), run to the same tolerance.
 """
 from __future__ import annotations
 
@@ -125,7 +127,7 @@ def simple_update(T, gates, G, bp_sweeps: int = 1000, bp_tol: float = 1e-13):
     M = None
     for i, (grp, r, c, r2, c2) in enumerate(gates):
         if grp != cur:
-            M, _, _ = obp.bp_messages(T, max_iter=bp_sweeps, tol=bp_tol)
+            M, _, _ = obp.bp_messages(T, max_iter=bp_sweeps, tol=bp_tol, init=M)
             cur = grp
         eps.append(apply_gate(T, M, r, c, r2, c2, Gs[i] if Gs is not None else G))
     f = float(np.prod([1.0 - e for e in eps]))

@@ -197,7 +197,10 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
         E.unraw(dscal);
     };
     try {
-        TN_HIP(hipMemcpyAsync(msg.p, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, E.s));
+        if (o.init_messages)
+            TN_HIP(hipMemcpyAsync(msg.p, o.init_messages, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
+        else
+            TN_HIP(hipMemcpyAsync(msg.p, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, E.s));
         TN_HIP(hipMemcpyAsync(nbr, hn.data(), hn.size() * sizeof(int), hipMemcpyHostToDevice, E.s));
         E.sync();  // the host arrays above are released on return
         auto out_op = [&](int leg) {

@@ -7,7 +7,8 @@
 // gauge with the square roots of the incoming messages, apply, SVD, ungauge
 // with their inverses).
 //
-// FP64 throughout.  Per group: BP messages (bp_contract), then the square root
+// FP64 throughout.  Per group: BP messages (bp_contract, started from the
+// previous group's converged messages), then the square root
 // and its pseudo-inverse of every message from one batched SVD (a Hermitian
 // positive message has U = V; values at or below 1e-12 of the largest are
 // dropped, which makes the inverse a pseudo-inverse).  Per gate (site v, site w
@@ -157,6 +158,7 @@ void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, cons
                 bo.tol = o.bp_tol;
                 bo.loops = false;
                 bo.messages = msg.p;
+                bo.init_messages = first ? nullptr : msg.p;  // warm start from the previous group's messages
                 BpResult br;
                 bp_contract(E, P, bo, br);
                 TN_HIP(tnk::launch_svd_trunc(static_cast<const double *>(msg.p), Dm, N * 4, 0.0, 0, Um.p, SVm.p, 16,

@@ -113,6 +113,9 @@ struct BpOpts {
     double tol = 1e-13;
     bool loops = true;          // also the loop BP error of every primitive loop
     void *messages = nullptr;   // optional device copy of the final messages [N][4][Dm][Dm]
+    // optional device messages to start from (same layout, those of an earlier
+    // state of the same lattice); identity / sqrt(D) on every bond otherwise
+    const void *init_messages = nullptr;
 };
 struct BpResult {
     double log_abs = 0, arg = 0, delta = 0, eps_mean = 0;
