@@ -8,6 +8,7 @@ Calls only the FP64 oracle (``oracle/``) on the seeded inputs of
     python tests/golden/make_golden.py c2_env        # 8x8 D=4 environments at chi = 32
     python tests/golden/make_golden.py c2_env64      # the same at chi = 64 (~10 min)
     python tests/golden/make_golden.py c2_samples64  # 3 samples of c2 at chi = chi_x = 64
+    python tests/golden/make_golden.py c4_small      # c4's lattice at chi = 16: norm, 2 samples with the SVD cutoff
     python tests/golden/make_golden.py c3_rows       # first 4 sampled rows at chi_x = 64 (~1 h)
     python tests/golden/make_golden.py c3_env        # c3 environments at chi = 64 (~40 min)
     python tests/golden/make_golden.py c3_bp         # c3 belief propagation and loop errors (~1 min)
@@ -85,6 +86,29 @@ def c2_samples(n=3, chi=64):
     print({k: v for k, v in out.items() if k != "bits"})
 
 
+def c4_small(chi=16, chi_x=16, cutoff=1e-8, chi_x_min=4, n=2):
+    """The batching workload's lattice (105-qubit rotated square in a 15 x 15
+    grid with dummy sites, D = 8) at a reduced boundary bond: the norm and two
+    samples with the adaptive amplitude bond (SVD cutoff, clamped to
+    [chi_x_min, chi_x]) on stored uniforms, with the kept bond of every row."""
+    lat, T, cfg = make_config("c4")
+    t0 = time.time()
+    below, logs, info = ob.boundary_set(T, chi, 2, 0, 0)
+    z = ob.close_row(T[0], below[0])
+    t1 = time.time()
+    u = sample_uniforms(67, n, lat.n_qubits)
+    used = np.zeros((n, lat.rows), dtype=np.int64)
+    bits, lq, lp = oracle.sample(T, lat.site_index, chi, chi_x, n, seed=0, first=0, uniforms=u, below=below,
+                                 svd_cutoff=cutoff, chi_x_min=chi_x_min, chi_used=used)
+    out = dict(config="c4", chi=chi, chi_x=chi_x, svd_cutoff=cutoff, chi_x_min=chi_x_min, sweeps=2, init_seed=0,
+               log_abs_Z=sum(logs) + math.log(abs(z)), arg_Z=math.atan2(z.imag, z.real), uniforms_seed=67, n=n,
+               bits=bits.tolist(), log_q=lq.tolist(), log_p=lp.tolist(), chi_used=used.tolist(),
+               boundary_seconds=t1 - t0, sample_seconds=time.time() - t1,
+               command="python tests/golden/make_golden.py c4_small")
+    json.dump(out, open(os.path.join(HERE, f"c4_chi{chi}_cutoff.json"), "w"))
+    print({k: v for k, v in out.items() if k not in ("bits",)})
+
+
 def c3_rows(chi_x=64, rows_limit=4, indices=(0, 17)):
     """The first rows of samples at the benchmark's sampling bond chi_x = 64:
     rows 0-1 sample under an exact amplitude boundary (bond 1, then 8), the fit
@@ -148,4 +172,4 @@ def c3_bp():
 
 if __name__ == "__main__":
     {"c3_norm": c3_norm, "c3_samples": c3_samples, "c2_env": c2_env, "c2_env64": lambda: c2_env(64),
-     "c2_samples64": c2_samples, "c3_rows": c3_rows, "c3_env": c3_env, "c3_bp": c3_bp}[sys.argv[1]]()
+     "c2_samples64": c2_samples, "c4_small": c4_small, "c3_rows": c3_rows, "c3_env": c3_env, "c3_bp": c3_bp}[sys.argv[1]]()

@@ -206,3 +206,39 @@ def test_c2_samples_at_chi_64_match_oracle(prec, tol):
     assert np.array_equal(bits, np.array(C2SAMP["bits"], dtype=np.uint8))
     assert np.abs(lq - np.array(C2SAMP["log_q"])).max() < tol
     assert np.abs(lp - np.array(C2SAMP["log_p"])).max() < tol
+
+
+C4_FILE = os.path.join(HERE, "golden", "c4_chi16_cutoff.json")
+C4 = json.load(open(C4_FILE)) if os.path.exists(C4_FILE) else None
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("bf16x6", 1e-5 * 10.25)])
+def test_c4_lattice_reduced_bond_matches_oracle(prec, tol):
+    """The batching workload's lattice (105-qubit rotated square in its 15 x 15
+    embedding, D = 8, complex64 data) at boundary bond 16: log|Z|, and two
+    samples with the adaptive amplitude bond (SVD cutoff 1e-8, kept bonds in
+    [4, 16]) on stored uniforms: identical bits and kept bonds per row, log q
+    and log p within 1e-5 sqrt(105) in bf16x6."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import sample_uniforms
+    if C4 is None:
+        pytest.skip("tests/golden/c4_chi16_cutoff.json not written (make_golden.py c4_small)")
+    lat, T, cfg = make_config("c4")
+    h = tnb.Handle(0)
+    try:
+        P = tnb.Peps.from_numpy(lat, T, dtype="c128" if prec == "fp64" else "c64")
+        o = tnb.make_opts(chi=C4["chi"], chi_x=C4["chi_x"], sweeps=C4["sweeps"], init_seed=C4["init_seed"],
+                          prec=prec, svd_cutoff=C4["svd_cutoff"], chi_x_min=C4["chi_x_min"])
+        lz, _ = h.boundary_contract(P, o)
+        u = torch.from_numpy(sample_uniforms(C4["uniforms_seed"], C4["n"], lat.n_qubits))
+        bits, lq, lp, cu = h.sample(P, o, C4["n"], uniforms=u, want_chi=True)
+        bits, lq, lp, cu = bits.cpu().numpy(), lq.cpu().numpy(), lp.cpu().numpy(), cu.cpu().numpy()
+    finally:
+        h.close()
+    print(f"{prec}: log|Z| {lz!r} vs {C4['log_abs_Z']!r}; max |d log q| {np.abs(lq - np.array(C4['log_q'])).max():.2e}")
+    assert abs(lz - C4["log_abs_Z"]) < (1e-10 if prec == "fp64" else 1e-5)
+    assert np.array_equal(bits, np.array(C4["bits"], dtype=np.uint8))
+    assert np.array_equal(cu, np.array(C4["chi_used"], dtype=np.int32))
+    assert np.abs(lq - np.array(C4["log_q"])).max() < tol
+    assert np.abs(lp - np.array(C4["log_p"])).max() < tol
