@@ -4,8 +4,10 @@
 // loopBPerror; Appendix, "Applying Gates to a Tensor Network State" -- the
 // message update and its normalisation -- and "Computing the BP Error").
 //
-// Every site tensor is embedded in a uniform layout A[z][s][u][l][d][r] with
-// all bond legs padded (with zeros) to the largest bond Dm; messages are
+// Every site tensor other than a dummy (a scalar without bonds, which only
+// contributes Z_v = 1 and e0 e0^T messages) is embedded in a uniform layout
+// A[z][s][u][l][d][r] with all bond legs padded (with zeros) to the largest
+// bond Dm; messages are
 // msg[z][leg][k][k'] (into site z through leg, ket index k, bra index k'),
 // e0 e0^T on legs without a bond, so padded entries never contribute.  A
 // parallel sweep computes, for each of the four legs, the message every site
@@ -150,44 +152,56 @@ std::vector<std::vector<LoopSite>> faces(const PepsDev &P) {
 }  // namespace
 
 void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
-    const int rows = P.rows, cols = P.cols, N = rows * cols;
+    const int rows = P.rows, cols = P.cols, NG = rows * cols;
     int Dm = 1;
     for (const Ten &t : P.site)
         for (int k = 1; k <= 4; ++k) Dm = std::max(Dm, t.d[k]);
     const int n2 = Dm * Dm;
-    // uniform padded tensors
+    // the sites that take part: every grid position except dummies (a scalar
+    // tensor with no bond: its messages are e0 e0^T and its Z_v is 1)
+    std::vector<int> act, aidx((size_t)NG, -1);
+    for (int z = 0; z < NG; ++z)
+        if (P.site[(size_t)z].numel() > 1) {
+            aidx[(size_t)z] = (int)act.size();
+            act.push_back(z);
+        }
+    const int N = (int)act.size();
+    if (N == 0) throw TnError(ST_INVALID, "belief propagation: the state has no site with a bond or a qubit");
+    // uniform padded tensors of the active sites
     Ten A = E.make({N, 2, Dm, Dm, Dm, Dm});
     TN_HIP(tnk::launch_fill(A.p, A.esz, A.numel(), 0.0, 0.0, E.s));
     const size_t per = (size_t)2 * Dm * Dm * Dm * Dm;
-    for (int z = 0; z < N; ++z) {
-        const Ten &t = P.site[z];
+    for (int i = 0; i < N; ++i) {
+        const Ten &t = P.site[(size_t)act[i]];
         TN_HIP(tnk::launch_bp_embed(t.p, t.d[0], t.d[1], t.d[2], t.d[3], t.d[4],
-                                    static_cast<char *>(A.p) + z * per * 16, Dm, E.s));
+                                    static_cast<char *>(A.p) + i * per * 16, Dm, E.s));
     }
     // neighbour table and initial messages: identity / sqrt(D) on bonds, e0 e0^T elsewhere
     std::vector<int> hn((size_t)N * NLEG, -1);
     std::vector<double> hm((size_t)N * NLEG * n2 * 2, 0.0);
-    for (int r = 0; r < rows; ++r)
-        for (int c = 0; c < cols; ++c) {
-            const int z = r * cols + c;
-            for (int leg = 0; leg < NLEG; ++leg) {
-                const int D = P.at(r, c).d[leg + 1];
-                const int r2 = r + DR[leg], c2 = c + DC[leg];
-                const bool bond = D > 1 && r2 >= 0 && r2 < rows && c2 >= 0 && c2 < cols;
-                double *m = hm.data() + ((size_t)z * NLEG + leg) * n2 * 2;
-                if (bond) {
-                    hn[(size_t)z * NLEG + leg] = r2 * cols + c2;
-                    for (int i = 0; i < D; ++i) m[(i * Dm + i) * 2] = 1.0 / std::sqrt((double)D);
-                } else {
-                    m[0] = 1.0;
-                }
+    for (int i = 0; i < N; ++i) {
+        const int r = act[i] / cols, c = act[i] % cols;
+        for (int leg = 0; leg < NLEG; ++leg) {
+            const int D = P.at(r, c).d[leg + 1];
+            const int r2 = r + DR[leg], c2 = c + DC[leg];
+            const bool bond = D > 1 && r2 >= 0 && r2 < rows && c2 >= 0 && c2 < cols;
+            double *m = hm.data() + ((size_t)i * NLEG + leg) * n2 * 2;
+            if (bond) {
+                const int j = aidx[(size_t)r2 * cols + c2];
+                if (j < 0) throw TnError(ST_SHAPE, "belief propagation: a bond leads to a dummy site");
+                hn[(size_t)i * NLEG + leg] = j;
+                for (int k = 0; k < D; ++k) m[(k * Dm + k) * 2] = 1.0 / std::sqrt((double)D);
+            } else {
+                m[0] = 1.0;
             }
         }
+    }
     Ten msg = E.make({N, NLEG, Dm, Dm});
     int *nbr = static_cast<int *>(E.raw(hn.size() * sizeof(int)));
     Ten out = E.make({NLEG, N, Dm, Dm});
     double *dmax = static_cast<double *>(E.raw((size_t)N * NLEG * 8));
     double *dscal = static_cast<double *>(E.raw(64));
+    const size_t site_msgs = (size_t)NLEG * n2 * 16;  // bytes of one site's four messages
     auto cleanup = [&]() {
         E.drop(A);
         E.drop(msg);
@@ -197,10 +211,14 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
         E.unraw(dscal);
     };
     try {
-        if (o.init_messages)
-            TN_HIP(hipMemcpyAsync(msg.p, o.init_messages, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
-        else
+        if (o.init_messages) {  // grid layout [NG][4][Dm][Dm]: the active sites' blocks
+            for (int i = 0; i < N; ++i)
+                TN_HIP(hipMemcpyAsync(static_cast<char *>(msg.p) + (size_t)i * site_msgs,
+                                      static_cast<const char *>(o.init_messages) + (size_t)act[i] * site_msgs,
+                                      site_msgs, hipMemcpyDeviceToDevice, E.s));
+        } else {
             TN_HIP(hipMemcpyAsync(msg.p, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, E.s));
+        }
         TN_HIP(hipMemcpyAsync(nbr, hn.data(), hn.size() * sizeof(int), hipMemcpyHostToDevice, E.s));
         E.sync();  // the host arrays above are released on return
         auto out_op = [&](int leg) {
@@ -240,7 +258,17 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
         E.unraw(ze);
         res.log_abs = h2[0];
         res.arg = h2[1];
-        if (o.messages) TN_HIP(hipMemcpyAsync(o.messages, msg.p, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
+        if (o.messages) {
+            // grid layout [NG][4][Dm][Dm]: dummies hold e0 e0^T on every leg
+            std::vector<double> dm((size_t)NG * NLEG * n2 * 2, 0.0);
+            for (size_t q = 0; q < (size_t)NG * NLEG; ++q) dm[q * n2 * 2] = 1.0;
+            TN_HIP(hipMemcpyAsync(o.messages, dm.data(), dm.size() * 8, hipMemcpyHostToDevice, E.s));
+            for (int i = 0; i < N; ++i)
+                TN_HIP(hipMemcpyAsync(static_cast<char *>(o.messages) + (size_t)act[i] * site_msgs,
+                                      static_cast<const char *>(msg.p) + (size_t)i * site_msgs, site_msgs,
+                                      hipMemcpyDeviceToDevice, E.s));
+            E.sync();  // dm is released on return
+        }
         // loop BP error
         res.eps.clear();
         res.eps_mean = 0.0;
@@ -289,7 +317,7 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
                         for (int k = 0; k < L; ++k) {
                             const LoopSite &s = loops[g.second[i]][k];
                             const int a = std::min(s.lin, s.lout), b = std::max(s.lin, s.lout);
-                            hoff[(size_t)i * L + k] = (int64_t)pid[a][b] * pstride + (int64_t)s.z * n2 * n2;
+                            hoff[(size_t)i * L + k] = (int64_t)pid[a][b] * pstride + (int64_t)aidx[(size_t)s.z] * n2 * n2;
                             htr[(size_t)i * L + k] = s.lin == a ? 0 : 1;  // walk enters through the larger leg
                         }
                     int64_t *doff = static_cast<int64_t *>(E.raw(hoff.size() * 8));
