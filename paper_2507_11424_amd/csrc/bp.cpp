@@ -4,10 +4,11 @@
 // loopBPerror; Appendix, "Applying Gates to a Tensor Network State" -- the
 // message update and its normalisation -- and "Computing the BP Error").
 //
-// Every site tensor other than a dummy (a scalar without bonds, which only
-// contributes Z_v = 1 and e0 e0^T messages) is embedded in a uniform layout
-// A[z][s][u][l][d][r] with all bond legs padded (with zeros) to the largest
-// bond Dm; messages are
+// Every site other than a dummy (a scalar without bonds, which only
+// contributes Z_v = 1 and e0 e0^T messages) takes part; the sites are grouped
+// by shape and each group's contractions run on its own dimensions (a site
+// with three bonds costs D^4, not Dm^5, per message).  Messages are stored
+// padded to the largest bond Dm:
 // msg[z][leg][k][k'] (into site z through leg, ket index k, bra index k'),
 // e0 e0^T on legs without a bond, so padded entries never contribute.  A
 // parallel sweep computes, for each of the four legs, the message every site
@@ -34,21 +35,43 @@ const char KET[NLEG] = {'a', 'b', 'c', 'd'};
 const char BRA[NLEG] = {'e', 'f', 'g', 'h'};
 const int DR[NLEG] = {-1, 0, 1, 0}, DC[NLEG] = {0, -1, 0, 1};
 
-// View of the incoming messages of one leg: [z][k][k'] inside msg[z][leg][k][k'].
-Op msg_op(const Ten &msg, int leg, int N, int Dm) {
+// The sites of one shape: their tensors stored unpadded, [count][p][u][l][d][r],
+// occupying active indices start .. start + count - 1.
+struct SiteClass {
+    int start = 0, count = 0;
+    int dims[5] = {1, 1, 1, 1, 1};
+    Ten A;
+};
+
+// View of one class's incoming messages of one leg: the D x D blocks of
+// msg[z][leg][k][k'] for z in the class.
+Op msg_op(const Ten &msg, const SiteClass &c, int leg, int Dm) {
     Op o;
-    o.p = static_cast<const char *>(msg.p) + (size_t)leg * Dm * Dm * msg.esz;
+    o.p = static_cast<const char *>(msg.p) + ((size_t)c.start * NLEG + leg) * Dm * Dm * msg.esz;
     o.esz = msg.esz;
     o.idx = std::string("z") + KET[leg] + BRA[leg];
-    o.dims = {N, Dm, Dm};
+    o.dims = {c.count, c.dims[leg + 1], c.dims[leg + 1]};
     o.str = {(int64_t)NLEG * Dm * Dm, Dm, 1};
     return o;
 }
 
-// The pair (A, conj A) of every site with the incoming messages on all legs not
-// in `keep` contracted; result [z] + (ket, bra) letters of the kept legs in
-// order, written to `out` (dense, dims {N, Dm, Dm, ...}).
-void pair_closed(Engine &E, const Ten &A, const Ten &msg, const std::vector<int> &keep, const Op &out, int N,
+Op class_op(const SiteClass &c, const std::string &idx, bool conj) {
+    Op o;
+    o.p = c.A.p;
+    o.esz = c.A.esz;
+    o.idx = idx;
+    o.dims = {c.count, c.dims[0], c.dims[1], c.dims[2], c.dims[3], c.dims[4]};
+    o.str.assign(6, 1);
+    for (int i = 4; i >= 0; --i) o.str[(size_t)i] = o.str[(size_t)i + 1] * o.dims[(size_t)i + 1];
+    o.conj = conj;
+    return o;
+}
+
+// The pair (A, conj A) of every site of the class with the incoming messages
+// on all legs not in `keep` contracted; result [z] + (ket, bra) letters of the
+// kept legs in order, written through `out` (the caller's view of the class's
+// blocks; every dimension is the site's own, nothing is padded).
+void pair_closed(Engine &E, const SiteClass &c, const Ten &msg, const std::vector<int> &keep, const Op &out,
                  int Dm) {
     std::string cur = "zsabcd";
     Ten t;  // current intermediate (empty: A itself)
@@ -58,13 +81,13 @@ void pair_closed(Engine &E, const Ten &A, const Ten &msg, const std::vector<int>
         for (char ch : cur)
             if (ch != KET[leg]) nxt += ch;
         nxt += BRA[leg];
-        Ten r = E.contract_new(t.p ? op(t, cur) : op(A, cur), msg_op(msg, leg, N, Dm), nxt);
+        Ten r = E.contract_new(t.p ? op(t, cur) : class_op(c, cur, false), msg_op(msg, c, leg, Dm), nxt);
         if (t.p) E.drop(t);
         t = r;
         cur = nxt;
     }
     // close with conj(A) over s and the bra legs of the contracted legs
-    E.contract(op(t, cur), op(A, "zsefgh", true), out);
+    E.contract(op(t, cur), class_op(c, "zsefgh", true), out);
     E.drop(t);
 }
 
@@ -158,23 +181,37 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
         for (int k = 1; k <= 4; ++k) Dm = std::max(Dm, t.d[k]);
     const int n2 = Dm * Dm;
     // the sites that take part: every grid position except dummies (a scalar
-    // tensor with no bond: its messages are e0 e0^T and its Z_v is 1)
+    // tensor with no bond: its messages are e0 e0^T and its Z_v is 1), grouped
+    // by shape so that each group's contractions run on its own dimensions
+    std::map<std::vector<int>, std::vector<int>> shapes;
+    for (int z = 0; z < NG; ++z) {
+        const Ten &t = P.site[(size_t)z];
+        if (t.numel() > 1) shapes[t.d].push_back(z);
+    }
     std::vector<int> act, aidx((size_t)NG, -1);
-    for (int z = 0; z < NG; ++z)
-        if (P.site[(size_t)z].numel() > 1) {
+    std::vector<SiteClass> cls;
+    for (auto &kv : shapes) {
+        SiteClass c;
+        c.start = (int)act.size();
+        c.count = (int)kv.second.size();
+        for (int i = 0; i < 5; ++i) c.dims[i] = kv.first[(size_t)i];
+        for (int z : kv.second) {
             aidx[(size_t)z] = (int)act.size();
             act.push_back(z);
         }
+        cls.push_back(c);
+    }
     const int N = (int)act.size();
     if (N == 0) throw TnError(ST_INVALID, "belief propagation: the state has no site with a bond or a qubit");
-    // uniform padded tensors of the active sites
-    Ten A = E.make({N, 2, Dm, Dm, Dm, Dm});
-    TN_HIP(tnk::launch_fill(A.p, A.esz, A.numel(), 0.0, 0.0, E.s));
-    const size_t per = (size_t)2 * Dm * Dm * Dm * Dm;
-    for (int i = 0; i < N; ++i) {
-        const Ten &t = P.site[(size_t)act[i]];
-        TN_HIP(tnk::launch_bp_embed(t.p, t.d[0], t.d[1], t.d[2], t.d[3], t.d[4],
-                                    static_cast<char *>(A.p) + i * per * 16, Dm, E.s));
+    for (auto &c : cls) {
+        c.A = E.make({c.count, c.dims[0], c.dims[1], c.dims[2], c.dims[3], c.dims[4]});
+        const size_t bytes = (size_t)c.dims[0] * c.dims[1] * c.dims[2] * c.dims[3] * c.dims[4] * 16;
+        for (int i = 0; i < c.count; ++i) {
+            const Ten &t = P.site[(size_t)act[(size_t)c.start + i]];
+            if (t.esz != 16) throw TnError(ST_INVALID, "belief propagation runs on complex128 site tensors");
+            TN_HIP(hipMemcpyAsync(static_cast<char *>(c.A.p) + (size_t)i * bytes, t.p, bytes,
+                                  hipMemcpyDeviceToDevice, E.s));
+        }
     }
     // neighbour table and initial messages: identity / sqrt(D) on bonds, e0 e0^T elsewhere
     std::vector<int> hn((size_t)N * NLEG, -1);
@@ -203,7 +240,8 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
     double *dscal = static_cast<double *>(E.raw(64));
     const size_t site_msgs = (size_t)NLEG * n2 * 16;  // bytes of one site's four messages
     auto cleanup = [&]() {
-        E.drop(A);
+        for (auto &c : cls)
+            if (c.A.p) E.drop(c.A);
         E.drop(msg);
         E.drop(out);
         E.unraw(nbr);
@@ -220,20 +258,23 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
             TN_HIP(hipMemcpyAsync(msg.p, hm.data(), hm.size() * 8, hipMemcpyHostToDevice, E.s));
         }
         TN_HIP(hipMemcpyAsync(nbr, hn.data(), hn.size() * sizeof(int), hipMemcpyHostToDevice, E.s));
+        // the sweeps write each site's own D x D block of its outgoing messages
+        TN_HIP(tnk::launch_fill(out.p, out.esz, out.numel(), 0.0, 0.0, E.s));
         E.sync();  // the host arrays above are released on return
-        auto out_op = [&](int leg) {
+        auto out_op = [&](int leg, const SiteClass &c) {
             Op q;
-            q.p = static_cast<char *>(out.p) + (size_t)leg * N * n2 * out.esz;
+            q.p = static_cast<char *>(out.p) + ((size_t)leg * N + c.start) * n2 * out.esz;
             q.esz = out.esz;
             q.idx = std::string("z") + KET[leg] + BRA[leg];
-            q.dims = {N, Dm, Dm};
+            q.dims = {c.count, c.dims[leg + 1], c.dims[leg + 1]};
             q.str = {(int64_t)n2, Dm, 1};
             return q;
         };
         double delta = INFINITY;
         int sweep = 0;
         while (sweep < o.max_sweeps) {
-            for (int leg = 0; leg < NLEG; ++leg) pair_closed(E, A, msg, {leg}, out_op(leg), N, Dm);
+            for (int leg = 0; leg < NLEG; ++leg)
+                for (const auto &c : cls) pair_closed(E, c, msg, {leg}, out_op(leg, c), Dm);
             TN_HIP(tnk::launch_bp_update(out.p, msg.p, nbr, N, Dm, dmax, dscal, E.s));
             ++sweep;
             if (sweep % 4 == 0 || sweep == o.max_sweeps) {
@@ -246,7 +287,7 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
         res.sweeps = sweep;
         res.delta = delta;
         // Z_BP from the final messages
-        pair_closed(E, A, msg, {3}, out_op(3), N, Dm);
+        for (const auto &c : cls) pair_closed(E, c, msg, {3}, out_op(3, c), Dm);
         double *zv = static_cast<double *>(E.raw((size_t)N * 16));
         double *ze = static_cast<double *>(E.raw((size_t)N * 32));
         TN_HIP(tnk::launch_bp_free_energy(static_cast<char *>(out.p) + (size_t)3 * N * n2 * 16, msg.p, nbr, N, Dm,
@@ -293,17 +334,19 @@ void bp_contract(Engine &E, const PepsDev &P, const BpOpts &o, BpResult &res) {
                         }
                     }
                 Ten pt = E.make({(int)pairs.size(), N, Dm, Dm, Dm, Dm});
+                TN_HIP(tnk::launch_fill(pt.p, pt.esz, pt.numel(), 0.0, 0.0, E.s));
                 const size_t pstride = (size_t)N * n2 * n2;
-                for (size_t k = 0; k < pairs.size(); ++k) {
-                    Op q;
-                    q.p = static_cast<char *>(pt.p) + k * pstride * 16;
-                    q.esz = 16;
-                    q.idx = std::string("z") + KET[pairs[k].first] + BRA[pairs[k].first] + KET[pairs[k].second] +
-                            BRA[pairs[k].second];
-                    q.dims = {N, Dm, Dm, Dm, Dm};
-                    q.str = {(int64_t)n2 * n2, (int64_t)Dm * n2, n2, Dm, 1};
-                    pair_closed(E, A, msg, {pairs[k].first, pairs[k].second}, q, N, Dm);
-                }
+                for (size_t k = 0; k < pairs.size(); ++k)
+                    for (const auto &c : cls) {
+                        const int a = pairs[k].first, b = pairs[k].second;
+                        Op q;
+                        q.p = static_cast<char *>(pt.p) + (k * pstride + (size_t)c.start * n2 * n2) * 16;
+                        q.esz = 16;
+                        q.idx = std::string("z") + KET[a] + BRA[a] + KET[b] + BRA[b];
+                        q.dims = {c.count, c.dims[a + 1], c.dims[a + 1], c.dims[b + 1], c.dims[b + 1]};
+                        q.str = {(int64_t)n2 * n2, (int64_t)Dm * n2, n2, Dm, 1};
+                        pair_closed(E, c, msg, {a, b}, q, Dm);
+                    }
                 // loops grouped by length: gather [loop][k] matrices, multiply along the walk
                 std::map<int, std::vector<int>> bylen;
                 for (int i = 0; i < (int)loops.size(); ++i) bylen[(int)loops[i].size()].push_back(i);

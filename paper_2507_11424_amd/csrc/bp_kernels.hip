@@ -59,21 +59,6 @@ __device__ double block_max(double v, double *red) {
     return r;
 }
 
-// dst[s][u][l][d][r] (dims 2 x Dm^4, cleared by the caller) <- src[p][u][l][d][r].
-__global__ void __launch_bounds__(NT) k_embed5(const double2 *src, int p, int u, int l, int d, int r, double2 *dst,
-                                              int Dm) {
-    const int64_t n = (int64_t)p * u * l * d * r;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) {
-        int64_t t = e;
-        const int ir = (int)(t % r); t /= r;
-        const int id = (int)(t % d); t /= d;
-        const int il = (int)(t % l); t /= l;
-        const int iu = (int)(t % u); t /= u;
-        const int is = (int)t;
-        dst[((((int64_t)is * Dm + iu) * Dm + il) * Dm + id) * Dm + ir] = src[e];
-    }
-}
-
 // One message per block b = z * 4 + leg (legs 0..3 = up, left, down, right):
 // the message site z sends through `leg`, out[leg][z] (Dm x Dm), becomes its
 // Hermitian part divided by its Frobenius norm and is stored as the message
@@ -324,16 +309,6 @@ __global__ void k_eig(double2 *mats, int n, int batch, double2 *lam, double *eps
 }
 
 }  // namespace
-
-hipError_t launch_bp_embed(const void *src, int p, int u, int l, int d, int r, void *dst, int Dm, hipStream_t s) {
-    const int64_t n = (int64_t)p * u * l * d * r;
-    if (n <= 0) return hipSuccess;
-    int g = (int)((n + NT - 1) / NT);
-    if (g > 1024) g = 1024;
-    hipLaunchKernelGGL(k_embed5, dim3(g), dim3(NT), 0, s, static_cast<const double2 *>(src), p, u, l, d, r,
-                       static_cast<double2 *>(dst), Dm);
-    return hipGetLastError();
-}
 
 hipError_t launch_bp_update(const void *out, void *msg, const int *nbr, int N, int Dm, double *dmax, double *delta,
                             hipStream_t s) {

@@ -250,8 +250,6 @@ hipError_t launch_logp(const double *amp, const double *mlog, int batch, double 
                        hipStream_t s);
 
 // ---------------------------------------------------------------- belief propagation
-// Embeds a site tensor src[p][u][l][d][r] (complex128) into dst[2][Dm]^4 (cleared).
-hipError_t launch_bp_embed(const void *src, int p, int u, int l, int d, int r, void *dst, int Dm, hipStream_t s);
 // out [4][N][Dm][Dm]: the message each site sends through each leg (0 up,
 // 1 left, 2 down, 3 right); msg [N][4][Dm][Dm]: incoming messages; nbr [N][4]:
 // the neighbour receiving through each leg, -1 without a bond.  Stores the
