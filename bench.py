@@ -451,9 +451,11 @@ def simple_update_bench(a):
            "eps_max": max(eps_all), "eps_mean": float(np.mean(eps_all)),
            "fidelity_estimate_timed_layers": float(np.prod([1 - e for e in eps_all])),
            "last_layer_launches": {"contraction": c["gemm_launches"], "orthonormalisation": c["qr_launches"]},
-           "roofline": {"bound": "latency", "note": "per gate tens of launches on D-sized tensors (gauge, QR, "
-                                                    "SVD of at most 4D x 4D, ungauge) plus a BP solve per colour "
-                                                    "group; no kernel here is near an MFMA or HBM bound"}}
+           "roofline": {"bound": "latency", "note": "per colour group a BP solve, then per class of gates "
+                                                    "(same orientation and site shapes) a few tens of batched "
+                                                    "launches on D-sized tensors (gauge, QR, Jacobi SVD of at most "
+                                                    "4D x 4D per gate, ungauge); no kernel here is near an MFMA "
+                                                    "or HBM bound"}}
     if not a.no_cpu_baseline and (D <= 16 or a.cpu_full):
         from oracle.circuit import simple_update as o_su
         n = 4

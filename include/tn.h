@@ -110,7 +110,7 @@ typedef struct {
                              <= svd_cutoff (the error measure of Eq. error_per_gate);
                              0 = fixed bond chi_x (the paper's sampler)                 */
     int32_t chi_x_min;    /* lower clamp of that truncation (never above the numerical
-                             rank, s_j > 1e-12 s_0); the upper clamp is chi_x <= 128    */
+                             rank, s_j > 1e-12 s_0); the upper clamp is chi_x <= 256    */
 } tn_opts;
 
 /* Fills opts with defaults: chi = chi_x = 16, sweeps = 2, direction 0, init 0,
@@ -234,7 +234,10 @@ tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, d
  *   gate_sites  host [n_gates][5] int32: group, r, c, r2, c2 with (r2, c2) =
  *               (r, c+1) or (r+1, c), both sites qubits.  The BP messages of
  *               the norm network are recomputed whenever `group` differs from
- *               the previous gate's (gates of one group must share no qubit).
+ *               the previous gate's.  Gates of one group must share no qubit
+ *               (TN_ERR_INVALID otherwise): they see the same messages
+ *               and are applied together, batched by orientation and
+ *               site shapes.
  *   gates       host complex128 4 x 4 row-major unitaries in the basis 2a + b,
  *               a the qubit at (r, c): gate_stride 16 = one matrix per gate,
  *               0 = one matrix for all.
@@ -247,7 +250,8 @@ tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, d
  * the largest taken as 0), reduced by QR, the gate applied, an SVD kept to
  * min(D, rank) values (rank: above 1e-12 of the largest) split as U S^1/2 and
  * S^1/2 V^H.  FP64 arithmetic whatever the input type (complex64 results are
- * rounded once on output).  Bonds up to 32.  Synchronises the stream.
+ * rounded once on output).  Bonds up to 64 (pair matrices up to 256 wide).
+ * Synchronises the stream.
  * TN_ERR_INVALID for a malformed gate list, TN_ERR_UNSUPPORTED above the bond
  * limit. */
 tn_status tn_simple_update(tn_handle *h, const tn_peps *peps, void *const *site_out, int n_gates,
@@ -352,7 +356,7 @@ tn_status tn_plan_report(const tn_handle *h, int top, char *buf, size_t len);
  *   (n x m, row-major), so the rows of Q are an orthonormal basis of the rows
  *   of A.  Enqueued on the handle's stream.
  * tn_test_svd: the sampler's SVD truncation step on `batch` row-major n x n
- *   complex128 DEVICE matrices R (n <= 128): U (n x n) and SV (n x n), element
+ *   complex128 DEVICE matrices R (n <= 256): U (n x n) and SV (n x n), element
  *   size esz (16 or 8), with R ~ U SV; columns of U and rows of SV past the
  *   kept count are zero; k (device int32 [batch]) receives the kept counts
  *   (rule as for tn_opts.svd_cutoff with the lower clamp chi_min).  Enqueued

@@ -671,12 +671,12 @@ void Engine::tune(Plan *P, tnk::GettArgs g) {
         P->base = saved;
         P->pack = saved_pack;
         P->fp32 = saved_fp32;
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         throw;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     P->base = saved;
     P->pack = win.pack;
     P->fp32 = win.fp32;

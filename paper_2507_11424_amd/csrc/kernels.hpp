@@ -120,7 +120,7 @@ hipError_t launch_cqr_pass(const CqrPass &p, hipStream_t s);
 // kout[b] = k.  n <= SVD_NMAX; n > 64 needs svd_trunc_workspace_bytes.
 // chi_max > 0 caps k; disc (optional, [batch]) receives the discarded weight
 // sum_{j>=k} sigma_j^2 / sum_j sigma_j^2.
-constexpr int SVD_NMAX = 128;
+constexpr int SVD_NMAX = 256;
 size_t svd_trunc_workspace_bytes(int n, int batch);
 hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, int chi_min, void *U, void *SV, int esz,
                             int *kout, void *workspace, hipStream_t s, int chi_max = 0, double *disc = nullptr);
@@ -131,8 +131,18 @@ hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, in
 hipError_t launch_msg_roots(const double *U, const double *SV, int n, int batch, double *Sq, double *Sp,
                             hipStream_t s);
 // U[:, c] *= sqrt(sigma_c), SV[c, :] /= sqrt(sigma_c) with sigma_c = |SV[c, :]|
-// (complex128, batch x n x n): the balanced factors U S^{1/2}, S^{1/2} V^H.
+// (complex128, batch x n x n, n <= 256): the balanced factors U S^{1/2}, S^{1/2} V^H.
 hipError_t launch_split_sqrt(double *U, double *SV, int n, int batch, hipStream_t s);
+// One entry of a block-copy table: a rows x cols block of complex128 elements
+// read with row stride src_ld, written contiguously (row-major) at dst.
+struct CopyBlock {
+    const void *src;
+    void *dst;
+    int64_t rows, cols, src_ld;
+};
+// Runs the n entries of the DEVICE table tab (max_elems = the largest
+// rows * cols, which sizes the grid).
+hipError_t launch_copy_blocks(const CopyBlock *tab, int n, int64_t max_elems, hipStream_t s);
 // x *= (re + i im) over n complex128 elements.
 hipError_t launch_scale(void *x, int64_t n, double re, double im, hipStream_t s);
 // out[b](i, j) = opA(in[b](i, j)) for an m x n matrix per batch item with element

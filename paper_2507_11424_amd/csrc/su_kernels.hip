@@ -1,7 +1,10 @@
 // Small kernels of the simple-update gate step (Appendix, "Applying Gates to a
-// Tensor Network State"): square roots of the BP messages and the balanced
-// split of the truncated SVD between the two sites.
+// Tensor Network State"): square roots of the BP messages, the balanced split
+// of the truncated SVD between the two sites, and the table-driven block copies
+// that gather the tensors of a batch of gates and scatter the results.
 #include "kernels.hpp"
+
+#include <algorithm>
 
 namespace tnk {
 namespace {
@@ -40,7 +43,7 @@ __global__ void __launch_bounds__(256) k_msg_roots(const double2 *U, const doubl
 }
 
 __global__ void __launch_bounds__(256) k_split_sqrt(double2 *U, double2 *SV, int n) {
-    __shared__ double rs[128];
+    __shared__ double rs[256];
     const int b = blockIdx.x, t = threadIdx.x;
     const int64_t off = (int64_t)b * n * n;
     if (t < n) {
@@ -63,7 +66,28 @@ __global__ void __launch_bounds__(256) k_split_sqrt(double2 *U, double2 *SV, int
     }
 }
 
+// Workgroup (x, y) copies the elements y, y + Y, ... (in units of 256) of
+// table entry x: dst[e] = src[(e / cols) * src_ld + e % cols].
+__global__ void __launch_bounds__(256) k_copy_blocks(const CopyBlock *tab) {
+    const CopyBlock b = tab[blockIdx.x];
+    const double2 *src = static_cast<const double2 *>(b.src);
+    double2 *dst = static_cast<double2 *>(b.dst);
+    const int64_t total = b.rows * b.cols;
+    for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.y * 256) {
+        const int64_t r = e / b.cols, c = e - r * b.cols;
+        dst[e] = src[r * b.src_ld + c];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_copy_blocks(const CopyBlock *tab, int n, int64_t max_elems, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (!tab || max_elems < 0) return hipErrorInvalidValue;
+    const int64_t y = std::min<int64_t>(std::max<int64_t>((max_elems + 4095) / 4096, 1), 256);
+    hipLaunchKernelGGL(k_copy_blocks, dim3(n, (unsigned)y), dim3(256), 0, s, tab);
+    return hipGetLastError();
+}
 
 hipError_t launch_msg_roots(const double *U, const double *SV, int n, int batch, double *Sq, double *Sp,
                             hipStream_t s) {
@@ -77,7 +101,7 @@ hipError_t launch_msg_roots(const double *U, const double *SV, int n, int batch,
 
 hipError_t launch_split_sqrt(double *U, double *SV, int n, int batch, hipStream_t s) {
     if (batch <= 0) return hipSuccess;
-    if (n < 1 || n > 128) return hipErrorInvalidValue;
+    if (n < 1 || n > 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_split_sqrt, dim3(batch), dim3(256), 0, s, reinterpret_cast<double2 *>(U),
                        reinterpret_cast<double2 *>(SV), n);
     return hipGetLastError();

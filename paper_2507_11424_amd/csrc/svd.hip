@@ -30,9 +30,10 @@ constexpr double SVD_TOL = 1e-15;  // |gamma| <= tol sqrt(alpha beta) counts as 
 constexpr int SVD_GRID = 512;      // blocks (and workspace slices) at most
 constexpr double SVD_RANK_RTOL = 1e-12;  // sigma <= rtol sigma_max counts as zero
 // Columns with ||w||^2 <= SVD_NEGL ||R||_F^2 take part in no rotation: they lie
-// below the rank cut (sigma_max >= ||R||_F / sqrt(128)), and rotating such
+// below the rank cut (sigma_max >= ||R||_F / sqrt(n) >= ||R||_F / 16), and rotating such
 // residue against the large columns only drives it towards underflow.
 constexpr double SVD_NEGL = 1e-28;
+static_assert(SVD_NMAX <= SVD_NT, "the rank sort gives one thread per column");
 
 __device__ inline double2 cm(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 

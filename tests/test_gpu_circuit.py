@@ -57,6 +57,9 @@ CASES = {
     "sq3x3D3-random": lambda: (square_lattice(3, 3, 3), "haar", lambda l: _random_gates(l, 1, 7), "full"),
     "brick3x4D4-random": lambda: (brick_lattice(3, 4, 4), "haar", lambda l: _random_gates(l, 2, 8), "full"),
     "sq1x6D2-random": lambda: (square_lattice(1, 6, 2), "haar", lambda l: _random_gates(l, 2, 9), "full"),
+    # bonds above 32: the middle column's vertical gate reduces to a 136 x 136
+    # pair matrix (the SVD's global-memory path)
+    "sq2x3D34-random": lambda: (square_lattice(2, 3, 34), "haar", lambda l: _random_gates(l, 1, 12), "full"),
 }
 
 
@@ -118,3 +121,7 @@ def test_simple_update_rejects_bad_gates(handle):
         handle.simple_update(P, [(0, 0, 0, 1, 1)], np.eye(4))  # diagonal pair
     with pytest.raises(tnb.TnError):
         handle.simple_update(P, [(0, 1, 1, 1, 2)], np.eye(4))  # outside the grid
+    with pytest.raises(tnb.TnError):  # two gates of one group on qubit (0, 0)
+        handle.simple_update(P, [(0, 0, 0, 0, 1), (0, 0, 0, 1, 0)], np.eye(4))
+    # the same pair in consecutive groups is fine
+    handle.simple_update(P, [(0, 0, 0, 0, 1), (1, 0, 0, 1, 0)], np.eye(4))

@@ -396,7 +396,7 @@ def test_timing_mode_with_nested_contractions():
 def _svd_cases():
     rng = np.random.default_rng(31)
     out = []
-    for n in (1, 2, 7, 16, 33, 64, 65, 128):
+    for n in (1, 2, 7, 16, 33, 64, 65, 128, 200, 256):
         R = _rand(rng, (5, n, n)) * np.exp(-0.35 * np.arange(n))[None, None, :]
         R[1] = np.triu(R[1])                      # QR-shaped
         if n > 2:
@@ -414,7 +414,7 @@ def _svd_cases():
     return out
 
 
-@pytest.mark.parametrize("case", range(8))
+@pytest.mark.parametrize("case", range(10))
 @pytest.mark.parametrize("cutoff,chi_min", [(1e-2, 1), (1e-6, 1), (1e-2, 5), (1e-300, 1)])
 @pytest.mark.parametrize("esz", [16, 8])
 def test_svd_truncation(handle, case, cutoff, chi_min, esz):
