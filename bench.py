@@ -425,7 +425,7 @@ def simple_update_bench(a):
         return h.simple_update(P, gl, G, in_place=True)
 
     t0 = time.perf_counter()
-    layer(0)
+    _, eps0, _ = layer(0)
     torch.cuda.synchronize()
     warm = time.perf_counter() - t0
     print(f"warmup layer {warm:.1f} s", file=sys.stderr, flush=True)
@@ -450,6 +450,8 @@ def simple_update_bench(a):
            "layer_ms": ms,
            "eps_max": max(eps_all), "eps_mean": float(np.mean(eps_all)),
            "fidelity_estimate_timed_layers": float(np.prod([1 - e for e in eps_all])),
+           "layers_total": a.su_layers + 1,
+           "fidelity_estimate_all_layers": float(np.prod([1 - e for e in list(eps0) + eps_all])),
            "last_layer_launches": {"contraction": c["gemm_launches"], "orthonormalisation": c["qr_launches"]},
            "roofline": {"bound": "latency", "note": "per colour group a BP solve, then per class of gates "
                                                     "(same orientation and site shapes) a few tens of batched "

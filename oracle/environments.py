@@ -80,11 +80,14 @@ def two_row_right(Re, U, A1, A2, B):
     return ein("pGabcxde,gxeG->pabcdg", x5, B)
 
 
-def environments(tensors, chi: int, sweeps: int = 2, seed: int = 0, force_fit: bool = False):
+def environments(tensors, chi: int, sweeps: int = 2, seed: int = 0, force_fit: bool = False,
+                 vertical: bool = True):
     """Returns dict with rho1 [rows][cols][2][2] (normalised, NaN for dummies),
     zz_h [rows][cols-1], zz_v [rows-1][cols], p2_h [rows][cols-1][4],
     p2_v [rows-1][cols][4] (diagonal of the two-site marginal, order
-    (s,t) = 00, 01, 10, 11) and the row-wise norm estimates."""
+    (s,t) = 00, 01, 10, 11) and the row-wise norm estimates.  vertical=False
+    skips the two-row environments (zz_v and p2_v stay NaN), by far the
+    costliest part at large bond."""
     rows, cols = len(tensors), len(tensors[0])
     below, _, _ = boundary_set(tensors, chi, sweeps, seed, TAG_INIT_DOWN, force_fit)
     fb, _, _ = boundary_set(flip_vertical(tensors), chi, sweeps, seed, TAG_INIT_UP, force_fit)
@@ -125,7 +128,7 @@ def environments(tensors, chi: int, sweeps: int = 2, seed: int = 0, force_fit: b
             p2_h[r, c] = P / P.sum()
             zz_h[r, c] = (P[0] - P[1] - P[2] + P[3]) / P.sum()
     one6 = np.ones((1,) * 6, dtype=np.complex128)
-    for r in range(rows - 1):
+    for r in range(rows - 1 if vertical else 0):
         U, B, r1, r2 = above[r], below[r + 1], tensors[r], tensors[r + 1]
         Le = [None] * (cols + 1)
         Ri = [None] * (cols + 1)

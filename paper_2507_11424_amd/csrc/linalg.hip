@@ -73,10 +73,32 @@ __device__ inline double block_sum(double v, double *red) {
     return s;
 }
 
+// Block maximum over QR_NT threads; every thread receives the result.
+__device__ inline double block_max(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < QR_NT / 64; ++i) m = fmax(m, red[i]);
+    return m;
+}
+
+// Below this sum of squares a column's norm is recomputed from values scaled
+// by its largest modulus: squares of entries under ~1e-154 fall into the
+// subnormal range (or to zero) and would give an inaccurate norm.
+constexpr double HH_SMALL2 = 1e-280;
+
 // In-place Householder factorisation of X (rows x n, leading dimension ld).
-// After return: X[i][j], i >= j, holds reflector j (v_j[0] on the diagonal);
-// X[i][j], i < j, holds R; beta[j] = R[j][j]; tau[j] = 2 / ||v_j||^2.
-// H_j = I - tau_j v_j v_j^H is Hermitian and unitary; A = H_0 ... H_{k-1} R.
+// After return: X[i][j], i >= j, holds reflector j normalised to v_j[0] = 1
+// (the 1 stored on the diagonal); X[i][j], i < j, holds R; beta[j] = R[j][j];
+// tau[j] = 2 / ||v_j||^2 = (|alpha| + sigma) / sigma, between 1 and 2 (0 for a
+// zero column).  H_j = I - tau_j v_j v_j^H is Hermitian and unitary; A = H_0 ...
+// H_{k-1} R.  With the normalised reflector nothing in the step scales like
+// 1 / sigma^2, so columns whose remaining norm is far below the others' (the
+// rank-deficient matrices of gauged site tensors) stay finite and exact.
 __device__ void hh_factor(double2 *X, int rows, int n, int ld, double2 *beta, double *tau,
                           double *red, double2 *wpart) {
     const int t = threadIdx.x;
@@ -88,17 +110,43 @@ __device__ void hh_factor(double2 *X, int rows, int n, int ld, double2 *beta, do
             s += x.x * x.x + x.y * x.y;
         }
         s = block_sum(s, red);
+        double sigma = sqrt(s);
+        if (s < HH_SMALL2) {  // uniform over the block
+            double cm = 0.0;
+            for (int i = j + t; i < rows; i += QR_NT) {
+                const double2 x = X[(int64_t)i * ld + j];
+                cm = fmax(cm, fmax(fabs(x.x), fabs(x.y)));
+            }
+            cm = block_max(cm, red);
+            double s2 = 0.0;
+            if (cm > 0.0) {
+                for (int i = j + t; i < rows; i += QR_NT) {
+                    const double2 x = X[(int64_t)i * ld + j];
+                    const double xr = x.x / cm, xi = x.y / cm;
+                    s2 += xr * xr + xi * xi;
+                }
+            }
+            s2 = block_sum(s2, red);
+            sigma = cm > 0.0 ? cm * sqrt(s2) : 0.0;
+        }
         const double2 alpha = X[(int64_t)j * ld + j];
-        const double sigma = sqrt(s);
         const double aabs = hypot(alpha.x, alpha.y);
         __syncthreads();
         double tj = 0.0;
         double2 bj = make_double2(0.0, 0.0);
         if (sigma > 0.0) {
             const double2 ph = aabs > 0.0 ? make_double2(alpha.x / aabs, alpha.y / aabs) : make_double2(1.0, 0.0);
+            const double d = aabs + sigma;  // |v_j[0]| before normalisation
             bj = make_double2(-ph.x * sigma, -ph.y * sigma);
-            tj = 1.0 / (sigma * (sigma + aabs));
-            if (t == 0) X[(int64_t)j * ld + j] = make_double2(ph.x * (aabs + sigma), ph.y * (aabs + sigma));
+            tj = d / sigma;
+            // v_j[i] = x_i / (ph d) below the diagonal (divisions, not a
+            // reciprocal: d may be subnormal)
+            for (int i = j + 1 + t; i < rows; i += QR_NT) {
+                const double2 x = X[(int64_t)i * ld + j];
+                const double2 xc = cmulc(ph, x);  // conj(ph) x
+                X[(int64_t)i * ld + j] = make_double2(xc.x / d, xc.y / d);
+            }
+            if (t == 0) X[(int64_t)j * ld + j] = make_double2(1.0, 0.0);
         }
         if (t == 0) { beta[j] = bj; tau[j] = tj; }
         __syncthreads();

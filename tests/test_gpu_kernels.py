@@ -329,6 +329,37 @@ def test_qr_rank_deficient(handle):
     assert np.abs(Q @ R - A[0]).max() < 1e-10 * np.abs(A).max()
 
 
+@pytest.mark.parametrize("m,n", [(2500, 100), (3000, 40), (50, 100)])
+def test_householder_tiny_columns(handle, m, n):
+    """Householder QR of matrices whose column norms span 1 down to the
+    subnormal range, with exact zero columns and a tiny multiple of another
+    column (the gauged site matrices of the simple update at large bond are
+    like this).  Paths: one workgroup in global memory (2500 x 100), a TSQR
+    tree (3000 x 40), one LDS block of a wide matrix (50 x 100).  Q must be
+    finite and orthonormal and QR must reproduce A: a column norm whose squares
+    underflow is taken from scaled values, and the normalised reflectors never
+    divide by a squared norm."""
+    import torch
+    rng = np.random.default_rng(m + 3 * n)
+    A = _rand(rng, (2, m, n))
+    A *= 10.0 ** -rng.choice([0, 3, 20, 156, 160, 170, 200, 310], size=(2, 1, n))
+    A[0, :, 3] = 0
+    A[1, :, :5] = 0
+    A[1, :, 10] = A[1, :, 11] * 1e-150
+    k = min(m, n)
+    dA = torch.from_numpy(A).cuda()
+    dQ = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
+    dR = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
+    handle.test_qr(dA, dQ, dR, "householder")
+    torch.cuda.synchronize()
+    Q, R = dQ.cpu().numpy(), dR.cpu().numpy()
+    assert np.all(np.isfinite(Q)) and np.all(np.isfinite(R))
+    for b in range(2):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(k)).max() < 1e-12 * np.sqrt(m)
+        assert np.abs(np.tril(R[b], -1)).max() == 0.0
+        assert np.abs(Q[b] @ R[b] - A[b]).max() < 1e-13 * np.abs(A[b]).max() * np.sqrt(m)
+
+
 @pytest.mark.parametrize("layout", ["ik,kj->ij", "ki,kj->ij"])
 def test_contract_operand_over_2gib(handle, layout):
     """An operand spanning more than 2 GiB is cut into slices on the host (the

@@ -196,6 +196,11 @@ def test_environments_exact(name):
                 # (s, t) = (upper, lower) qubit: a swapped order leaves zz unchanged but not p2
                 p2 = [np.sum(P * (idx[q] == s) * (idx[q2] == t)) for s in (0, 1) for t in (0, 1)]
                 assert np.abs(np.array(p2) - env["p2_v"][r, c]).max() < 1e-12
+    # without the two-row environments: the same one-site and horizontal values
+    env_h = environments(T, chi, vertical=False)
+    for k in ("rho1", "zz_h", "p2_h"):
+        assert np.array_equal(env_h[k], env[k], equal_nan=True)
+    assert np.all(np.isnan(env_h["zz_v"])) and np.all(np.isnan(env_h["p2_v"]))
 
 
 @pytest.mark.parametrize("name", ["square3x3D2", "brick4x4D2", "c1", "rotsq10D2", "heavyhex3x5D2", "stag10D2"])
