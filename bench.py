@@ -419,10 +419,11 @@ def simple_update_bench(a):
     h.set_autotune(True, None)
     P = tnb.Peps.from_numpy(lat, T0, dtype="c128", device="cuda:0")
     ngroups = len({g[0] for g in gates1})
+    msgs = h.message_buffer(P)  # each layer's BP continues from the previous layer's messages
 
     def layer(l):
         gl = [(l * ngroups + g[0],) + tuple(g[1:]) for g in gates1]
-        return h.simple_update(P, gl, G, in_place=True)
+        return h.simple_update(P, gl, G, in_place=True, messages_in=msgs if l > 0 else None, messages_out=msgs)
 
     t0 = time.perf_counter()
     _, eps0, _ = layer(0)

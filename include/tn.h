@@ -245,6 +245,13 @@ tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, d
  *   eps         host [n_gates] out: the discarded weight of each gate's
  *               normalised singular values, sum_{j>=D} s_j^2 / sum_j s_j^2.
  *   fidelity    host out (may be NULL): prod_i (1 - eps_i).
+ *   messages_in   optional DEVICE [rows*cols][4][Dm][Dm] complex128 (the
+ *                 layout of tn_bp's messages, Dm = the largest bond): the
+ *                 first group's BP starts from them instead of identity /
+ *                 sqrt(D) -- pass an earlier call's messages_out to continue
+ *                 a circuit split over several calls exactly as one call.
+ *   messages_out  optional DEVICE, same layout (may equal messages_in): the
+ *                 last group's converged messages.
  * Per gate: the pair gauged with the square roots of its incoming messages
  * (pseudo-inverse roots to undo it; message eigenvalues at or below 1e-12 of
  * the largest taken as 0), reduced by QR, the gate applied, an SVD kept to
@@ -256,7 +263,8 @@ tn_status tn_bp(tn_handle *h, const tn_peps *peps, int max_sweeps, double tol, d
  * limit. */
 tn_status tn_simple_update(tn_handle *h, const tn_peps *peps, void *const *site_out, int n_gates,
                            const int32_t *gate_sites, const double *gates, int gate_stride, int bp_max_sweeps,
-                           double bp_tol, double *eps, double *fidelity);
+                           double bp_tol, double *eps, double *fidelity, const void *messages_in,
+                           void *messages_out);
 
 /* Sample-quality metrics from per-sample log q and log p (device [n] doubles,
  * natural logs), with w_i = p(x_i)/q(x_i) (Methods, the unbiased norm

@@ -100,7 +100,7 @@ def lib(path: Optional[str] = None):
                         ctypes.c_int, ip, vp]
     L.tn_test_eig.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
     L.tn_simple_update.argtypes = [vp, ctypes.POINTER(c_peps), vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_double, vp, dp]
+                                   ctypes.c_double, vp, dp, vp, vp]
     for f in ("tn_create", "tn_destroy", "tn_boundary_contract", "tn_environments", "tn_sample",
               "tn_get_counters", "tn_set_timing", "tn_set_autotune", "tn_test_contract",
               "tn_test_qr", "tn_test_svd", "tn_test_set_mask", "tn_amplitude", "tn_sample_stats",
@@ -324,12 +324,15 @@ class Handle:
         return res
 
     def simple_update(self, peps: Peps, gates, G, bp_max_sweeps: int = 1000, bp_tol: float = 1e-13,
-                      in_place: bool = False):
+                      in_place: bool = False, messages_in=None, messages_out=None):
         """Applies two-qubit gates by BP-gauged simple update (see
         tn_simple_update).  gates: sequence of (group, r, c, r2, c2); G: one
         4 x 4 complex matrix for all gates or one per gate.  Returns (Peps of
         the result, gate errors eps (numpy), fidelity estimate prod(1 - eps));
-        in_place writes the result into peps's own tensors."""
+        in_place writes the result into peps's own tensors.  messages_in /
+        messages_out: optional complex128 device tensors [rows*cols][4][Dm][Dm]
+        (see message_buffer) to start the BP from and to receive the last
+        group's messages."""
         import torch
         gl = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 5))
         Gm = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
@@ -343,8 +346,29 @@ class Handle:
         self._check(lib().tn_simple_update(self.h, ctypes.byref(peps.c), ptrs, int(gl.shape[0]),
                                            gl.ctypes.data_as(ctypes.c_void_p), Gm.ctypes.data_as(ctypes.c_void_p),
                                            stride, int(bp_max_sweeps), float(bp_tol),
-                                           eps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(f)))
+                                           eps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(f),
+                                           self._msg_ptr(peps, messages_in), self._msg_ptr(peps, messages_out)))
         return out, eps, f.value
+
+    @staticmethod
+    def message_buffer(peps: Peps):
+        """A complex128 device tensor [rows*cols][4][Dm][Dm] for BP messages."""
+        import torch
+        L = peps.lattice
+        dm = int(max(1, np.max(L.dim_h) if L.dim_h.size else 1, np.max(L.dim_v) if L.dim_v.size else 1))
+        return torch.zeros((L.rows * L.cols, 4, dm, dm), dtype=torch.complex128, device=peps.tensors[0].device)
+
+    @staticmethod
+    def _msg_ptr(peps: Peps, m):
+        import torch
+        if m is None:
+            return None
+        L = peps.lattice
+        dm = int(max(1, np.max(L.dim_h) if L.dim_h.size else 1, np.max(L.dim_v) if L.dim_v.size else 1))
+        if (m.dtype != torch.complex128 or tuple(m.shape) != (L.rows * L.cols, 4, dm, dm) or not m.is_contiguous()
+                or m.device != peps.tensors[0].device):
+            raise ValueError("messages: contiguous complex128 [rows*cols][4][Dm][Dm] on the state's device")
+        return ctypes.c_void_p(m.data_ptr())
 
     def test_eig(self, A):
         """Eigenvalues (unordered), eps and info of complex128 matrices A

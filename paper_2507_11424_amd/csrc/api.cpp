@@ -358,7 +358,8 @@ tn_status tn_sample(tn_handle *h, const tn_peps *p, const tn_opts *o, uint64_t s
 
 tn_status tn_simple_update(tn_handle *h, const tn_peps *p, void *const *site_out, int n_gates,
                            const int32_t *gate_sites, const double *gates, int gate_stride, int bp_max_sweeps,
-                           double bp_tol, double *eps, double *fidelity) {
+                           double bp_tol, double *eps, double *fidelity, const void *messages_in,
+                           void *messages_out) {
     try {
         begin(h, nullptr);
         tn_opts dflt;
@@ -388,7 +389,7 @@ tn_status tn_simple_update(tn_handle *h, const tn_peps *p, void *const *site_out
             SuOpts so;
             so.bp_max_sweeps = bp_max_sweeps;
             so.bp_tol = bp_tol;
-            simple_update(E, P, gl, gates, gate_stride, so, eps);
+            simple_update(E, P, gl, gates, gate_stride, so, eps, messages_in, messages_out);
             const int dst_esz = p->dtype == TN_C128 ? 16 : 8;
             for (int i = 0; i < rows * cols; ++i) {
                 const Ten &t = P.site[(size_t)i];

@@ -137,7 +137,7 @@ void run_copies(Engine &E, std::vector<tnk::CopyBlock> &&tab, std::vector<std::v
 }  // namespace
 
 void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, const double *gmat, int gstride,
-                   const SuOpts &o, double *eps_host) {
+                   const SuOpts &o, double *eps_host, const void *msg_in, void *msg_out) {
     const int rows = P.rows, cols = P.cols, N = rows * cols;
     const int ng = (int)gates.size();
     if (ng == 0) return;
@@ -192,6 +192,10 @@ void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, cons
     try {
         TN_HIP(hipMemcpyAsync(Gd.p, gmat, (size_t)nmat * 16 * 16, hipMemcpyHostToDevice, E.s));
         bool first = true;
+        if (msg_in) {  // continue from an earlier call's messages
+            TN_HIP(hipMemcpyAsync(msg.p, msg_in, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
+            first = false;
+        }
         for (int g0 = 0; g0 < ng;) {
             int g1 = g0;
             while (g1 < ng && gates[g1].group == gates[g0].group) ++g1;
@@ -347,6 +351,7 @@ void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, cons
             raws.clear();
             g0 = g1;
         }
+        if (msg_out) TN_HIP(hipMemcpyAsync(msg_out, msg.p, msg.bytes(), hipMemcpyDeviceToDevice, E.s));
         std::vector<double> tmp((size_t)ng);
         TN_HIP(hipMemcpyAsync(tmp.data(), eps_d, (size_t)ng * 8, hipMemcpyDeviceToHost, E.s));
         E.sync();

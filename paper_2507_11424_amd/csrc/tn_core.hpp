@@ -137,7 +137,12 @@ struct SuOpts {
 // P's complex128 site tensors are replaced in place; gmat (host) holds the
 // 4 x 4 complex128 gate matrices, gstride = 16 complex numbers per gate or 0
 // (one matrix for every gate); eps_host [gates] receives the gate errors.
+// msg_in (optional, device [rows*cols][4][Dm][Dm] complex128, the BpOpts
+// message layout): the first group's BP starts from these messages instead of
+// identity / sqrt(D); msg_out (optional, same layout, may alias msg_in)
+// receives the last group's converged messages, so that a circuit split over
+// several calls runs as one.
 void simple_update(Engine &E, PepsDev &P, const std::vector<SuGate> &gates, const double *gmat, int gstride,
-                   const SuOpts &o, double *eps_host);
+                   const SuOpts &o, double *eps_host, const void *msg_in = nullptr, void *msg_out = nullptr);
 
 }  // namespace tnb

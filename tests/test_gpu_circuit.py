@@ -113,6 +113,28 @@ def test_simple_update_in_place_and_complex64(handle):
         assert np.abs(a.cpu().numpy() - b.cpu().numpy().astype(np.complex64)).max() == 0.0
 
 
+def test_simple_update_continues_from_messages(handle):
+    """A circuit split over two calls, the second starting its BP from the
+    first call's final messages, gives the same gate errors and state as one
+    call over the whole circuit (and the oracle's)."""
+    import paper_2507_11424_amd as tnb
+    lat = brick_lattice(3, 4, 3)
+    T0 = random_peps(lat, "haar", 0.5, 74)
+    gates, G = _random_gates(lat, 2, 13)
+    cut = next(i for i, g in enumerate(gates) if g[0] != gates[0][0])  # after the first group
+    ref, reps, _ = handle.simple_update(tnb.Peps.from_numpy(lat, T0), gates, G)
+    P = tnb.Peps.from_numpy(lat, T0)
+    m = handle.message_buffer(P)
+    _, e1, _ = handle.simple_update(P, gates[:cut], G[:cut], in_place=True, messages_out=m)
+    _, e2, _ = handle.simple_update(P, gates[cut:], G[cut:], in_place=True, messages_in=m, messages_out=m)
+    eps = np.concatenate([e1, e2])
+    assert np.abs(eps - reps).max() < 1e-12
+    for a, b in zip(P.tensors, ref.tensors):
+        assert (a - b).abs().max().item() < 1e-12
+    _, oeps, _ = simple_update(T0, gates, G)
+    assert np.abs(eps - np.array(oeps)).max() < 1e-9
+
+
 def test_simple_update_rejects_bad_gates(handle):
     import paper_2507_11424_amd as tnb
     lat = square_lattice(2, 2, 2)
