@@ -67,6 +67,14 @@ def parse():
     ap.add_argument("--su-D", type=int, default=16, help="bond dimension of the simple-update state")
     ap.add_argument("--su-layers", type=int, default=4, help="timed Trotter layers (one more untimed first)")
     ap.add_argument("--su-dt", type=float, default=0.1)
+    ap.add_argument("--quench-R", default="",
+                    help="with --quench-sample: comma-separated boundary dimensions R, each sampled in turn from "
+                         "the same evolved state (default: --chi, else 8)")
+    ap.add_argument("--quench-sample", default="", choices=["", "hhx", "rotsq"],
+                    help="the paper's end-to-end experiment: the Heisenberg quench by simple update (--su-D, "
+                         "1 + --su-layers layers), then the norm and --samples samples from the evolved state at "
+                         "R = --chi (boundary and amplitude bonds), the sample KLD and the share of samples with "
+                         "the conserved magnetisation; one JSON line of its own")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -477,6 +485,96 @@ def simple_update_bench(a):
     h.close()
 
 
+def quench_sample_bench(a):
+    """Evolve the domain wall by simple update, then contract and sample the
+    evolved state with boundary MPSs of dimension R (the paper's heavy-hex and
+    Willow sampling experiments): samples/s, KLD against p / Z, and the share
+    of samples whose number of 1s equals the domain wall's (the Heisenberg
+    layers conserve it)."""
+    import numpy as np
+    import torch
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import heavy_hex_lattice, rotated_square_lattice
+    from peps_inputs.circuits import heisenberg_circuit, domain_wall_peps, domain_wall_ones
+    D, R = a.su_D, a.chi or 8
+    n = a.samples
+    lat = heavy_hex_lattice(7, 15, D) if a.quench_sample == "hhx" else rotated_square_lattice(D)
+    gates1, G = heisenberg_circuit(lat, 1, a.su_dt)
+    ngroups = len({g[0] for g in gates1})
+    layers = a.su_layers + 1
+    h = tnb.Handle(0, torch.cuda.current_stream(0))
+    h.set_autotune(not a.no_autotune, a.tune_cache or None)
+    P = tnb.Peps.from_numpy(lat, domain_wall_peps(lat), dtype="c128", device="cuda:0")
+    msgs = h.message_buffer(P)
+    eps_all = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for l in range(layers):
+        gl = [(l * ngroups + g[0],) + tuple(g[1:]) for g in gates1]
+        _, eps, _ = h.simple_update(P, gl, G, in_place=True, messages_in=msgs if l > 0 else None, messages_out=msgs)
+        eps_all.extend(eps.tolist())
+        print(f"layer {l}: max eps {max(eps):.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_su = time.perf_counter() - t0
+    Ps = P if a.prec == "fp64" else tnb.Peps(lat, [t.to(torch.complex64) for t in P.tensors])
+    want = domain_wall_ones(lat)
+    Rs = [int(x) for x in a.quench_R.split(",")] if a.quench_R else [R]
+    # references: Z from the boundary contraction at the largest R, p(x) certified by the separate
+    # amplitude contraction at bond 2D (the paper's check)
+    R_ref = max(Rs)
+    t0 = time.perf_counter()
+    lz_ref, _ = h.boundary_contract(P, tnb.make_opts(chi=R_ref, chi_x=R_ref))
+    t_ref = time.perf_counter() - t0
+    o_amp = tnb.make_opts(chi=2 * D, chi_x=2 * D)
+    bp_z = h.bp(P, loops=False)["log_abs_Z"]
+    print(f"reference log|Z| at R={R_ref}: {lz_ref:.8f} ({t_ref:.1f} s); BP log|Z_BP| {bp_z:.8f}",
+          file=sys.stderr, flush=True)
+    runs = []
+    for R in Rs:
+        o = tnb.make_opts(chi=R, chi_x=R, prec=a.prec)
+        t0 = time.perf_counter()
+        lz, _ = h.boundary_contract(Ps, o)
+        torch.cuda.synchronize()
+        t_norm = time.perf_counter() - t0
+        h.sample(Ps, o, min(n, 2), seed=11)  # warm-up: tile choices and plans
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bits, lq, lp = h.sample(Ps, o, n, seed=11)[:3]
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lp_c = h.amplitude(P, o_amp, bits)
+        torch.cuda.synchronize()
+        t_amp = time.perf_counter() - t0
+        st = h.sample_stats(lq, lp_c, lz_ref)
+        ones = bits.to(torch.int64).sum(dim=1).cpu().numpy()
+        r = (lp_c - lq - lz_ref).cpu().numpy()  # log (p(x) / Z q(x))
+        runs.append({"R": R, "norm_s": t_norm, "log_abs_Z": lz, "samples_per_s": n / t_s, "kld": st["kld"],
+                     "ess": st["ess"], "log_norm_estimate": st["log_norm_est"],
+                     "share_correct_magnetisation": float(np.mean(ones == want)),
+                     "log10_p_over_Zq_range": [float(r.min() / np.log(10)), float(r.max() / np.log(10))],
+                     "max_abs_sampler_log_p_vs_certified": float((lp - lp_c).abs().max()),
+                     "certify_s": t_amp})
+        print(f"R={R}: norm {t_norm:.1f} s, {n} samples {t_s:.1f} s, KLD {st['kld']:.3e}, "
+              f"correct magnetisation {runs[-1]['share_correct_magnetisation']:.3f}", file=sys.stderr, flush=True)
+    last = runs[-1]
+    out = {"metric": "samples/sec (evolved Heisenberg quench state, boundary-MPS sampler)",
+           "value": last["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": 1e3 * n / last["samples_per_s"], "higher_is_better": True, "dtype": DTYPE[a.prec],
+           "data": "synthetic",
+           "config": {"workload": f"{lat.name}: {lat.n_qubits} qubits, Heisenberg quench dt={a.su_dt} J=1 from the "
+                                  f"domain wall, {layers} layers by simple update at D={D}, then norm and {n} "
+                                  f"samples per R in {Rs} (value: R={last['R']})"},
+           "simple_update_s": t_su, "fidelity_estimate": float(np.prod([1 - e for e in eps_all])),
+           "magnetisation_ones": want, "reference_log_abs_Z": lz_ref, "reference_R": R_ref,
+           "bp_log_abs_Z": bp_z, "certified_p_bond": 2 * D,
+           "note": "kld = mean(log q - log p + log Z) with p from tn_amplitude at bond 2D and Z from the "
+                   "boundary contraction at the largest R",
+           "runs": runs}
+    print(json.dumps(out))
+    h.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -487,6 +585,9 @@ def main():
         return
     if a.simple_update:
         simple_update_bench(a)
+        return
+    if a.quench_sample:
+        quench_sample_bench(a)
         return
     import numpy as np
     import torch

@@ -469,7 +469,12 @@ Plan *Engine::plan(const Op &A0, const Op &B0, const Op &C0) {
         std::memcpy(host.data() + off, src64[i]->data(), src64[i]->size() * 8);
         off += src64[i]->size() * 8;
     }
-    TN_HIP(hipMalloc(&P->dev, bytes));
+    if (hipMalloc(&P->dev, bytes) != hipSuccess) {
+        // the pool's cached blocks may hold the memory: return them and retry
+        (void)hipGetLastError();
+        if (!capturing()) pool_.trim();
+        TN_HIP(hipMalloc(&P->dev, bytes));
+    }
     TN_HIP(hipMemcpy(P->dev, host.data(), bytes, hipMemcpyHostToDevice));
     char *d = reinterpret_cast<char *>(P->dev);
     size_t o2 = 0;
@@ -1017,6 +1022,9 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
             if (a.R)
                 for (int i = 0; i < 3; ++i) tmp.push_back(make({Z, n, n}, 16));
             const double u = 1.1102230246251565e-16;
+            // a clamped pivot in any pass flags the item for the Householder fallback
+            int *flags = static_cast<int *>(raw((size_t)Z * sizeof(int)));
+            TN_HIP(tnk::launch_fill_i32(flags, Z, 0, s));
             for (int pass = 0; pass <= 3; ++pass) {
                 tnk::CqrPass c{};
                 c.m = m; c.n = n; c.batch = Z; c.rb = rb;
@@ -1045,7 +1053,7 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
                                              reinterpret_cast<double *>(G.p), s));
                 TN_HIP(tnk::launch_chol_inv(reinterpret_cast<const double *>(G.p), n, Z, shift, clamp,
                                             reinterpret_cast<double *>(Ri.p),
-                                            a.R ? reinterpret_cast<double *>(tmp[r0 + pass].p) : nullptr, nullptr,
+                                            a.R ? reinterpret_cast<double *>(tmp[r0 + pass].p) : nullptr, flags,
                                             s));
             }
             if (a.R) {
@@ -1054,6 +1062,13 @@ void Engine::ortho_impl(const tnk::QrArgs &a, bool householder_blocks) {
                 TN_HIP(tnk::launch_strided_copy(Ri.p, 16, (int64_t)n * n, n, 1, a.R, a.r_esz, a.r_bs, a.r_rs, a.r_cs, n,
                                                 n, Z, a.r_conj, s));
             }
+            // Numerically rank-deficient items (a pivot clamped: the passes cannot
+            // complete a basis from dependent columns) are refactored by Householder,
+            // which returns orthonormal columns for any rank; the others skip it.
+            void *ws = raw(tnk::qr_fallback_workspace_bytes(m, n, Z));
+            TN_HIP(tnk::launch_qr_fallback(a, flags, ws, s));
+            unraw(ws);
+            unraw(flags);
         } else {
             // Wider than one Cholesky block: columns in blocks of 64; each block is
             // made orthogonal to the finished ones by three passes of block

@@ -174,7 +174,10 @@ class Engine {
     // Orthonormal Q for m >= n (else Householder): shifted CholeskyQR3 in
     // FP64 -- three passes of Gram matrix (MFMA), Cholesky and R^{-1} (one
     // workgroup), Q <- Q R^{-1} (MFMA); the first pass adds the shift
-    // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots.  If
+    // 11 (mn + n(n+1)) u tr(G), the others only clamp non-positive pivots;
+    // an item with a clamped pivot (numerically rank deficient: singular values
+    // below ~1e-11 of the largest) is refactored by Householder on the device,
+    // so Q has orthonormal columns for any rank.  If
     // a.R is set, R = R_3 R_2 R_1 (A = Q R to about u cond(A); meant for
     // well-conditioned A such as random initial guesses).  n > 64: blocks of 64
     // columns, each orthogonalised against the previous ones by three passes of

@@ -86,6 +86,13 @@ struct QrArgs {
 };
 size_t qr_workspace_bytes(int m, int n, int batch);
 hipError_t launch_qr(const QrArgs &a, void *workspace, hipStream_t s);
+// Householder QR (one workgroup per matrix, global memory) of the batch items
+// whose flags[b] has bit 4 set (a clamped Cholesky pivot), overwriting their Q
+// (and R); the other items return at once.  The fallback of CholeskyQR for
+// numerically rank-deficient input.  Its workspace holds at most 16 MiB of
+// per-matrix slots (at least one): the workgroups loop over the batch.
+size_t qr_fallback_workspace_bytes(int m, int n, int batch);
+hipError_t launch_qr_fallback(const QrArgs &a, const int *flags, void *workspace, hipStream_t s);
 
 // Cholesky of Hermitian G (batch x n x n, complex128, only the upper triangle is
 // read) as G + shift * tr(G)/n * I = R^H R, Rinv = R^{-1} (upper triangular,

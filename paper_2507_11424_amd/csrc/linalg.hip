@@ -334,45 +334,52 @@ struct GlobalQrArgs {
     char *ws; int64_t ws_bs;
     size_t w_off, y_off, t_off, b_off;
     MatOut Q; MatOut R; int want_r;
+    int batch;
+    const int *only_if;  // optional [batch]: factor only the items whose flag has bit 4 set
 };
 
+// One workgroup per matrix; the workgroups loop over the batch (workspace slot
+// = blockIdx.x), skipping the items not flagged in only_if when it is given.
 __global__ void __launch_bounds__(QR_NT) k_qr_global(GlobalQrArgs a) {
     __shared__ double red[QR_NT / 64];
     __shared__ double2 wpart[QR_NT];
-    const int bt = blockIdx.x;
     const int m = a.m, n = a.n, k = m < n ? m : n;
-    char *wb = a.ws + (int64_t)bt * a.ws_bs;
+    char *wb = a.ws + (int64_t)blockIdx.x * a.ws_bs;
     double2 *X = reinterpret_cast<double2 *>(wb + a.w_off);
     double2 *Y = reinterpret_cast<double2 *>(wb + a.y_off);
     double *tau = reinterpret_cast<double *>(wb + a.t_off);
     double2 *beta = reinterpret_cast<double2 *>(wb + a.b_off);
-    const char *inb = reinterpret_cast<const char *>(a.in.p) + (int64_t)bt * a.in.bs * a.in.esz;
-    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += QR_NT) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        X[e] = ld_c(inb, a.in.esz, (int64_t)i * a.in.rs + (int64_t)j * a.in.cs, a.in.conj);
-    }
-    __syncthreads();
-    hh_factor(X, m, n, n, beta, tau, red, wpart);
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
-        const int i = (int)(e / k), c = (int)(e % k);
-        Y[e] = make_double2(i == c ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    hh_apply(Y, m, k, k, X, n, k, tau, wpart);
-    char *qb = reinterpret_cast<char *>(a.Q.p) + (int64_t)bt * a.Q.bs * a.Q.esz;
-    for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
-        const int i = (int)(e / k), c = (int)(e % k);
-        st_c(qb, a.Q.esz, (int64_t)i * a.Q.rs + (int64_t)c * a.Q.cs, Y[e], a.Q.conj);
-    }
-    if (a.want_r) {
-        char *rb = reinterpret_cast<char *>(a.R.p) + (int64_t)bt * a.R.bs * a.R.esz;
-        for (int64_t e = threadIdx.x; e < (int64_t)k * n; e += QR_NT) {
+    for (int bt = blockIdx.x; bt < a.batch; bt += gridDim.x) {
+        if (a.only_if && !(a.only_if[bt] & 4)) continue;  // uniform over the block
+        const char *inb = reinterpret_cast<const char *>(a.in.p) + (int64_t)bt * a.in.bs * a.in.esz;
+        __syncthreads();  // the previous item's last reads of the workspace
+        for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += QR_NT) {
             const int i = (int)(e / n), j = (int)(e % n);
-            double2 v = make_double2(0.0, 0.0);
-            if (j == i) v = beta[i];
-            else if (j > i) v = X[(int64_t)i * n + j];
-            st_c(rb, a.R.esz, (int64_t)i * a.R.rs + (int64_t)j * a.R.cs, v, a.R.conj);
+            X[e] = ld_c(inb, a.in.esz, (int64_t)i * a.in.rs + (int64_t)j * a.in.cs, a.in.conj);
+        }
+        __syncthreads();
+        hh_factor(X, m, n, n, beta, tau, red, wpart);
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
+            const int i = (int)(e / k), c = (int)(e % k);
+            Y[e] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        hh_apply(Y, m, k, k, X, n, k, tau, wpart);
+        char *qb = reinterpret_cast<char *>(a.Q.p) + (int64_t)bt * a.Q.bs * a.Q.esz;
+        for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += QR_NT) {
+            const int i = (int)(e / k), c = (int)(e % k);
+            st_c(qb, a.Q.esz, (int64_t)i * a.Q.rs + (int64_t)c * a.Q.cs, Y[e], a.Q.conj);
+        }
+        if (a.want_r) {
+            char *rb = reinterpret_cast<char *>(a.R.p) + (int64_t)bt * a.R.bs * a.R.esz;
+            for (int64_t e = threadIdx.x; e < (int64_t)k * n; e += QR_NT) {
+                const int i = (int)(e / n), j = (int)(e % n);
+                double2 v = make_double2(0.0, 0.0);
+                if (j == i) v = beta[i];
+                else if (j > i) v = X[(int64_t)i * n + j];
+                st_c(rb, a.R.esz, (int64_t)i * a.R.rs + (int64_t)j * a.R.cs, v, a.R.conj);
+            }
         }
     }
 }
@@ -792,6 +799,39 @@ hipError_t launch_strided_copy(const void *in, int ie, int64_t ibs, int64_t irs,
     return hipGetLastError();
 }
 
+// workgroups (and workspace slots) of the fallback: at most 512, and at most
+// 16 MiB of workspace (at least one slot)
+static int qr_fallback_slots(int m, int n, int batch) {
+    size_t w, y, t, b;
+    const size_t per = global_qr_bytes(m, n, &w, &y, &t, &b);
+    const size_t cap = (size_t)16 << 20;
+    const int by_cap = (int)std::max<size_t>(1, cap / std::max<size_t>(per, 1));
+    return std::max(1, std::min(std::min(batch, 512), by_cap));
+}
+
+size_t qr_fallback_workspace_bytes(int m, int n, int batch) {
+    if (m <= 0 || n <= 0 || batch <= 0) return 0;
+    size_t w, y, t, b;
+    return global_qr_bytes(m, n, &w, &y, &t, &b) * (size_t)qr_fallback_slots(m, n, batch);
+}
+
+hipError_t launch_qr_fallback(const QrArgs &q, const int *flags, void *workspace, hipStream_t s) {
+    const int m = q.m, n = q.n;
+    if (m <= 0 || n <= 0 || q.batch <= 0) return hipSuccess;
+    if (!flags || !workspace) return hipErrorInvalidValue;
+    GlobalQrArgs g;
+    const size_t per = global_qr_bytes(m, n, &g.w_off, &g.y_off, &g.t_off, &g.b_off);
+    g.in = MatDesc{q.A, q.a_esz, q.a_bs, q.a_rs, q.a_cs, q.a_conj};
+    g.m = m; g.n = n; g.ws = reinterpret_cast<char *>(workspace); g.ws_bs = (int64_t)per;
+    g.Q = MatOut{q.Q, q.q_esz, q.q_bs, q.q_rs, q.q_cs, q.q_conj};
+    g.R = MatOut{q.R, q.r_esz, q.r_bs, q.r_rs, q.r_cs, q.r_conj};
+    g.want_r = q.R != nullptr;
+    g.batch = q.batch;
+    g.only_if = flags;
+    hipLaunchKernelGGL(k_qr_global, dim3(qr_fallback_slots(m, n, q.batch)), dim3(QR_NT), 0, s, g);
+    return hipGetLastError();
+}
+
 size_t qr_workspace_bytes(int m, int n, int batch) {
     if (m <= 0 || n <= 0) return 0;
     std::vector<TsqrLevel> lv;
@@ -813,6 +853,8 @@ hipError_t launch_qr(const QrArgs &q, void *workspace, hipStream_t s) {
         const size_t per = global_qr_bytes(m, n, &g.w_off, &g.y_off, &g.t_off, &g.b_off);
         g.in = in; g.m = m; g.n = n; g.ws = ws; g.ws_bs = (int64_t)per;
         g.Q = qo; g.R = ro; g.want_r = q.R != nullptr;
+        g.batch = q.batch;
+        g.only_if = nullptr;
         hipLaunchKernelGGL(k_qr_global, dim3(q.batch), dim3(QR_NT), 0, s, g);
         return hipGetLastError();
     }

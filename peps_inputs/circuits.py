@@ -31,7 +31,7 @@ import numpy as np
 
 from . import Lattice, site_dims
 
-__all__ = ["heisenberg_gate", "edge_groups", "heisenberg_circuit", "domain_wall_peps", "Gate"]
+__all__ = ["heisenberg_gate", "edge_groups", "heisenberg_circuit", "domain_wall_peps", "domain_wall_ones", "Gate"]
 
 Gate = Tuple[int, int, int, int, int]
 
@@ -102,3 +102,10 @@ def domain_wall_peps(lat: Lattice) -> List[List[np.ndarray]]:
             row.append(t)
         out.append(row)
     return out
+
+
+def domain_wall_ones(lat: Lattice) -> int:
+    """Qubits in |1> in the domain-wall state: the total magnetisation every
+    Heisenberg layer conserves (each gate commutes with sum_i Z_i)."""
+    return int(sum(1 for r in range(lat.rows) for c in range(lat.cols)
+                   if lat.phys[r, c] == 2 and c >= lat.cols // 2))

@@ -270,6 +270,34 @@ def test_orthonormalise(handle, m, n, batch, esz, cond):
         assert np.abs(proj - A[b]).max() < tol * 10 * np.abs(A[b]).max()
 
 
+@pytest.mark.parametrize("m,n", [(200, 50), (4096, 64), (300, 130)])
+def test_orthonormalise_zero_columns(handle, m, n):
+    """Orthonormalisation of rank-deficient A with exact zero columns, tiny
+    ones and singular values spread down to 1e-27 (the fit's matrices when its
+    bond exceeds the rank of the state it compresses, e.g. simple-update states
+    with zero-padded bonds): the CholeskyQR passes clamp a pivot and the item
+    is refactored by Householder, so Q has orthonormal columns whose span
+    holds A's."""
+    import torch
+    rng = np.random.default_rng(m + 7 * n)
+    A = _rand(rng, (4, m, 5)) @ _rand(rng, (4, 5, n))  # rank 5
+    A[0, :, 7:19] = 0
+    A[1, :, ::3] = 0
+    A[2, :, 2] = 1e-200 * _rand(rng, (m,))
+    U, _ = np.linalg.qr(_rand(rng, (m, n)))
+    V, _ = np.linalg.qr(_rand(rng, (n, n)))
+    A[3] = (U * (0.15 * 10.0 ** -np.linspace(0, 27, n))) @ V  # numerical rank ~ 20
+    dA = torch.from_numpy(A).cuda()
+    dQ = torch.zeros((4, m, n), dtype=torch.complex128, device="cuda")
+    handle.test_qr(dA, dQ, None, "cholesky")
+    torch.cuda.synchronize()
+    Q = dQ.cpu().numpy()
+    assert np.all(np.isfinite(Q))
+    for b in range(4):
+        assert np.abs(Q[b].conj().T @ Q[b] - np.eye(n)).max() < 1e-12 * np.sqrt(m)
+        assert np.abs(A[b] - Q[b] @ (Q[b].conj().T @ A[b])).max() < 1e-12 * np.abs(A[b]).max()
+
+
 @pytest.mark.parametrize("m,n,batch", [(4096, 64, 1), (512, 64, 16), (700, 33, 2), (37, 5, 3), (4097, 64, 1)])
 @pytest.mark.parametrize("esz", [16, 8])
 def test_orthonormalise_lq_layout(handle, m, n, batch, esz):
