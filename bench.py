@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--quench-R", default="",
                     help="with --quench-sample: comma-separated boundary dimensions R, each sampled in turn from "
                          "the same evolved state (default: --chi, else 8)")
+    ap.add_argument("--quench-Rref", type=int, default=0,
+                    help="with --quench-sample: boundary dimension of the reference norm Z in the KLD "
+                         "(default: the largest R)")
     ap.add_argument("--quench-sample", default="", choices=["", "hhx", "rotsq"],
                     help="the paper's end-to-end experiment: the Heisenberg quench by simple update (--su-D, "
                          "1 + --su-layers layers), then the norm and --samples samples from the evolved state at "
@@ -521,7 +524,7 @@ def quench_sample_bench(a):
     Rs = [int(x) for x in a.quench_R.split(",")] if a.quench_R else [R]
     # references: Z from the boundary contraction at the largest R, p(x) certified by the separate
     # amplitude contraction at bond 2D (the paper's check)
-    R_ref = max(Rs)
+    R_ref = a.quench_Rref or max(Rs)
     t0 = time.perf_counter()
     lz_ref, _ = h.boundary_contract(P, tnb.make_opts(chi=R_ref, chi_x=R_ref))
     t_ref = time.perf_counter() - t0

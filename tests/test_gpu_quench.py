@@ -58,3 +58,32 @@ def test_quench_samples_keep_magnetisation(handle, name, lat_fn, layers):
     assert abs(st["kld"]) < 1e-9
     # the samples are not all alike: the quench spread the domain wall
     assert len({tuple(b) for b in bits.cpu().numpy().tolist()}) > 8
+
+
+def test_truncated_quench_norm_and_sampler_exact(handle):
+    """A quench that truncates (gate errors up to ~1e-2 on the 4x4 square at
+    D = 3): the state is no longer an exact Trotter state, but its norm and
+    amplitudes are what they are -- the boundary contraction at the exact bond
+    gives the statevector's norm, and the sampler's q(x) = p(x) / Z with p from
+    the statevector."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    from oracle.statevector import statevector
+    lat = square_lattice(4, 4, 3)
+    gates, G = heisenberg_circuit(lat, 3, 0.3)
+    P = tnb.Peps.from_numpy(lat, domain_wall_peps(lat))
+    _, eps, f = handle.simple_update(P, gates, G, in_place=True)
+    assert eps.max() > 1e-6  # truncation happened
+    T = [[P.tensors[r * lat.cols + c].cpu().numpy() for c in range(lat.cols)] for r in range(lat.rows)]
+    psi = statevector(T, lat.site_index)
+    Z = float(np.sum(np.abs(psi) ** 2))
+    o = tnb.make_opts(chi=128, chi_x=128)
+    lz, _ = handle.boundary_contract(P, o)
+    bits, lq, lp = handle.sample(P, o, 256, seed=5)[:3]
+    b = bits.cpu().numpy()
+    exact = np.array([2 * np.log(abs(psi[tuple(x)])) for x in b])
+    print(f"max eps {eps.max():.2e}, f {f:.6f}; log Z {lz:.12f} vs {np.log(Z):.12f}; "
+          f"max |log p - exact| {np.abs(lp.cpu().numpy() - exact).max():.2e}")
+    assert abs(lz - np.log(Z)) < 1e-10
+    assert np.abs(lp.cpu().numpy() - exact).max() < 1e-9
+    assert (lq + lz - lp).abs().max().item() < 1e-9
