@@ -674,6 +674,15 @@ void amplitude(Engine &E, const PepsDev &P, const SampleOpts &o, uint64_t first,
         Zw = (int)std::max(1.0, std::min(4096.0, std::floor(budget / std::max(per, 1.0))));
     }
     Zw = (int)std::min<int64_t>(Zw, n);
+    // the check contracts at a bond (typically 2 chi) well above the ranks of
+    // the state's own bonds, where the fit's matrices are rank deficient:
+    // Householder throughout instead of CholeskyQR with its per-item fallback
+    struct HouseholderScope {
+        Engine &E;
+        bool saved;
+        explicit HouseholderScope(Engine &e) : E(e), saved(e.householder_only) { E.householder_only = true; }
+        ~HouseholderScope() { E.householder_only = saved; }
+    } hh(E);
     uint64_t *sidx = reinterpret_cast<uint64_t *>(E.raw((size_t)Zw * 8));
     double *mlog = reinterpret_cast<double *>(E.raw((size_t)Zw * 8));
     int *xsel = reinterpret_cast<int *>(E.raw((size_t)Zw * 4 * cols));
