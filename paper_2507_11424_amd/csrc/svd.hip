@@ -23,7 +23,8 @@
 namespace tnk {
 namespace {
 
-constexpr int SVD_NT = 256;
+constexpr int SVD_NT = 256;       // threads per matrix held in LDS
+constexpr int SVD_NT_GLOBAL = 1024;  // threads per matrix held in global memory (more lanes per column pair)
 constexpr int SVD_LDS_N = 64;     // largest n kept in LDS
 constexpr int SVD_MAX_SWEEPS = 40;
 constexpr double SVD_TOL = 1e-15;  // |gamma| <= tol sqrt(alpha beta) counts as orthogonal
@@ -33,7 +34,7 @@ constexpr double SVD_RANK_RTOL = 1e-12;  // sigma <= rtol sigma_max counts as ze
 // below the rank cut (sigma_max >= ||R||_F / sqrt(n) >= ||R||_F / 16), and rotating such
 // residue against the large columns only drives it towards underflow.
 constexpr double SVD_NEGL = 1e-28;
-static_assert(SVD_NMAX <= SVD_NT, "the rank sort gives one thread per column");
+static_assert(SVD_NMAX <= SVD_NT && SVD_NMAX <= SVD_NT_GLOBAL, "the rank sort gives one thread per column");
 
 __device__ inline double2 cm(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
@@ -58,8 +59,8 @@ __device__ inline void store(void *base, int esz, int64_t off, double2 v) {
     else reinterpret_cast<float2 *>(base)[off] = make_float2((float)v.x, (float)v.y);
 }
 
-template <bool IN_LDS>
-__global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
+template <bool IN_LDS, int NT>
+__global__ void __launch_bounds__(NT) k_svd_trunc(SvdArgs a) {
     extern __shared__ double2 lds[];
     __shared__ double sig[SVD_NMAX];
     __shared__ double wsort[SVD_NMAX];
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
     __shared__ int rk[SVD_NMAX];
     __shared__ int rotated;
     __shared__ int kkeep;
-    __shared__ double fro2p[SVD_NT / 64];
+    __shared__ double fro2p[NT / 64];
     const int n = a.n, tid = threadIdx.x;
     double2 *W, *V;  // column-major: column j at [j * n]
     if constexpr (IN_LDS) {
@@ -80,14 +81,14 @@ __global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
     const int N = n + (n & 1);  // tournament players; index n is a bye when n is odd
     const int P = N / 2;
     int tpp = 64;
-    while (tpp > 1 && tpp * P > SVD_NT) tpp >>= 1;
+    while (tpp > 1 && tpp * P > NT) tpp >>= 1;
     const int pair = tid / tpp, lane = tid % tpp;
-    const int NG = SVD_NT / tpp;  // lane groups
+    const int NG = NT / tpp;  // lane groups
 
     for (int b = blockIdx.x; b < a.batch; b += gridDim.x) {
         const double2 *Rb = a.R + (int64_t)b * n * n;
         double f2 = 0;
-        for (int e = tid; e < n * n; e += SVD_NT) {
+        for (int e = tid; e < n * n; e += NT) {
             const int i = e / n, j = e % n;
             const double2 x = Rb[e];
             f2 += x.x * x.x + x.y * x.y;
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
         if ((tid & 63) == 0) fro2p[tid >> 6] = f2;
         __syncthreads();
         double fro2 = 0;
-        for (int w = 0; w < SVD_NT / 64; ++w) fro2 += fro2p[w];
+        for (int w = 0; w < NT / 64; ++w) fro2 += fro2p[w];
         const double negl = SVD_NEGL * fro2;
         for (int sweep = 0; sweep < SVD_MAX_SWEEPS; ++sweep) {
             if (tid == 0) rotated = 0;
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(SVD_NT) k_svd_trunc(SvdArgs a) {
         __syncthreads();
         const int k = kkeep;
         // U[b](i, rk_j) = w_j(i) / sigma_j; SV[b](rk_j, l) = sigma_j conj(v_j(l)); zero past k
-        for (int e = tid; e < n * n; e += SVD_NT) {
+        for (int e = tid; e < n * n; e += NT) {
             const int j = e / n, i = e % n;
             const int col = rk[j];
             const double sj = sig[j];
@@ -241,15 +242,16 @@ hipError_t launch_svd_trunc(const double *R, int n, int batch, double cutoff, in
         static bool attr = false;
         const size_t lds = (size_t)2 * SVD_LDS_N * SVD_LDS_N * sizeof(double2);
         if (!attr) {
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_svd_trunc<true>),
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_svd_trunc<true, SVD_NT>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             attr = true;
         }
-        hipLaunchKernelGGL(k_svd_trunc<true>, dim3(grid), dim3(SVD_NT), (size_t)2 * n * n * sizeof(double2), s, a);
+        hipLaunchKernelGGL((k_svd_trunc<true, SVD_NT>), dim3(grid), dim3(SVD_NT), (size_t)2 * n * n * sizeof(double2), s,
+                           a);
     } else {
         if (!workspace) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_svd_trunc<false>, dim3(grid), dim3(SVD_NT), 0, s, a);
+        hipLaunchKernelGGL((k_svd_trunc<false, SVD_NT_GLOBAL>), dim3(grid), dim3(SVD_NT_GLOBAL), 0, s, a);
     }
     return hipGetLastError();
 }
