@@ -186,6 +186,43 @@ def marginal_errors(env, ref, lz):
     return out
 
 
+def sample_quality(h, P, o, lat, bits):
+    """Total-variation distance between the step's samples and the contracted
+    marginals (after the timed steps, untimed): per qubit |f(0) - P(0)|, per
+    neighbouring pair 1/2 sum_st |f(s,t) - P(s,t)| against the two-site
+    diagonals of tn_environments, with the bound that shot noise alone stays
+    under with probability 1 - 1e-3 over all tested marginals (k outcomes, n
+    samples: 1/2 sqrt((k-1)/n) + sqrt(ln(m/delta)/(2n)), m marginals)."""
+    import math
+    import numpy as np
+    env = h.environments(P, o, want_zz=False, want_p2=True)
+    b = bits.cpu().numpy().astype(np.int64)
+    n = b.shape[0]
+    idx = lat.site_index
+    rho = env["rho1"].cpu().numpy().reshape(lat.rows, lat.cols, 2, 2)
+    one = []
+    for r in range(lat.rows):
+        for c in range(lat.cols):
+            if idx[r, c] >= 0:
+                one.append(abs(np.mean(b[:, idx[r, c]] == 0) - rho[r, c, 0, 0].real))
+    two = []
+    for key, dr, dc in (("p2_h", 0, 1), ("p2_v", 1, 0)):
+        p2 = env[key].cpu().numpy()
+        for r in range(p2.shape[0]):
+            for c in range(p2.shape[1]):
+                q1, q2 = idx[r, c], idx[r + dr, c + dc]
+                if q1 < 0 or q2 < 0 or not np.all(np.isfinite(p2[r, c])):
+                    continue
+                f = np.bincount(2 * b[:, q1] + b[:, q2], minlength=4) / n
+                two.append(0.5 * np.abs(f - p2[r, c]).sum())
+    m = len(one) + len(two)
+    bound = lambda k: 0.5 * math.sqrt((k - 1) / n) + math.sqrt(math.log(m / 1e-3) / (2 * n))  # noqa: E731
+    return {"samples": n, "qubits": len(one), "pairs": len(two),
+            "max_1site_tvd": float(max(one)), "mean_1site_tvd": float(np.mean(one)), "bound_1site": bound(2),
+            "max_2site_tvd": float(max(two)) if two else None, "mean_2site_tvd": float(np.mean(two)) if two else None,
+            "bound_2site": bound(4)}
+
+
 def host_info():
     """CPU model, usable cores and the BLAS thread pool the oracle's NumPy runs on."""
     import numpy as np
@@ -772,6 +809,8 @@ def main():
                                             "launch from the host so that each is timed)"}
     oref = oracle_reference(a.config, chi) if cutoff == 0 else {}
     out["vs_oracle"] = marginal_errors(last.get("env"), oref, lz)
+    if a.samples >= 1000 and not a.no_env:
+        out["sample_quality"] = sample_quality(h, P, o, lat, last["res"][0])
     modes = [m for m in a.compare.split(",") if m and m != "none" and m != a.prec]
     if a.prec == "fp64" and modes:
         ref_res = tuple(x.clone() for x in last["res"][:3])

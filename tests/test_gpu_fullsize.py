@@ -123,8 +123,10 @@ def test_c2_environments_match_oracle(prec, tol, chi):
 
 def test_c2_sample_histograms_within_shot_noise():
     """2048 samples at chi = chi_x = 32: every qubit's frequency of 0 against
-    the environments' P(0), within the total-variation bound
-    tau = 1/2 sqrt((k-1)/n) + sqrt(ln(1/delta) / (2n)), k = 2, delta = 1e-3 / 64."""
+    the oracle's P(0), and every neighbouring pair's four frequencies against
+    the two-site diagonals of the environments, within the total-variation
+    bound tau = 1/2 sqrt((k-1)/n) + sqrt(ln(m/delta) / (2n)) (k = 2 or 4
+    outcomes, m = 176 marginals, delta = 1e-3)."""
     import math
     import paper_2507_11424_amd as tnb
     lat, T, cfg = make_config("c2")
@@ -132,12 +134,17 @@ def test_c2_sample_histograms_within_shot_noise():
     h = tnb.Handle(0)
     try:
         P = tnb.Peps.from_numpy(lat, T)
-        bits, lq, _ = h.sample(P, tnb.make_opts(chi=32, chi_x=32), n, seed=2024)
-        bits = bits.cpu().numpy()
+        o = tnb.make_opts(chi=32, chi_x=32)
+        bits, lq, _ = h.sample(P, o, n, seed=2024)
+        bits = bits.cpu().numpy().astype(np.int64)
+        env = h.environments(P, o, want_zz=False, want_p2=True)
+        p2 = {"h": env["p2_h"].cpu().numpy(), "v": env["p2_v"].cpu().numpy()}
     finally:
         h.close()
     rho, _, _ = _c2_ref(32)
-    tau = 0.5 * math.sqrt(1.0 / n) + math.sqrt(math.log(64 / 1e-3) / (2 * n))
+    m = 64 + 112
+    tau = 0.5 * math.sqrt(1.0 / n) + math.sqrt(math.log(m / 1e-3) / (2 * n))
+    tau2 = 0.5 * math.sqrt(3.0 / n) + math.sqrt(math.log(m / 1e-3) / (2 * n))
     worst = 0.0
     for r in range(lat.rows):
         for c in range(lat.cols):
@@ -145,8 +152,16 @@ def test_c2_sample_histograms_within_shot_noise():
             p0 = rho[r, c, 0, 0].real
             f0 = np.mean(bits[:, q] == 0)
             worst = max(worst, abs(f0 - p0))
-    print(f"largest |freq - P(0)| = {worst:.4f}, bound {tau:.4f}")
+    worst2 = 0.0
+    for key, dr, dc in (("h", 0, 1), ("v", 1, 0)):
+        for r in range(p2[key].shape[0]):
+            for c in range(p2[key].shape[1]):
+                q1, q2 = lat.site_index[r, c], lat.site_index[r + dr, c + dc]
+                f = np.bincount(2 * bits[:, q1] + bits[:, q2], minlength=4) / n
+                worst2 = max(worst2, 0.5 * np.abs(f - p2[key][r, c]).sum())
+    print(f"largest |freq - P(0)| = {worst:.4f}, bound {tau:.4f}; largest pair TVD {worst2:.4f}, bound {tau2:.4f}")
     assert worst < tau
+    assert worst2 < tau2
 
 
 def test_c4_full_lattice_small_bond():
