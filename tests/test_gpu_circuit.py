@@ -147,3 +147,8 @@ def test_simple_update_rejects_bad_gates(handle):
         handle.simple_update(P, [(0, 0, 0, 0, 1), (0, 0, 0, 1, 0)], np.eye(4))
     # the same pair in consecutive groups is fine
     handle.simple_update(P, [(0, 0, 0, 0, 1), (1, 0, 0, 1, 0)], np.eye(4))
+    # bonds above 64 (pair matrices above 256) are refused before any work
+    big = square_lattice(1, 2, 65)
+    Pb = tnb.Peps.from_numpy(big, random_peps(big, "haar", 0.5, 75))
+    with pytest.raises(tnb.TnError, match="UNSUPPORTED"):
+        handle.simple_update(Pb, [(0, 0, 0, 0, 1)], np.eye(4))
