@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--quench-Rref", type=int, default=0,
                     help="with --quench-sample: boundary dimension of the reference norm Z in the KLD "
                          "(default: the largest R)")
+    ap.add_argument("--quench-bp", default="", choices=["", "hhx", "rotsq"],
+                    help="the paper's loop-correlation experiment: after each Trotter layer of the quench (simple "
+                         "update at --su-D <= 16, 1 + --su-layers layers) the loop BP error of every primitive loop "
+                         "(tn_bp); one JSON line of its own")
     ap.add_argument("--quench-sample", default="", choices=["", "hhx", "rotsq"],
                     help="the paper's end-to-end experiment: the Heisenberg quench by simple update (--su-D, "
                          "1 + --su-layers layers), then the norm and --samples samples from the evolved state at "
@@ -525,6 +529,52 @@ def simple_update_bench(a):
     h.close()
 
 
+def quench_bp_bench(a):
+    """Loop correlations of the evolving quench state (the paper's loop BP
+    error per Trotter layer, Eqs. avBPError and loopBPerror): after every layer
+    of the simple update, BP on the norm network and the error of every
+    primitive loop; the mean, the largest and the BP solve's time per layer."""
+    import numpy as np
+    import torch
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import heavy_hex_lattice, rotated_square_lattice
+    from peps_inputs.circuits import heisenberg_circuit, domain_wall_peps
+    D = a.su_D
+    lat = heavy_hex_lattice(7, 15, D) if a.quench_bp == "hhx" else rotated_square_lattice(D)
+    gates1, G = heisenberg_circuit(lat, 1, a.su_dt)
+    ngroups = len({g[0] for g in gates1})
+    layers = a.su_layers + 1
+    h = tnb.Handle(0, torch.cuda.current_stream(0))
+    P = tnb.Peps.from_numpy(lat, domain_wall_peps(lat), dtype="c128", device="cuda:0")
+    msgs = h.message_buffer(P)
+    rows, eps_all = [], []
+    t_su = t_bp = 0.0
+    for l in range(layers):
+        gl = [(l * ngroups + g[0],) + tuple(g[1:]) for g in gates1]
+        t0 = time.perf_counter()
+        _, eps, _ = h.simple_update(P, gl, G, in_place=True, messages_in=msgs if l > 0 else None, messages_out=msgs)
+        torch.cuda.synchronize()
+        t_su += time.perf_counter() - t0
+        eps_all.extend(eps.tolist())
+        t0 = time.perf_counter()
+        b = h.bp(P, loops=True)
+        t_bp += time.perf_counter() - t0
+        el = b["eps_loops"]
+        rows.append({"layer": l + 1, "eps_mean": b["eps"], "eps_max": float(np.max(el)), "loops": int(el.size),
+                     "bp_sweeps": b["sweeps"], "fidelity_estimate": float(np.prod([1 - e for e in eps_all]))})
+        print(f"layer {l + 1}: loop BP error mean {b['eps']:.3e} max {np.max(el):.3e} over {el.size} loops "
+              f"({b['sweeps']} sweeps)", file=sys.stderr, flush=True)
+    out = {"metric": "loop BP error per Trotter layer (evolved Heisenberg quench state)",
+           "value": layers / (t_su + t_bp), "unit": "layers/s (simple update + BP with loop errors)",
+           "n_gpus": 1, "steps": layers, "warmup": 0, "ms_per_step": 1e3 * (t_su + t_bp) / layers,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{lat.name}: {lat.n_qubits} qubits, Heisenberg quench dt={a.su_dt} J=1 from the "
+                                  f"domain wall, {layers} layers by simple update at D={D}, loop BP error after each"},
+           "simple_update_s": t_su, "bp_s": t_bp, "layers": rows}
+    print(json.dumps(out))
+    h.close()
+
+
 def quench_sample_bench(a):
     """Evolve the domain wall by simple update, then contract and sample the
     evolved state with boundary MPSs of dimension R (the paper's heavy-hex and
@@ -628,6 +678,9 @@ def main():
         return
     if a.quench_sample:
         quench_sample_bench(a)
+        return
+    if a.quench_bp:
+        quench_bp_bench(a)
         return
     import numpy as np
     import torch
