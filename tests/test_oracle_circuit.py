@@ -93,6 +93,25 @@ def test_exact_regime_is_the_evolved_statevector(lat, layers):
     assert np.count_nonzero(p > 1e-6) > 2
 
 
+@pytest.mark.parametrize("lat,layers", [(square_lattice(2, 3, 8), 1), (heavy_hex_lattice(3, 5, 8), 1)])
+def test_quench_conserves_the_magnetisation(lat, layers):
+    """Every Heisenberg gate commutes with sum_i Z_i: the exactly evolved
+    domain wall has weight only on bitstrings with the domain wall's number of
+    1s (domain_wall_ones), the property the GPU quench-then-sample test and
+    bench check on the samples."""
+    from peps_inputs.circuits import domain_wall_ones
+    T0 = domain_wall_peps(lat)
+    gates, G = heisenberg_circuit(lat, layers, 0.3)
+    T, eps, _ = simple_update(T0, gates, G)
+    assert max(eps) < 1e-24
+    psi = statevector(T, lat.site_index)
+    ones = np.indices(psi.shape).sum(axis=0)
+    want = domain_wall_ones(lat)
+    w = np.abs(psi) ** 2
+    assert np.sum(w[ones != want]) < 1e-24 * np.sum(w)
+    assert np.count_nonzero(w[ones == want] > 1e-8 * w.max()) > 2
+
+
 def _comb(rows, cols, D):
     phys = np.full((rows, cols), 2, np.int32)
     dh = np.full((rows, cols - 1), D, np.int32)
