@@ -61,3 +61,28 @@ def test_binding_fails_loudly_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         tnb.Handle(0)
+
+
+def _declared_arity():
+    """Parameter count of every function the header declares (top-level commas
+    of its parameter list; comments stripped)."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(tn_[a-z_]+)\s*\(([^;{]*?)\)\s*;", txt):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argtypes_match_the_header():
+    """The ctypes binding declares every call with the header's parameter
+    count, so a changed signature cannot go unnoticed."""
+    import paper_2507_11424_amd as tnb
+    if not os.path.exists(tnb.LIB_PATH):
+        pytest.skip("library not built")
+    L = tnb.lib()
+    arity = _declared_arity()
+    assert set(arity) == set(_declared())
+    for name, n in arity.items():
+        at = getattr(L, name).argtypes
+        assert at is not None and len(at) == n, (name, n, at)
