@@ -288,8 +288,9 @@ tn_status tn_boundary_contract(tn_handle *h, const tn_peps *p, const tn_opts *o,
         } else {
             PepsDev P = stage(*h->E, p);
             LView V = make_view(P, o->direction);
-            BoundarySet S = boundary_set(*h->E, V, fit_opts(o), (o->direction == 1 || o->direction == 3) ? 1 : 0);
+            BoundarySet S;
             try {
+                S = boundary_set(*h->E, V, fit_opts(o), (o->direction == 1 || o->direction == 3) ? 1 : 0);
                 norm_close(*h->E, V, S, logabs, arg);
             } catch (...) {
                 free_set(*h->E, S);

@@ -87,3 +87,42 @@ def test_truncated_quench_norm_and_sampler_exact(handle):
     assert abs(lz - np.log(Z)) < 1e-10
     assert np.abs(lp.cpu().numpy() - exact).max() < 1e-9
     assert (lq + lz - lp).abs().max().item() < 1e-9
+
+
+def test_padded_bonds_exact(handle):
+    """A state whose bonds are zero-padded beyond their rank (as simple update
+    leaves them) gives the unpadded state's norm, amplitudes and samples: its
+    fits meet exactly dependent columns, where CholeskyQR flags the items and
+    Householder refactors them on the device."""
+    import torch
+    import paper_2507_11424_amd as tnb
+    from peps_inputs import random_peps
+    lat3, lat5 = square_lattice(4, 3, 3), square_lattice(4, 3, 5)
+    small = random_peps(lat3, "haar", 0.5, seed=5)
+    padded = []
+    for row in small:
+        prow = []
+        for t in row:
+            shape = (t.shape[0],) + tuple(5 if d == 3 else d for d in t.shape[1:])
+            z = np.zeros(shape, dtype=t.dtype)
+            z[tuple(slice(0, d) for d in t.shape)] = t
+            prow.append(z)
+        padded.append(prow)
+    # every boundary of a 3-column lattice at D = 3 has rank <= 9: exact at chi 16,
+    # where the factorised matrices are at most 16 wide (no blocked scheme)
+    o = tnb.make_opts(chi=16, chi_x=16)
+    res = {}
+    for name, lat, T in (("plain", lat3, small), ("padded", lat5, padded)):
+        P = tnb.Peps.from_numpy(lat, T)
+        lz, arg = handle.boundary_contract(P, o)
+        bits, lq, lp = handle.sample(P, o, 256, seed=9)[:3]
+        res[name] = (lz, arg, bits.cpu().numpy(), lp.cpu().numpy())
+        print(f"{name}: log|Z| {lz:.15f} arg {arg:.3e}")
+    from oracle.statevector import statevector
+    psi = statevector(small, lat3.site_index)
+    exact = np.array([2 * np.log(abs(psi[tuple(x)])) for x in res["plain"][2]])
+    assert abs(res["plain"][0] - np.log(np.sum(np.abs(psi) ** 2))) < 1e-10
+    assert abs(res["plain"][0] - res["padded"][0]) < 1e-10
+    assert np.array_equal(res["plain"][2], res["padded"][2])
+    assert np.abs(res["plain"][3] - exact).max() < 1e-9
+    assert np.abs(res["padded"][3] - exact).max() < 1e-9
