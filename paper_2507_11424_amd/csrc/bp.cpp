@@ -98,16 +98,21 @@ Ten with_messages(Engine &E, const SiteClass &c, const Ten &msg, const Ten &t, s
                   const std::vector<int> &legs, int Dm) {
     Ten r = t;
     bool own = false;
-    for (int leg : legs) {
-        std::string nxt;
-        for (char ch : cur)
-            if (ch != KET[leg]) nxt += ch;
-        nxt += BRA[leg];
-        Ten x = E.contract_new(r.p ? op(r, cur) : class_op(c, cur, false), msg_op(msg, c, leg, Dm), nxt);
+    try {
+        for (int leg : legs) {
+            std::string nxt;
+            for (char ch : cur)
+                if (ch != KET[leg]) nxt += ch;
+            nxt += BRA[leg];
+            Ten x = E.contract_new(r.p ? op(r, cur) : class_op(c, cur, false), msg_op(msg, c, leg, Dm), nxt);
+            if (own) E.drop(r);
+            r = x;
+            own = true;
+            cur = nxt;
+        }
+    } catch (...) {
         if (own) E.drop(r);
-        r = x;
-        own = true;
-        cur = nxt;
+        throw;
     }
     return r;
 }
@@ -124,12 +129,22 @@ void all_outgoing(Engine &E, const SiteClass &c, const Ten &msg, int Dm, OutOp o
         std::string base = "zsabcd";
         Ten X = with_messages(E, c, msg, Ten{}, base, {pr[0], pr[1]}, Dm);
         const int o0 = pr[0] == 2 ? 0 : 2;
-        for (int q = 0; q < 2; ++q) {
-            const int keep = o0 + q, other = o0 + 1 - q;
-            std::string cur = base;
-            Ten Y = with_messages(E, c, msg, X, cur, {other}, Dm);
-            E.contract(op(Y, cur), class_op(c, "zsefgh", true), out_op(keep, c));
-            E.drop(Y);
+        try {
+            for (int q = 0; q < 2; ++q) {
+                const int keep = o0 + q, other = o0 + 1 - q;
+                std::string cur = base;
+                Ten Y = with_messages(E, c, msg, X, cur, {other}, Dm);
+                try {
+                    E.contract(op(Y, cur), class_op(c, "zsefgh", true), out_op(keep, c));
+                } catch (...) {
+                    E.drop(Y);
+                    throw;
+                }
+                E.drop(Y);
+            }
+        } catch (...) {
+            E.drop(X);
+            throw;
         }
         E.drop(X);
     }

@@ -76,18 +76,23 @@ Ten gauge_batch(Engine &E, const Ten &A, const Ten R[5], int bond, std::string &
     Ten cur;
     bool have = false;
     int count = 0;
-    for (int k = 1; k <= 4; ++k) {
-        if (k == bond) continue;
-        ++count;
-        const std::string in = "z" + letters(done);
-        done[k] = true;
-        std::string out = "z" + letters(done);
-        if (count == 3) out = "z" + ext + std::string{SLOT[0], SLOT[bond]};
-        const Op src = have ? op(cur, in) : op(A, in);
-        Ten nxt = E.contract_new(src, op(R[k], std::string{'z', SLOT[k], GAUGED[k]}), out);
+    try {
+        for (int k = 1; k <= 4; ++k) {
+            if (k == bond) continue;
+            ++count;
+            const std::string in = "z" + letters(done);
+            done[k] = true;
+            std::string out = "z" + letters(done);
+            if (count == 3) out = "z" + ext + std::string{SLOT[0], SLOT[bond]};
+            const Op src = have ? op(cur, in) : op(A, in);
+            Ten nxt = E.contract_new(src, op(R[k], std::string{'z', SLOT[k], GAUGED[k]}), out);
+            if (have) E.drop(cur);
+            cur = nxt;
+            have = true;
+        }
+    } catch (...) {
         if (have) E.drop(cur);
-        cur = nxt;
-        have = true;
+        throw;
     }
     return cur;
 }
@@ -99,22 +104,27 @@ void ungauge_batch(Engine &E, const Ten &T, const std::string &in, const Ten R[5
     bool have = false;
     std::string cin = "z" + in;
     int count = 0;
-    for (int k = 1; k <= 4; ++k) {
-        if (k == bond) continue;
-        ++count;
-        std::string o = cin;
-        o[o.find(GAUGED[k])] = SLOT[k];
-        const Op src = have ? op(cur, cin) : op(T, cin);
-        const Op Rk = op(R[k], std::string{'z', GAUGED[k], SLOT[k]});
-        if (count == 3) {
-            E.contract(src, Rk, op(out, "zsuldr"));
-        } else {
-            Ten nxt = E.contract_new(src, Rk, o);
-            if (have) E.drop(cur);
-            cur = nxt;
-            have = true;
+    try {
+        for (int k = 1; k <= 4; ++k) {
+            if (k == bond) continue;
+            ++count;
+            std::string o = cin;
+            o[o.find(GAUGED[k])] = SLOT[k];
+            const Op src = have ? op(cur, cin) : op(T, cin);
+            const Op Rk = op(R[k], std::string{'z', GAUGED[k], SLOT[k]});
+            if (count == 3) {
+                E.contract(src, Rk, op(out, "zsuldr"));
+            } else {
+                Ten nxt = E.contract_new(src, Rk, o);
+                if (have) E.drop(cur);
+                cur = nxt;
+                have = true;
+            }
+            cin = o;
         }
-        cin = o;
+    } catch (...) {
+        if (have) E.drop(cur);
+        throw;
     }
     if (have) E.drop(cur);
 }
